@@ -1,0 +1,206 @@
+"""Benchmark of the tiled composite SpMV hot path on one MI355X.
+
+Workload (default): a Chung-Lu power-law graph with 2^23 nodes and 2^27
+distinct edges (in/out-degree exponent 2.1, degrees capped at 2^20, node ids
+randomly permuted), PageRank matrix M = W^T with values fl32(1/outdeg).
+
+One step = the whole hot path on that input, which is resident in HBM before
+the timed region starts:
+    build_tiled(M)      column lengths, column sort, tile count, bucketing,
+                        per-tile row sort, workload sizes, pack
+    pagerank(100 it.)   100 tiled SpMVs with the fused PageRank update
+    destroy
+value = 100 x (8 nnz + 4 (n_rows + n_cols)) bytes per step / step time, in
+GB/s (whole step, build included).  The roofline object reports the tile
+SpMV kernel alone, from HIP events around every launch in the timed region.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpMV GB/s & % HBM peak; batched RWR queries/s vs plain SpMV loop"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    import graphgen as gg
+    t0 = time.time()
+    if name == "cl23":
+        g = gg.chung_lu(23, 1 << 27, gamma=2.1, cap=float(1 << 20), seed=23)
+        desc = {"workload": "pagerank-chung-lu-2^23", "nodes": g.n, "edges": g.m, "gamma": 2.1,
+                "degree_cap": 1 << 20, "ids_permuted": True, "pagerank_iters": 100, "seed": 23}
+    elif name == "rmat20":
+        g = gg.rmat(20, 16, seed=20)
+        desc = {"workload": "pagerank-rmat-20", "nodes": g.n, "edges": g.m, "edge_factor": 16,
+                "abcd": [0.57, 0.19, 0.19, 0.05], "pagerank_iters": 100, "seed": 20}
+    elif name == "rmat14":
+        g = gg.rmat(14, 16, seed=14)
+        desc = {"workload": "pagerank-rmat-14", "nodes": g.n, "edges": g.m, "edge_factor": 16,
+                "abcd": [0.57, 0.19, 0.19, 0.05], "pagerank_iters": 100, "seed": 14}
+    else:
+        raise SystemExit("unknown workload " + name)
+    csr = gg.pagerank_matrix(g)
+    log("workload %s: n=%d nnz=%d generated in %.1fs" % (name, g.n, csr[3].size, time.time() - t0))
+    return csr, desc
+
+
+def cpu_baseline(csr, budget_s: float):
+    """The oracle's FP64 PageRank on the host cores, on a bounded number of iterations."""
+    import oracle
+    n, _, rp, col, val = csr
+    nbytes = 8 * col.size + 4 * (n + n)
+    t0 = time.time()
+    oracle.pagerank(csr, 0.85, 0.0, 1)
+    one = time.time() - t0
+    iters = max(1, min(100, int(budget_s / max(one, 1e-3))))
+    t0 = time.time()
+    oracle.pagerank(csr, 0.85, 0.0, iters)
+    dt = time.time() - t0
+    return {"value": round(iters * nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d FP64 PageRank iterations of the same matrix (one CSR SpMV + update each), "
+                      "%.1f s; same byte formula" % (iters, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--workload", default="cl23")
+    ap.add_argument("--tile-width", type=int, default=0)
+    ap.add_argument("--split-len", type=int, default=-1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-launch kernel timing")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1103_2405_amd import DeviceCsr, TiledMatrix, csr_spmv, load_library
+
+    load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    csr, desc = make_workload(args.workload)
+    n = csr[0]
+    nnz = csr[3].size
+    spmv_bytes = 8 * nnz + 4 * (csr[0] + csr[1])
+    A = DeviceCsr(csr, device=dev)
+    p_out = torch.empty(n, dtype=torch.float32, device=dev)
+    perf_table = "default"
+
+    def step(timing: bool):
+        tm = TiledMatrix(A, tile_width=args.tile_width, split_len=args.split_len, perf_table=perf_table)
+        if timing:
+            tm.set_timing(True)
+        tm.pagerank(0.85, 0.0, args.iters, out=p_out)
+        tinfo = tm.get_timing() if timing else None
+        info = tm.info()
+        tm.close()
+        return info, tinfo
+
+    # warmup
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+
+    # timed steps
+    timing = not args.no_timing
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(step(timing))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = args.iters * spmv_bytes / (ms_per_step / 1e3) / 1e9
+    info = infos[-1][0]
+
+    roofline = None
+    if timing:
+        tot_ms = sum(t["tile_kernel_ms"] for _, t in infos)
+        launches = sum(t["tile_launches"] for _, t in infos)
+        calls = sum(t["spmv_calls"] for _, t in infos)
+        per_launch_bytes = spmv_bytes * calls / max(launches, 1)
+        avg_ms = tot_ms / max(launches, 1)
+        achieved = per_launch_bytes / (avg_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_tile_spmv", "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "launches_per_spmv": round(launches / max(calls, 1), 2),
+                    "bytes_per_launch": int(per_launch_bytes)}
+
+    # separate measurements (not part of value): PageRank alone and the plain CSR baseline
+    tm = TiledMatrix(A, tile_width=args.tile_width, split_len=args.split_len, perf_table=perf_table)
+    tm.pagerank(0.85, 0.0, 5, out=p_out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm.pagerank(0.85, 0.0, args.iters, out=p_out)
+    torch.cuda.synchronize()
+    pr_ms = (time.perf_counter() - t1) * 1e3
+    x = torch.rand(n, device=dev)
+    y = torch.empty(n, device=dev)
+    csr_spmv(A, x, y)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        csr_spmv(A, x, y)
+    torch.cuda.synchronize()
+    csr_ms = (time.perf_counter() - t1) * 1e3 / 20
+    tm.close()
+
+    if args.probe_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(csr, args.cpu_budget)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": dict(desc, step="build_tiled + %d PageRank iterations + destroy" % args.iters,
+                       tile_width=info["tile_width"], n_tiles=info["n_tiles"],
+                       n_workloads=info["n_workloads"], nnz_pad=info["nnz_pad"]),
+        "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "accumulate": "f64",
+        "build_ms": round(info["build_us"] / 1e3, 3),
+        "pagerank_ms": round(pr_ms, 3),
+        "pagerank_spmv_gbps": round(args.iters * spmv_bytes / (pr_ms / 1e3) / 1e9, 1),
+        "csr_baseline_spmv_gbps": round(spmv_bytes / (csr_ms / 1e3) / 1e9, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

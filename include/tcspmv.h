@@ -1,0 +1,227 @@
+/*
+ * tcspmv.h -- tiled composite sparse matrix-vector products for power-law
+ * graph matrices on AMD Instinct MI355X (gfx950), and the PageRank, HITS and
+ * Random Walk with Restart power iterations built on them.
+ *
+ * Method: Yang, Parthasarathy, Sadayappan, "Fast Sparse Matrix-Vector
+ * Multiplication on GPUs: Implications for Graph Mining" (arXiv 1103.2405).
+ *   - columns reordered by decreasing length and the long ones cut into column
+ *     tiles so each tile reads one segment of x (Section 3.1, Solutions 1-2);
+ *   - inside each tile, rows sorted by length and packed into balanced
+ *     workloads, row-major when at least as wide as tall, else column-major,
+ *     padded to the wavefront width (Solution 3); the remaining short columns
+ *     form one more such tile;
+ *   - the number of tiles and each tile's workload size chosen by Algorithms
+ *     1-3 and the performance model of Eq. 1-5 (Section 3.3, Appendix E).
+ *
+ * Conventions for every call below:
+ *   - Matrices are given in CSR with 64-bit row offsets, 32-bit column ids and
+ *     FP32 values; vectors are FP32.  Pointers named d_* or documented as
+ *     "device" are device memory owned by the caller; they must stay valid
+ *     until the work queued on `stream` has finished.
+ *   - Every call is asynchronous on `stream` (a hipStream_t) unless it says it
+ *     synchronises.  Calls on one handle must not overlap on different streams.
+ *   - Errors: every call returns a tc_status; on anything but TC_OK,
+ *     tc_last_error() gives a message (per thread).  No call aborts the process.
+ *   - Index space: tc_spmv / tc_spmm take x and return y in the caller's own
+ *     row and column ids; the *_internal variants and the drivers' inner loops
+ *     work in the handle's relabelled ids (columns sorted by length; for a
+ *     square matrix rows carry the same relabelling).
+ */
+#ifndef TCSPMV_H
+#define TCSPMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* identical to hipStream_t */
+typedef struct ihipStream_t* tc_stream_t;
+
+typedef enum {
+  TC_OK = 0,
+  TC_EINVAL = 1,        /* invalid argument or invalid CSR */
+  TC_ENOMEM = 2,        /* a device allocation failed */
+  TC_EHIP = 3,          /* a HIP runtime call failed */
+  TC_ENOTCONV = 4,      /* a driver did not reach its tolerance in max_iter */
+  TC_EUNSUPPORTED = 5   /* valid but not supported (e.g. nnz >= 2^31) */
+} tc_status;
+
+typedef struct tc_handle tc_handle;
+
+/* A sparse matrix in CSR form, all arrays in device memory, read only.
+ *   row_ptr: n_rows + 1 offsets, row_ptr[0] = 0, non-decreasing, row_ptr[n_rows] = nnz
+ *   col_idx: nnz column ids in [0, n_cols)
+ *   val:     nnz values (finite: a stored 0 times inf would not be 0) */
+typedef struct {
+  int64_t n_rows, n_cols, nnz;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const float* val;
+} tc_csr;
+
+/* Build options (tc_build_opts_default fills the defaults). */
+typedef struct {
+  int32_t tile_width;         /* W, columns per dense tile (Solution 1); 0 = library default */
+  int32_t n_tiles;            /* -1: Algorithm 1 decides; >= 0: that many dense tiles (clipped) */
+  int32_t wl_policy;          /* 0: Algorithm 2 per tile; 1: wl_per_tile; 2: wl_all for every tile */
+  int32_t wl_all;             /* workload size for wl_policy 2 */
+  const int32_t* wl_per_tile; /* host array, one size per tile (dense tiles, then the sparse
+                                 tile), at least as long as the number of tiles built */
+  int32_t n_wl_per_tile;      /* length of wl_per_tile */
+  int32_t wave;               /* padding multiple S of workloads; 0 = 64 (the wavefront width) */
+  int32_t split_len;          /* rows longer than this many entries in a tile are split
+                                 across wavefronts in chunks of this size; 0 = never
+                                 (the paper's rule); -1 = default 8192 */
+  int32_t camping_pad;        /* 1: 64 pad elements after workloads whose size is a multiple
+                                 of 512 (Solution 3, partition camping); default 0 */
+  int32_t relabel;            /* -1: relabel rows like columns when square; 0: keep row ids */
+  int32_t max_act_warp;       /* resident wavefronts assumed by the model (Eq. 1); 0 = 8192 */
+  const char* perf_table;     /* path of a throughput table for the model; NULL = built-in */
+  /* optional device allocator for the handle's buffers; NULL = hipMalloc / hipFree */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* alloc_ctx;
+} tc_build_opts;
+
+/* Sizes and parameters of a built handle (host struct filled by tc_handle_info). */
+typedef struct {
+  int64_t n_rows, n_cols, nnz;
+  int32_t tile_width, wave, split_len, relabel;
+  int32_t n_dense_tiles;      /* T of Algorithm 1 */
+  int32_t n_tiles;            /* T plus one if a sparse tile exists */
+  int64_t n_workloads;
+  int64_t nnz_pad;            /* stored elements, pads included */
+  int64_t n_rowid;            /* stored row ids */
+  int64_t n_rows_sorted;      /* sum over tiles of the tile's non-empty rows */
+  int64_t n_split_rows;       /* heavy rows split across wavefronts */
+  int64_t n_partials;         /* chunks of split rows */
+  int64_t n_dangling;         /* empty columns; internal ids n_cols - n_dangling .. n_cols-1 */
+  int64_t device_bytes;       /* device memory held by the handle */
+  double build_us;            /* wall time of tc_build_tiled */
+} tc_info;
+
+/* Host copies of the whole format, for checking it entry by entry.  The caller
+ * allocates every array (sizes from tc_info; a NULL pointer skips that array). */
+typedef struct {
+  int32_t* cperm;             /* [n_cols]  internal column -> original column */
+  int32_t* rowmap;            /* [n_rows]  original row -> internal row */
+  int64_t* tile_col_begin;    /* [n_tiles] first internal column of each tile */
+  int64_t* tile_col_end;      /* [n_tiles] one past the last */
+  int64_t* tile_nnz;          /* [n_tiles] */
+  int64_t* tile_wl;           /* [n_tiles] workload size used */
+  int64_t* tile_row_off;      /* [n_tiles + 1] offsets into rows_sorted */
+  int32_t* rows_sorted;       /* [n_rows_sorted] each tile's rows by decreasing length */
+  int32_t* rows_len;          /* [n_rows_sorted] the row's entries in that tile */
+  int32_t* wl_tile;           /* [n_workloads] ... one entry per workload ... */
+  int32_t* wl_layout;         /* 0 row-major, 1 column-major (a split chunk is row-major) */
+  int32_t* wl_w;              /* width of the first row (chunk: the chunk's length) */
+  int32_t* wl_w_pad;          /* stored row length (RM) or w (CM) */
+  int32_t* wl_h_pad;          /* stored rows: h (RM), padded rows (CM), 1 (chunk) */
+  int32_t* wl_row_begin;      /* index of the first row in rows_sorted */
+  int32_t* wl_n_rows;         /* real rows */
+  int32_t* wl_chunk;          /* chunk index of a split row, -1 otherwise */
+  int32_t* wl_n_chunks;       /* chunks of that split row in this tile, 0 otherwise */
+  int64_t* wl_data_off;       /* first element in idx / val */
+  int64_t* wl_rowid_off;      /* first entry in rowid */
+  int32_t* idx;               /* [nnz_pad] internal column id; pads: the tile's first column */
+  float* val;                 /* [nnz_pad] value; pads: +0.0 */
+  int32_t* rowid;             /* [n_rowid] internal row id; pad rows: -1 */
+} tc_format_view;
+
+/* Accumulated time of the tile kernels when timing is enabled (tc_set_timing). */
+typedef struct {
+  double tile_kernel_ms;      /* sum of per-launch durations (HIP events) */
+  int64_t tile_launches;
+  int64_t spmv_calls;         /* products run (each = one pass over all tiles) */
+} tc_timing;
+
+void tc_build_opts_default(tc_build_opts* opts);
+
+/* Build the tiled composite format of `A` on the GPU (Section 3.1 Solutions
+ * 1-3; Section 3.3 and Algorithms 1-3 for the tile count and workload sizes).
+ * Steps: column lengths, columns sorted by decreasing length (ties by id),
+ * tile count, entries bucketed by tile, each tile's rows sorted by decreasing
+ * length (ties by internal row id), workloads chosen and packed.  The handle
+ * owns all its device memory; A may be freed once this call returns.
+ * Synchronises `stream`.  Errors: TC_EINVAL for a NULL argument, negative
+ * sizes, a non-monotone row_ptr, row_ptr[n_rows] != nnz, a column id out of
+ * range or an unusable option; TC_EUNSUPPORTED for nnz >= 2^31 or sizes that
+ * do not fit 32-bit ids; TC_ENOMEM; TC_EHIP. */
+tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, tc_stream_t stream,
+                         tc_handle** out);
+
+/* y := A x (overwrite) in the caller's index space (Appendix B: y = A x for an
+ * n x m sparse A).  d_x: n_cols floats, d_y: n_rows floats, device, must not
+ * alias.  Tiles are applied in order, dense tiles first, then the sparse tile;
+ * each row's sum is formed in FP64 and added to y in FP32 once per tile. */
+tc_status tc_spmv(const tc_handle* h, const float* d_x, float* d_y, tc_stream_t stream);
+
+/* y := A x with x and y in the handle's internal ids (no permutation). */
+tc_status tc_spmv_internal(const tc_handle* h, const float* d_x, float* d_y, tc_stream_t stream);
+
+/* Y := A X for k right-hand sides: X is n_cols x k and Y n_rows x k, both
+ * row-major, device, caller's index space; 1 <= k <= 256. */
+tc_status tc_spmm(const tc_handle* h, const float* d_X, float* d_Y, int32_t k, tc_stream_t stream);
+
+/* PageRank (Appendix F, Eq. 6): M must be the handle of the column-stochastic
+ * matrix W^T (M[v][u] = 1/outdeg(u)); empty columns are dangling nodes whose
+ * mass is spread uniformly.  p^(0) = 1/n;
+ *   p' = c (M p + (d/n) 1) + ((1-c)/n) 1,  d = sum of p over dangling nodes.
+ * Stops when the L1 change is <= tol, checked every check_every iterations
+ * (that check synchronises); tol <= 0 runs exactly max_iter iterations with no
+ * synchronisation until the end.  d_p_out: n floats (device, caller's ids).
+ * *iters: iterations run; *resid: L1 change of the last iteration (FP64
+ * reduction).  TC_ENOTCONV if tol > 0 was not reached (p_out still written). */
+tc_status tc_pagerank(const tc_handle* M, float c, float tol, int32_t max_iter, int32_t check_every,
+                      float* d_p_out, int32_t* iters, double* resid, tc_stream_t stream);
+
+/* HITS (Appendix F, Eq. 7-8): B must be the handle of the 2n x 2n matrix
+ * [[0, A^T], [A, 0]].  x^(0) = 1/n everywhere; each iteration x' = B x, then
+ * the authority half (ids < n) and the hub half (ids >= n) are each divided by
+ * their own sum.  d_auth, d_hub: n floats each (device).  Convergence as in
+ * tc_pagerank on the L1 change of the 2n vector.  TC_EINVAL if a half sums to
+ * zero (a graph without edges). */
+tc_status tc_hits(const tc_handle* B, float tol, int32_t max_iter, int32_t check_every, float* d_auth,
+                  float* d_hub, int32_t* iters, double* resid, tc_stream_t stream);
+
+/* Random walk with restart (Appendix F, Eq. 9) for k query nodes at once:
+ * r' = c W r + (1-c) e_s, r^(0) = e_s, W the handle of the column-normalised
+ * adjacency (of the symmetrised graph for the paper's undirected setting).
+ * seeds: host array of k node ids (caller's ids).  d_R: n x k row-major
+ * (device).  Stops when every column's L1 change is <= tol (check as above);
+ * *resid is the largest column change of the last iteration. */
+tc_status tc_rwr(const tc_handle* W, const int32_t* seeds, int32_t k, float c, float tol,
+                 int32_t max_iter, int32_t check_every, float* d_R, int32_t* iters, double* resid,
+                 tc_stream_t stream);
+
+/* Plain CSR SpMV (one thread per row, Appendix B's CSR kernel), the baseline
+ * the tiled kernels are compared with: y := A x, caller's ids, no handle. */
+tc_status tc_csr_spmv(const tc_csr* A, const float* d_x, float* d_y, tc_stream_t stream);
+
+/* Sizes and parameters of a handle (host, no GPU work). */
+tc_status tc_handle_info(const tc_handle* h, tc_info* info);
+
+/* Copy the format to host arrays (synchronous). */
+tc_status tc_export_format(const tc_handle* h, tc_format_view* view);
+
+/* Time every tile-kernel launch with HIP events (enable = 1) or stop (0);
+ * enabling also clears the totals. */
+tc_status tc_set_timing(tc_handle* h, int32_t enable);
+/* Read the totals (synchronises the handle's pending events). */
+tc_status tc_get_timing(tc_handle* h, tc_timing* t);
+
+/* Release the handle and all its device memory (waits for the device). */
+void tc_destroy(tc_handle* h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* tc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCSPMV_H */

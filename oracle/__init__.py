@@ -24,10 +24,10 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so: g++-free plain C, -O3 -march=native, OpenMP, no fast-math."""
+    """Compile liboracle.so: plain C, -O3 (portable x86-64), OpenMP, no fast-math."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O3", "-march=native", "-fno-fast-math", "-fopenmp",
+        subprocess.check_call(["gcc", "-O3", "-fno-fast-math", "-fopenmp",
                                "-ffp-contract=off", "-shared", "-fPIC", "-std=c11",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)

@@ -1,0 +1,881 @@
+// Format builder on the GPU (Section 3.1 Solutions 1-3, Section 3.3,
+// Algorithms 1-3).  Steps, in order:
+//   a1  column lengths (entries per column)
+//   a2  columns sorted by decreasing length, ties by increasing id (stable
+//       LSD counting sort); square matrices relabel rows the same way
+//   a3  number of dense tiles (Algorithm 1, on the host from W-strided
+//       samples of the sorted lengths)
+//   a4  entries bucketed by tile, keeping the input order inside each tile
+//   a5  each tile's rows sorted by decreasing length, ties by internal row id
+//   a6  workload size per tile (Algorithm 2 with the model of Algorithm 3) and
+//       the greedy partition into workloads (host, from length histograms)
+//   a7  pack: padded row-major / column-major rectangles, row ids, descriptors
+// Every sort is a chain of stable counting-sort passes, so the format is a
+// pure function of the input and the options.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+#include "tc_prims.h"
+
+namespace tc {
+const char* get_error();
+
+namespace {
+
+constexpr int kB = 256;
+
+inline unsigned nblk(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+int bits_for(uint64_t v) {
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+struct Fail {
+  tc_status st;
+  std::string msg;
+};
+
+#define HIPX(call)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      throw Fail{TC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+// Temporary device buffers of one build, freed when the build ends.
+struct Tmp {
+  std::vector<void*> bufs;
+  template <class T>
+  T* get(int64_t n) {
+    void* p = nullptr;
+    size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{TC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+    bufs.push_back(p);
+    return (T*)p;
+  }
+  void release(void* p) {
+    for (auto& b : bufs)
+      if (b == p) {
+        (void)hipFree(b);
+        b = nullptr;
+      }
+  }
+  ~Tmp() {
+    for (void* p : bufs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+template <class T>
+T* hold(tc_handle* h, int64_t n) {
+  size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+  void* p = nullptr;
+  if (h->alloc) {
+    p = h->alloc(bytes, h->alloc_ctx);
+    if (!p) throw Fail{TC_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{TC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  }
+  h->owned.push_back(p);
+  return (T*)p;
+}
+
+// ----------------------------------------------------------------- kernels
+__global__ void k_validate_rows(const int64_t* __restrict__ rp, int64_t n_rows, int64_t nnz, int* flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n_rows) return;
+  int64_t a = rp[i];
+  bool bad = (i == 0 && a != 0) || (i == n_rows && a != nnz) || (i < n_rows && rp[i + 1] < a);
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void k_validate_cols(const int32_t* __restrict__ col, int64_t nnz, int64_t n_cols, int* flag) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz && (col[k] < 0 || (int64_t)col[k] >= n_cols)) atomicOr(flag, 2);
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_iota(int32_t* a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (int32_t)i;
+}
+
+// a1: column lengths (one atomic per entry).
+__global__ void k_col_count(const int32_t* __restrict__ col, int64_t nnz, int32_t* __restrict__ clen) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) atomicAdd(&clen[col[k]], 1);
+}
+
+__global__ void k_max_i32(const int32_t* __restrict__ a, int64_t n, int32_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t v = i < n ? a[i] : 0;
+  for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
+  if (lane_id() == 0) atomicMax(out, v);
+}
+
+__global__ void k_count_eq(const int32_t* __restrict__ a, int64_t n, int32_t v, unsigned long long* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool e = i < n && a[i] == v;
+  uint64_t m = __ballot(e);
+  if (lane_id() == 0 && m) atomicAdd(out, (unsigned long long)__popcll(m));
+}
+
+__global__ void k_desc_keys(const int32_t* __restrict__ len, int64_t n, int32_t maxv, uint32_t* __restrict__ keys,
+                            int32_t* __restrict__ vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    keys[i] = (uint32_t)(maxv - len[i]);
+    vals[i] = (int32_t)i;
+  }
+}
+
+__global__ void k_cols_finish(const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals, int64_t n,
+                              int32_t maxv, int32_t* __restrict__ cperm, int32_t* __restrict__ cpos,
+                              int32_t* __restrict__ clen_sorted) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    int32_t j = vals[k];
+    cperm[k] = j;
+    cpos[j] = (int32_t)k;
+    clen_sorted[k] = maxv - (int32_t)keys[k];
+  }
+}
+
+__global__ void k_rowmap(const int32_t* __restrict__ cpos, int64_t n_rows, int relabel, int32_t* __restrict__ rowmap,
+                         int32_t* __restrict__ rowinv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_rows) {
+    int32_t r = relabel ? cpos[i] : (int32_t)i;
+    rowmap[i] = r;
+    rowinv[r] = (int32_t)i;
+  }
+}
+
+__global__ void k_strided(const int32_t* __restrict__ a, int64_t stride, int64_t cnt, int32_t* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < cnt) out[t] = a[t * stride];
+}
+
+// Row id of every entry: lanes write their own short rows, the whole
+// wavefront writes each long row.
+__global__ void k_expand_rows(const int64_t* __restrict__ rp, int64_t n_rows, int32_t* __restrict__ row_of) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = lane_id();
+  int64_t a = 0, b = 0;
+  if (i < n_rows) {
+    a = rp[i];
+    b = rp[i + 1];
+  }
+  const bool longrow = (b - a) > kWave;
+  if (!longrow)
+    for (int64_t k = a; k < b; ++k) row_of[k] = (int32_t)i;
+  uint64_t m = __ballot(longrow);
+  while (m) {
+    const int src = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int64_t aa = __shfl(a, src, kWave), bb = __shfl(b, src, kWave);
+    const int32_t r = (int32_t)__shfl((int64_t)i, src, kWave);
+    for (int64_t k = aa + lane; k < bb; k += kWave) row_of[k] = r;
+  }
+}
+
+__global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __restrict__ at, int64_t n,
+                             int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = src[at[i]];
+}
+
+__global__ void k_icol(const int32_t* __restrict__ col, const int32_t* __restrict__ cpos, int64_t nnz,
+                       int32_t* __restrict__ icol) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) icol[k] = cpos[col[k]];
+}
+
+__device__ inline int32_t tile_of(int32_t icol, int32_t W, int32_t T) { return min(icol / W, T); }
+
+// first position of each tile in the bucketed entries (tile ids are sorted)
+__global__ void k_tile_bounds(const int32_t* __restrict__ b_icol, int64_t nnz, int32_t W, int32_t T, int32_t ntiles,
+                              int64_t* __restrict__ tstart) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  int64_t lo = 0, hi = nnz;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (tile_of(b_icol[mid], W, T) < t) lo = mid + 1; else hi = mid;
+  }
+  tstart[t] = lo;
+}
+
+// a5: segment heads = first entry of each (tile, row) pair
+__global__ void k_seg_flags(const int32_t* __restrict__ b_icol, const int32_t* __restrict__ b_row, int64_t nnz,
+                            int32_t W, int32_t T, int32_t* __restrict__ flags) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  int f = k == 0 || b_row[k] != b_row[k - 1] || tile_of(b_icol[k], W, T) != tile_of(b_icol[k - 1], W, T);
+  flags[k] = f;
+}
+
+__global__ void k_seg_emit(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos,
+                           const int32_t* __restrict__ b_icol, const int32_t* __restrict__ b_row,
+                           const int32_t* __restrict__ rowmap, int64_t nnz, int32_t W, int32_t T,
+                           int32_t* __restrict__ seg_start, int32_t* __restrict__ seg_row,
+                           int32_t* __restrict__ seg_tile) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz || !flags[k]) return;
+  int32_t s = pos[k];
+  seg_start[s] = (int32_t)k;
+  seg_row[s] = rowmap[b_row[k]];
+  seg_tile[s] = tile_of(b_icol[k], W, T);
+}
+
+__global__ void k_seg_len(const int32_t* __restrict__ seg_start, int64_t nseg, int64_t nnz, int32_t* __restrict__ seg_len) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nseg) seg_len[s] = (int32_t)((s + 1 < nseg ? (int64_t)seg_start[s + 1] : nnz) - seg_start[s]);
+}
+
+__global__ void k_seg_keys(const int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_len,
+                           const int32_t* __restrict__ seg_row, int64_t nseg, int32_t maxlen, int lb, int rb,
+                           uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  keys[s] = ((uint64_t)seg_tile[s] << (lb + rb)) | ((uint64_t)(maxlen - seg_len[s]) << rb) | (uint64_t)seg_row[s];
+  vals[s] = (int32_t)s;
+}
+
+__global__ void k_seg_gather(const int32_t* __restrict__ perm, const int32_t* __restrict__ seg_row,
+                             const int32_t* __restrict__ seg_len, const int32_t* __restrict__ seg_start, int64_t nseg,
+                             int32_t* __restrict__ rows_sorted, int32_t* __restrict__ rows_len,
+                             int32_t* __restrict__ srt_start) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nseg) return;
+  int32_t s = perm[i];
+  rows_sorted[i] = seg_row[s];
+  rows_len[i] = seg_len[s];
+  srt_start[i] = seg_start[s];
+}
+
+// start of each tile in the sorted segment keys (tile in the top bits)
+__global__ void k_key_bounds(const uint64_t* __restrict__ keys, int64_t nseg, int shift, int32_t ntiles,
+                             int64_t* __restrict__ off) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  int64_t lo = 0, hi = nseg;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)(keys[mid] >> shift) < t) lo = mid + 1; else hi = mid;
+  }
+  off[t] = lo;
+}
+
+// run heads of (tile, length) in the sorted segment keys
+__global__ void k_run_flags(const uint64_t* __restrict__ keys, int64_t nseg, int rb, int32_t* __restrict__ flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nseg) flags[i] = i == 0 || (keys[i] >> rb) != (keys[i - 1] >> rb);
+}
+
+__global__ void k_run_emit(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos,
+                           const int32_t* __restrict__ rows_len, int64_t nseg, int64_t* __restrict__ run_pos,
+                           int32_t* __restrict__ run_len) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nseg && flags[i]) {
+    run_pos[pos[i]] = i;
+    run_len[pos[i]] = rows_len[i];
+  }
+}
+
+struct PackWl {
+  int64_t data_off, rowid_off;
+  int32_t w_pad, h_pad, n_rows, layout;
+  int32_t row_begin, chunk, tile_first, extra;
+};
+
+// a7: one wavefront per workload writes its rectangle, its pads and row ids.
+__global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int64_t n_wl,
+                                             const int32_t* __restrict__ srt_start,
+                                             const int32_t* __restrict__ rows_len,
+                                             const int32_t* __restrict__ rows_sorted,
+                                             const int32_t* __restrict__ b_icol, const float* __restrict__ b_val,
+                                             int32_t split_len, int32_t* __restrict__ idx, float* __restrict__ val,
+                                             int32_t* __restrict__ rowid) {
+  const int lane = lane_id();
+  const int64_t j = (int64_t)blockIdx.x * (kB / kWave) + threadIdx.x / kWave;
+  if (j >= n_wl) return;
+  const PackWl d = wls[j];
+  const int64_t off = d.data_off;
+  if (d.chunk >= 0) {
+    const int32_t s = d.row_begin;
+    const int64_t c0 = (int64_t)d.chunk * split_len;
+    const int64_t st = (int64_t)srt_start[s] + c0;
+    const int64_t L = min((int64_t)split_len, (int64_t)rows_len[s] - c0);
+    for (int64_t c = lane; c < d.w_pad; c += kWave) {
+      const bool real = c < L;
+      idx[off + c] = real ? b_icol[st + c] : d.tile_first;
+      val[off + c] = real ? b_val[st + c] : 0.0f;
+    }
+    if (lane == 0) rowid[d.rowid_off] = rows_sorted[s];
+  } else if (d.layout == kRM) {
+    for (int32_t r = 0; r < d.n_rows; ++r) {
+      const int32_t s = d.row_begin + r;
+      const int64_t st = srt_start[s];
+      const int32_t L = rows_len[s];
+      const int64_t base = off + (int64_t)r * d.w_pad;
+      for (int64_t c = lane; c < d.w_pad; c += kWave) {
+        const bool real = c < L;
+        idx[base + c] = real ? b_icol[st + c] : d.tile_first;
+        val[base + c] = real ? b_val[st + c] : 0.0f;
+      }
+      if (lane == 0) rowid[d.rowid_off + r] = rows_sorted[s];
+    }
+  } else {
+    for (int32_t r = lane; r < d.h_pad; r += kWave) {
+      int64_t st = 0;
+      int32_t L = 0, row = -1;
+      if (r < d.n_rows) {
+        const int32_t s = d.row_begin + r;
+        st = srt_start[s];
+        L = rows_len[s];
+        row = rows_sorted[s];
+      }
+      rowid[d.rowid_off + r] = row;
+      for (int32_t c = 0; c < d.w_pad; ++c) {
+        const int64_t e = off + (int64_t)c * d.h_pad + r;
+        const bool real = c < L;
+        idx[e] = real ? b_icol[st + c] : d.tile_first;
+        val[e] = real ? b_val[st + c] : 0.0f;
+      }
+    }
+  }
+  const int64_t end = off + (int64_t)d.w_pad * d.h_pad;
+  for (int32_t c = lane; c < d.extra; c += kWave) {
+    idx[end + c] = d.tile_first;
+    val[end + c] = 0.0f;
+  }
+}
+
+// ------------------------------------------------------ counting-sort ops
+struct RadixU32Op {
+  const uint32_t* kin;
+  const int32_t* vin;
+  uint32_t* kout;
+  int32_t* vout;
+  int shift;
+  __device__ uint32_t bucket(int64_t k) const { return (kin[k] >> shift) & 255u; }
+  __device__ void move(int64_t k, int64_t p) const {
+    kout[p] = kin[k];
+    vout[p] = vin[k];
+  }
+};
+
+struct RadixU64Op {
+  const uint64_t* kin;
+  const int32_t* vin;
+  uint64_t* kout;
+  int32_t* vout;
+  int shift;
+  __device__ uint32_t bucket(int64_t k) const { return (uint32_t)(kin[k] >> shift) & 255u; }
+  __device__ void move(int64_t k, int64_t p) const {
+    kout[p] = kin[k];
+    vout[p] = vin[k];
+  }
+};
+
+struct TileOp {
+  const int32_t* icol_in;
+  const float* val_in;
+  const int32_t* row_in;
+  int32_t* icol_out;
+  float* val_out;
+  int32_t* row_out;
+  int32_t W, T;
+  int shift;
+  __device__ uint32_t bucket(int64_t k) const { return ((uint32_t)tile_of(icol_in[k], W, T) >> shift) & 255u; }
+  __device__ void move(int64_t k, int64_t p) const {
+    icol_out[p] = icol_in[k];
+    val_out[p] = val_in[k];
+    row_out[p] = row_in[k];
+  }
+};
+
+// ------------------------------------------------------------ host helpers
+template <typename In, typename Out>
+int64_t excl_scan(const In* in, int64_t n, Out* out, Tmp& tmp, hipStream_t st) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+  int64_t* bs = tmp.get<int64_t>(nb + 1);
+  if (n > 0) {
+    hipLaunchKernelGGL((k_scan_reduce<In>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, bs);
+    HIPX(hipGetLastError());
+  } else {
+    HIPX(hipMemsetAsync(bs, 0, sizeof(int64_t), st));
+  }
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, st, bs, nb, bs + nb);
+  HIPX(hipGetLastError());
+  if (n > 0) {
+    hipLaunchKernelGGL((k_scan_down<In, Out>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, bs, out);
+    HIPX(hipGetLastError());
+  }
+  int64_t total = 0;
+  HIPX(hipMemcpyAsync(&total, bs + nb, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPX(hipStreamSynchronize(st));
+  tmp.release(bs);
+  return total;
+}
+
+template <class Op>
+void cs_pass(const Op& op, int64_t n, int nbits, Tmp& tmp, hipStream_t st) {
+  if (n <= 0) return;
+  const int nbuckets = 1 << nbits;
+  const int64_t chunk = 4096;
+  const int64_t nchunks = (n + chunk - 1) / chunk;
+  const unsigned grid = (unsigned)((nchunks + kCsWaves - 1) / kCsWaves);
+  int32_t* hist = tmp.get<int32_t>((int64_t)nbuckets * nchunks);
+  int64_t* offs = tmp.get<int64_t>((int64_t)nbuckets * nchunks);
+  hipLaunchKernelGGL((k_cs_hist<Op>), dim3(grid), dim3(kCsBlock), kCsWaves * nbuckets * sizeof(int32_t), st, op, n,
+                     nbuckets, chunk, nchunks, hist);
+  HIPX(hipGetLastError());
+  excl_scan<int32_t, int64_t>(hist, (int64_t)nbuckets * nchunks, offs, tmp, st);
+  hipLaunchKernelGGL((k_cs_scatter<Op>), dim3(grid), dim3(kCsBlock), kCsWaves * nbuckets * sizeof(int64_t), st, op,
+                     n, nbuckets, nbits, chunk, nchunks, (const int64_t*)offs);
+  HIPX(hipGetLastError());
+  HIPX(hipStreamSynchronize(st));
+  tmp.release(hist);
+  tmp.release(offs);
+}
+
+int32_t dev_max(const int32_t* a, int64_t n, Tmp& tmp, hipStream_t st) {
+  int32_t* d = tmp.get<int32_t>(1);
+  HIPX(hipMemsetAsync(d, 0, sizeof(int32_t), st));
+  if (n > 0) hipLaunchKernelGGL(k_max_i32, dim3(nblk(n, kB)), dim3(kB), 0, st, a, n, d);
+  HIPX(hipGetLastError());
+  int32_t v = 0;
+  HIPX(hipMemcpyAsync(&v, d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPX(hipStreamSynchronize(st));
+  tmp.release(d);
+  return v;
+}
+
+int64_t ceil_to(int64_t v, int64_t s) { return (v + s - 1) / s * s; }
+
+void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h) {
+  const int64_t n_rows = A->n_rows, n_cols = A->n_cols, nnz = A->nnz;
+  Tmp tmp;
+
+  // ---- validation
+  {
+    int* flag = tmp.get<int>(1);
+    HIPX(hipMemsetAsync(flag, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_validate_rows, dim3(nblk(n_rows + 1, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, nnz, flag);
+    HIPX(hipGetLastError());
+    if (nnz > 0) hipLaunchKernelGGL(k_validate_cols, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, nnz, n_cols, flag);
+    HIPX(hipGetLastError());
+    int f = 0;
+    HIPX(hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    if (f & 1) throw Fail{TC_EINVAL, "invalid CSR: row_ptr must start at 0, not decrease and end at nnz"};
+    if (f & 2) throw Fail{TC_EINVAL, "invalid CSR: a column id is outside [0, n_cols)"};
+  }
+
+  // ---- a1: column lengths
+  int32_t* clen = hold<int32_t>(h, n_cols);
+  h->d_clen = clen;
+  if (n_cols > 0) {
+    HIPX(hipMemsetAsync(clen, 0, sizeof(int32_t) * n_cols, st));
+    if (nnz > 0) hipLaunchKernelGGL(k_col_count, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, nnz, clen);
+    HIPX(hipGetLastError());
+  }
+  const int32_t maxclen = dev_max(clen, n_cols, tmp, st);
+
+  // ---- a2: stable sort of columns by decreasing length
+  int32_t* cperm = hold<int32_t>(h, n_cols);
+  int32_t* cpos = hold<int32_t>(h, n_cols);
+  int32_t* clen_sorted = tmp.get<int32_t>(n_cols);
+  h->d_cperm = cperm;
+  h->d_cpos = cpos;
+  if (n_cols > 0) {
+    uint32_t* k0 = tmp.get<uint32_t>(n_cols);
+    uint32_t* k1 = tmp.get<uint32_t>(n_cols);
+    int32_t* v0 = tmp.get<int32_t>(n_cols);
+    int32_t* v1 = tmp.get<int32_t>(n_cols);
+    hipLaunchKernelGGL(k_desc_keys, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, clen, n_cols, maxclen, k0, v0);
+    HIPX(hipGetLastError());
+    const int kb = bits_for((uint64_t)maxclen);
+    for (int sh = 0; sh < kb; sh += 8) {
+      cs_pass(RadixU32Op{k0, v0, k1, v1, sh}, n_cols, 8, tmp, st);
+      std::swap(k0, k1);
+      std::swap(v0, v1);
+    }
+    hipLaunchKernelGGL(k_cols_finish, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, k0, v0, n_cols, maxclen, cperm, cpos,
+                       clen_sorted);
+    HIPX(hipGetLastError());
+    unsigned long long* cnt = tmp.get<unsigned long long>(1);
+    HIPX(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
+    hipLaunchKernelGGL(k_count_eq, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, clen_sorted, n_cols, 0, cnt);
+    HIPX(hipGetLastError());
+    unsigned long long nd = 0;
+    HIPX(hipMemcpyAsync(&nd, cnt, sizeof(nd), hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    h->n_dangling = (int64_t)nd;
+  }
+  int32_t* rowmap = hold<int32_t>(h, n_rows);
+  int32_t* rowinv = hold<int32_t>(h, n_rows);
+  h->d_rowmap = rowmap;
+  h->d_rowinv = rowinv;
+  if (n_rows > 0) {
+    hipLaunchKernelGGL(k_rowmap, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, cpos, n_rows, h->relabel ? 1 : 0, rowmap,
+                       rowinv);
+    HIPX(hipGetLastError());
+  }
+
+  // ---- a3: Algorithm 1
+  const int32_t W = h->W;
+  const int64_t NT = (n_cols + W - 1) / W;
+  int32_t T = 0;
+  if (o->n_tiles >= 0) {
+    T = (int32_t)std::min<int64_t>(o->n_tiles, NT);
+  } else if (NT > 0) {
+    int32_t* samp = tmp.get<int32_t>(NT);
+    hipLaunchKernelGGL(k_strided, dim3(nblk(NT, kB)), dim3(kB), 0, st, clen_sorted, (int64_t)W, NT, samp);
+    HIPX(hipGetLastError());
+    std::vector<int32_t> hs(NT);
+    HIPX(hipMemcpyAsync(hs.data(), samp, sizeof(int32_t) * NT, hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    while (T < NT && hs[T] >= 2) ++T;
+  }
+  const int32_t ntiles = (int32_t)(T + ((int64_t)T * W < n_cols ? 1 : 0));
+  h->T = T;
+  h->n_tiles = ntiles;
+  h->tile_col_begin.resize(ntiles);
+  h->tile_col_end.resize(ntiles);
+  for (int t = 0; t < ntiles; ++t) {
+    h->tile_col_begin[t] = (int64_t)t * W;
+    h->tile_col_end[t] = t < T ? std::min<int64_t>((int64_t)(t + 1) * W, n_cols) : n_cols;
+  }
+
+  // ---- a4: bucket entries by tile (stable)
+  int32_t *b_icol = nullptr, *b_row = nullptr;
+  float* b_val = nullptr;
+  std::vector<int64_t> tstart(ntiles + 1, 0);
+  if (nnz > 0) {
+    int32_t* row_of = tmp.get<int32_t>(nnz);
+    hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, row_of);
+    HIPX(hipGetLastError());
+    int32_t* icol = tmp.get<int32_t>(nnz);
+    hipLaunchKernelGGL(k_icol, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, cpos, nnz, icol);
+    HIPX(hipGetLastError());
+    const int tb = bits_for((uint64_t)(ntiles > 1 ? ntiles - 1 : 0));
+    if (tb == 0) {
+      b_icol = icol;
+      b_row = row_of;
+      b_val = tmp.get<float>(nnz);
+      HIPX(hipMemcpyAsync(b_val, A->val, sizeof(float) * nnz, hipMemcpyDeviceToDevice, st));
+    } else {
+      // LSD passes over 8-bit digits of the tile id; buffers alternate between
+      // two sets (the caller's values are only read)
+      int32_t* bi[2] = {tmp.get<int32_t>(nnz), icol};
+      int32_t* br[2] = {tmp.get<int32_t>(nnz), row_of};
+      float* bv[2] = {tmp.get<float>(nnz), nullptr};
+      const int32_t* ci = icol;
+      const int32_t* cr = row_of;
+      const float* cv = A->val;
+      int p = 0;
+      for (int sh = 0; sh < tb; sh += 8, ++p) {
+        const int s = p & 1;
+        if (!bv[s]) bv[s] = tmp.get<float>(nnz);
+        const int nb = std::min(8, tb - sh);
+        cs_pass(TileOp{ci, cv, cr, bi[s], bv[s], br[s], W, T, sh}, nnz, nb, tmp, st);
+        ci = bi[s];
+        cr = br[s];
+        cv = bv[s];
+      }
+      b_icol = (int32_t*)ci;
+      b_row = (int32_t*)cr;
+      b_val = (float*)cv;
+    }
+    int64_t* d_ts = tmp.get<int64_t>(ntiles + 1);
+    hipLaunchKernelGGL(k_tile_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, b_icol, nnz, W, T, ntiles, d_ts);
+    HIPX(hipGetLastError());
+    HIPX(hipMemcpyAsync(tstart.data(), d_ts, sizeof(int64_t) * (ntiles + 1), hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+  }
+  h->tile_nnz.resize(ntiles);
+  for (int t = 0; t < ntiles; ++t) h->tile_nnz[t] = tstart[t + 1] - tstart[t];
+
+  // ---- a5: segments (tile, row) and their sort by decreasing length
+  int64_t nseg = 0;
+  int32_t *rows_sorted = nullptr, *rows_len = nullptr, *srt_start = nullptr;
+  std::vector<int64_t> trow(ntiles + 1, 0);
+  std::vector<int64_t> run_pos;
+  std::vector<int32_t> run_len;
+  if (nnz > 0) {
+    int32_t* flags = tmp.get<int32_t>(nnz);
+    int32_t* pos = tmp.get<int32_t>(nnz);
+    hipLaunchKernelGGL(k_seg_flags, dim3(nblk(nnz, kB)), dim3(kB), 0, st, b_icol, b_row, nnz, W, T, flags);
+    HIPX(hipGetLastError());
+    nseg = excl_scan<int32_t, int32_t>(flags, nnz, pos, tmp, st);
+    int32_t* seg_start = tmp.get<int32_t>(nseg);
+    int32_t* seg_row = tmp.get<int32_t>(nseg);
+    int32_t* seg_tile = tmp.get<int32_t>(nseg);
+    int32_t* seg_len = tmp.get<int32_t>(nseg);
+    hipLaunchKernelGGL(k_seg_emit, dim3(nblk(nnz, kB)), dim3(kB), 0, st, flags, pos, b_icol, b_row, rowmap, nnz, W, T,
+                       seg_start, seg_row, seg_tile);
+    HIPX(hipGetLastError());
+    hipLaunchKernelGGL(k_seg_len, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_start, nseg, nnz, seg_len);
+    HIPX(hipGetLastError());
+    tmp.release(flags);
+    tmp.release(pos);
+    const int32_t maxlen = dev_max(seg_len, nseg, tmp, st);
+    const int lb = bits_for((uint64_t)maxlen);
+    const int rb = bits_for((uint64_t)(n_rows > 1 ? n_rows - 1 : 0));
+    const int tb = bits_for((uint64_t)(ntiles > 1 ? ntiles - 1 : 0));
+    if (lb + rb + tb > 64) throw Fail{TC_EUNSUPPORTED, "sort key of (tile, length, row) exceeds 64 bits"};
+    uint64_t* k0 = tmp.get<uint64_t>(nseg);
+    uint64_t* k1 = tmp.get<uint64_t>(nseg);
+    int32_t* v0 = tmp.get<int32_t>(nseg);
+    int32_t* v1 = tmp.get<int32_t>(nseg);
+    hipLaunchKernelGGL(k_seg_keys, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg, maxlen, lb,
+                       rb, k0, v0);
+    HIPX(hipGetLastError());
+    for (int sh = 0; sh < lb + rb + tb; sh += 8) {
+      cs_pass(RadixU64Op{k0, v0, k1, v1, sh}, nseg, 8, tmp, st);
+      std::swap(k0, k1);
+      std::swap(v0, v1);
+    }
+    rows_sorted = hold<int32_t>(h, nseg);
+    rows_len = hold<int32_t>(h, nseg);
+    srt_start = tmp.get<int32_t>(nseg);
+    hipLaunchKernelGGL(k_seg_gather, dim3(nblk(nseg, kB)), dim3(kB), 0, st, v0, seg_row, seg_len, seg_start, nseg,
+                       rows_sorted, rows_len, srt_start);
+    HIPX(hipGetLastError());
+    int64_t* d_off = tmp.get<int64_t>(ntiles + 1);
+    hipLaunchKernelGGL(k_key_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, k0, nseg, lb + rb, ntiles, d_off);
+    HIPX(hipGetLastError());
+    HIPX(hipMemcpyAsync(trow.data(), d_off, sizeof(int64_t) * (ntiles + 1), hipMemcpyDeviceToHost, st));
+    // length runs
+    int32_t* rflags = tmp.get<int32_t>(nseg);
+    int32_t* rpos = tmp.get<int32_t>(nseg);
+    hipLaunchKernelGGL(k_run_flags, dim3(nblk(nseg, kB)), dim3(kB), 0, st, k0, nseg, rb, rflags);
+    HIPX(hipGetLastError());
+    const int64_t nruns = excl_scan<int32_t, int32_t>(rflags, nseg, rpos, tmp, st);
+    int64_t* d_rp = tmp.get<int64_t>(nruns);
+    int32_t* d_rl = tmp.get<int32_t>(nruns);
+    hipLaunchKernelGGL(k_run_emit, dim3(nblk(nseg, kB)), dim3(kB), 0, st, rflags, rpos, rows_len, nseg, d_rp, d_rl);
+    HIPX(hipGetLastError());
+    run_pos.resize(nruns);
+    run_len.resize(nruns);
+    HIPX(hipMemcpyAsync(run_pos.data(), d_rp, sizeof(int64_t) * nruns, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(run_len.data(), d_rl, sizeof(int32_t) * nruns, hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+  }
+  h->d_rows_sorted = rows_sorted;
+  h->d_rows_len = rows_len;
+  h->n_rows_sorted = nseg;
+  h->tile_row_off = trow;
+
+  // ---- a6: workload sizes (Algorithm 2) and partition
+  PerfTable table;
+  if (o->perf_table) {
+    std::string err;
+    if (!load_perf_table(o->perf_table, &table, &err)) throw Fail{TC_EINVAL, err};
+  } else {
+    default_perf_table(&table);
+  }
+  PartitionParams pp{h->S, h->split_len, h->max_act_warp, h->camping_pad};
+  h->tile_wl.assign(ntiles, 0);
+  h->tile_wl_begin.assign(ntiles + 1, 0);
+  std::vector<HostWl>& wls = h->wls;
+  wls.clear();
+  size_t ri = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    std::vector<LenRun> runs;
+    while (ri < run_pos.size() && run_pos[ri] < trow[t + 1]) {
+      const int64_t end = ri + 1 < run_pos.size() ? std::min(run_pos[ri + 1], trow[t + 1]) : trow[t + 1];
+      runs.push_back(LenRun{run_len[ri], end - run_pos[ri]});
+      ++ri;
+    }
+    int64_t WLt;
+    if (o->wl_policy == 1) {
+      if (t >= o->n_wl_per_tile) throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
+      WLt = o->wl_per_tile[t];
+    } else if (o->wl_policy == 2) {
+      WLt = o->wl_all;
+    } else {
+      WLt = choose_wl(runs, h->tile_nnz[t], table, t >= T, pp);
+    }
+    if (WLt < 1) throw Fail{TC_EINVAL, "workload size must be >= 1"};
+    h->tile_wl[t] = WLt;
+    h->tile_wl_begin[t] = (int64_t)wls.size();
+    partition_tile(runs, WLt, t, trow[t], pp, &wls);
+  }
+  h->tile_wl_begin[ntiles] = (int64_t)wls.size();
+  const int64_t nwl = (int64_t)wls.size();
+  h->n_wl = nwl;
+
+  // split rows: slots grouped by row, in (tile, chunk) order
+  std::vector<int64_t> chunk_wl;
+  for (int64_t j = 0; j < nwl; ++j)
+    if (wls[j].chunk >= 0) chunk_wl.push_back(j);
+  std::vector<int32_t> chunk_row(chunk_wl.size());
+  if (!chunk_wl.empty()) {
+    // row ids of split rows (they sit at the start of their tile's sorted rows)
+    const int64_t nc = (int64_t)chunk_wl.size();
+    std::vector<int32_t> at(nc);
+    for (int64_t q = 0; q < nc; ++q) at[q] = wls[chunk_wl[q]].row_begin;
+    int32_t* d_at = tmp.get<int32_t>(nc);
+    int32_t* d_r = tmp.get<int32_t>(nc);
+    HIPX(hipMemcpyAsync(d_at, at.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gather_i32, dim3(nblk(nc, kB)), dim3(kB), 0, st, rows_sorted, d_at, nc, d_r);
+    HIPX(hipGetLastError());
+    HIPX(hipMemcpyAsync(chunk_row.data(), d_r, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+  }
+  std::vector<size_t> ord(chunk_wl.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return chunk_row[a] < chunk_row[b]; });
+  std::vector<int32_t> slot_of(chunk_wl.size());
+  std::vector<SplitRow> srows;
+  for (size_t q = 0; q < ord.size(); ++q) {
+    slot_of[ord[q]] = (int32_t)q;
+    if (q == 0 || chunk_row[ord[q]] != chunk_row[ord[q - 1]])
+      srows.push_back(SplitRow{chunk_row[ord[q]], (int32_t)q, 0, 0});
+    srows.back().n_slots++;
+  }
+  h->n_slots = (int64_t)chunk_wl.size();
+  h->n_split_rows = (int64_t)srows.size();
+
+  // offsets
+  int64_t doff = 0, roff = 0;
+  std::vector<Wl> dwl(nwl);
+  std::vector<PackWl> pwl(nwl);
+  size_t cq = 0;
+  for (int64_t j = 0; j < nwl; ++j) {
+    HostWl& w = wls[j];
+    const int64_t area = (int64_t)w.w_pad * w.h_pad;
+    const int32_t extra = (h->camping_pad && area % 512 == 0) ? 64 : 0;
+    w.data_off = doff;
+    w.rowid_off = roff;
+    int32_t info = w.layout;
+    if (w.chunk >= 0) info = kChunk | (slot_of[cq++] << 2);
+    dwl[j] = Wl{doff, roff, w.w_pad, w.h_pad, w.n_rows, info};
+    pwl[j] = PackWl{doff, roff, w.w_pad, w.h_pad, w.n_rows, w.layout, w.row_begin, w.chunk,
+                    (int32_t)h->tile_col_begin[w.tile], extra};
+    doff += area + extra;
+    roff += w.h_pad;
+  }
+  h->nnz_pad = doff;
+  h->n_rowid = roff;
+  if (doff >= ((int64_t)1 << 40)) throw Fail{TC_EUNSUPPORTED, "padded format too large"};
+
+  // ---- a7: pack
+  h->d_idx = hold<int32_t>(h, doff);
+  h->d_val = hold<float>(h, doff);
+  h->d_rowid = hold<int32_t>(h, roff);
+  h->d_wl = hold<Wl>(h, nwl);
+  if (nwl > 0) {
+    PackWl* d_pwl = tmp.get<PackWl>(nwl);
+    HIPX(hipMemcpyAsync(d_pwl, pwl.data(), sizeof(PackWl) * nwl, hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(h->d_wl, dwl.data(), sizeof(Wl) * nwl, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_pack, dim3(nblk(nwl, kB / kWave)), dim3(kB), 0, st, d_pwl, nwl, srt_start, rows_len,
+                       rows_sorted, b_icol, b_val, h->split_len, h->d_idx, h->d_val, h->d_rowid);
+    HIPX(hipGetLastError());
+  }
+  h->d_split = hold<SplitRow>(h, (int64_t)srows.size());
+  h->d_partial = hold<double>(h, std::max<int64_t>(h->n_slots, 1) * 256);
+  if (!srows.empty())
+    HIPX(hipMemcpyAsync(h->d_split, srows.data(), sizeof(SplitRow) * srows.size(), hipMemcpyHostToDevice, st));
+  h->d_xbuf = hold<float>(h, std::max(n_rows, n_cols));
+  h->d_ybuf = hold<float>(h, std::max(n_rows, n_cols));
+  h->d_red = hold<double>(h, 4096);
+  HIPX(hipStreamSynchronize(st));
+}
+
+}  // namespace
+}  // namespace tc
+
+using namespace tc;
+
+extern "C" void tc_build_opts_default(tc_build_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tile_width = 0;
+  o->n_tiles = -1;
+  o->wl_policy = 0;
+  o->wave = 64;
+  o->split_len = -1;
+  o->relabel = -1;
+}
+
+extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, tc_stream_t stream, tc_handle** out) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!A || !out) {
+    set_error("tc_build_tiled: NULL argument");
+    return TC_EINVAL;
+  }
+  *out = nullptr;
+  tc_build_opts def;
+  tc_build_opts_default(&def);
+  const tc_build_opts* o = opts ? opts : &def;
+  if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) {
+    set_error("tc_build_tiled: negative size");
+    return TC_EINVAL;
+  }
+  if (A->nnz >= ((int64_t)1 << 31) || A->n_rows >= ((int64_t)1 << 31) - 1 || A->n_cols >= ((int64_t)1 << 31) - 1) {
+    set_error("tc_build_tiled: sizes must fit 32-bit ids (nnz < 2^31)");
+    return TC_EUNSUPPORTED;
+  }
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val))) {
+    set_error("tc_build_tiled: NULL CSR array");
+    return TC_EINVAL;
+  }
+  if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->max_act_warp < 0 || o->wl_policy < 0 ||
+      o->wl_policy > 2 || (o->wl_policy == 1 && !o->wl_per_tile) || (o->relabel > 0 && A->n_rows != A->n_cols)) {
+    set_error("tc_build_tiled: invalid option");
+    return TC_EINVAL;
+  }
+  if ((o->alloc == nullptr) != (o->free == nullptr)) {
+    set_error("tc_build_tiled: give both alloc and free or neither");
+    return TC_EINVAL;
+  }
+  tc_handle* h = new tc_handle();
+  h->n_rows = A->n_rows;
+  h->n_cols = A->n_cols;
+  h->nnz = A->nnz;
+  h->W = o->tile_width > 0 ? o->tile_width : (1 << 20);
+  h->S = o->wave > 0 ? o->wave : 64;
+  h->split_len = o->split_len < 0 ? 8192 : o->split_len;
+  h->camping_pad = o->camping_pad != 0;
+  h->relabel = o->relabel < 0 ? (A->n_rows == A->n_cols) : (o->relabel != 0);
+  h->max_act_warp = o->max_act_warp > 0 ? o->max_act_warp : 8192;
+  h->alloc = o->alloc;
+  h->dfree = o->free;
+  h->alloc_ctx = o->alloc_ctx;
+  try {
+    build(A, o, (hipStream_t)stream, h);
+  } catch (const Fail& f) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    set_error("tc_build_tiled: " + f.msg);
+    tc_destroy(h);
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    set_error("tc_build_tiled: host allocation failed");
+    tc_destroy(h);
+    return TC_ENOMEM;
+  }
+  h->build_us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return TC_OK;
+}

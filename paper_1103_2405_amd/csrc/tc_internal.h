@@ -1,0 +1,136 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tcspmv.h"
+
+namespace tc {
+
+constexpr int kWave = 64;
+
+// Workload layouts (Solution 3): row-major rectangles run one row at a time
+// across the wavefront, column-major ones give each lane its own row; a chunk
+// is one piece of a heavy row that was split across wavefronts.
+enum : int32_t { kRM = 0, kCM = 1, kChunk = 2 };
+
+// Device descriptor of one workload (32 bytes).
+struct Wl {
+  int64_t data_off;   // first element in idx/val
+  int64_t rowid_off;  // first entry in rowid
+  int32_t w_pad;      // elements per row as stored (RM, chunk) or columns (CM)
+  int32_t h_pad;      // rows as stored (RM: real rows, CM: padded rows, chunk: 1)
+  int32_t n_rows;     // real rows
+  int32_t info;       // layout in bits 0-1; for chunks the partial slot in bits 2..31
+};
+static_assert(sizeof(Wl) == 32, "descriptor layout");
+
+// One heavy row whose chunks (from any tile) are summed after the tile passes.
+struct SplitRow {
+  int32_t row;        // internal row id
+  int32_t slot_begin; // first partial slot
+  int32_t n_slots;    // chunks over all tiles, in (tile, chunk) order
+  int32_t pad_;
+};
+
+// Host-side workload record (also what the format export returns).
+struct HostWl {
+  int32_t tile, layout, w, w_pad, h_pad, row_begin, n_rows, chunk, n_chunks;
+  int64_t data_off, rowid_off;
+};
+
+// Throughput table over powers of two of (w, h) for the dense tiles and the
+// sparse tile (Section 3.3: offline component of the performance model).
+struct PerfTable {
+  int nw = 0, nh = 0;
+  std::vector<int64_t> dense, sparse;  // [lw * nh + lh]
+  int64_t perf(bool sparse_tile, int64_t w, int64_t h) const;
+};
+bool load_perf_table(const char* path, PerfTable* t, std::string* err);
+void default_perf_table(PerfTable* t);
+
+// Length histogram of one tile's rows, in decreasing length.
+struct LenRun {
+  int64_t len;
+  int64_t count;
+};
+
+struct PartitionParams {
+  int32_t S;
+  int32_t split_len;
+  int64_t max_act_warp;
+  bool camping_pad;
+};
+
+// Algorithm 2 / Algorithm 3 (performance model) for one tile.
+int64_t choose_wl(const std::vector<LenRun>& runs, int64_t tile_nnz, const PerfTable& table,
+                  bool sparse_tile, const PartitionParams& p);
+double model_time(const std::vector<LenRun>& runs, int64_t wl, const PerfTable& table,
+                  bool sparse_tile, const PartitionParams& p);
+// Greedy packing of a tile into workloads (Solution 3); appends to `out`.
+// row_base is the index of the tile's first row in the global sorted-row list.
+void partition_tile(const std::vector<LenRun>& runs, int64_t wl, int32_t tile, int64_t row_base,
+                    const PartitionParams& p, std::vector<HostWl>* out);
+
+// thread-local error message
+void set_error(const std::string& msg);
+
+}  // namespace tc
+
+// The handle: every device buffer of one built matrix.
+struct tc_handle {
+  int64_t n_rows = 0, n_cols = 0, nnz = 0;
+  int32_t W = 0, S = 64, split_len = 0, T = 0, n_tiles = 0;
+  bool relabel = false, camping_pad = false;
+  int64_t max_act_warp = 8192;
+  int64_t nnz_pad = 0, n_rowid = 0, n_rows_sorted = 0, n_dangling = 0;
+  int64_t n_wl = 0, n_slots = 0, n_split_rows = 0;
+  double build_us = 0.0;
+
+  // host copies of small metadata
+  std::vector<int64_t> tile_col_begin, tile_col_end, tile_nnz, tile_wl, tile_row_off;
+  std::vector<int64_t> tile_wl_begin;  // workloads of tile t: [tile_wl_begin[t], tile_wl_begin[t+1])
+  std::vector<tc::HostWl> wls;
+
+  // device buffers (owned)
+  int32_t* d_cperm = nullptr;       // internal column -> original column
+  int32_t* d_cpos = nullptr;        // original column -> internal column
+  int32_t* d_rowmap = nullptr;      // original row -> internal row
+  int32_t* d_rowinv = nullptr;      // internal row -> original row
+  int32_t* d_clen = nullptr;        // column lengths (original ids)
+  int32_t* d_rows_sorted = nullptr; // per-tile sorted internal rows
+  int32_t* d_rows_len = nullptr;
+  tc::Wl* d_wl = nullptr;
+  int32_t* d_idx = nullptr;
+  float* d_val = nullptr;
+  int32_t* d_rowid = nullptr;
+  tc::SplitRow* d_split = nullptr;
+  double* d_partial = nullptr;
+  float* d_xbuf = nullptr;          // internal-space x for spmv on user vectors
+  float* d_ybuf = nullptr;
+  double* d_red = nullptr;          // reduction scratch
+  int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
+
+  // allocator
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*dfree)(void*, void*) = nullptr;
+  void* alloc_ctx = nullptr;
+  std::vector<void*> owned;
+
+  // growable workspace for SpMM and the drivers (device)
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+
+  // timing of the tile kernels (optional)
+  bool timing = false;
+  double tile_kernel_ms = 0.0;
+  int64_t tile_launches = 0;
+  int64_t spmv_calls = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+};

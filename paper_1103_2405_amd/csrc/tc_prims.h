@@ -1,0 +1,168 @@
+// Device primitives of the format builder: a deterministic exclusive scan and
+// one stable counting-sort pass.  Every sort of the builder (columns by
+// length, entries by tile, rows by length) is a sequence of such passes, so
+// the order of equal keys is always the input order and the result never
+// depends on scheduling.
+#pragma once
+
+#include "tc_internal.h"
+
+namespace tc {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanPer = 16;
+constexpr int64_t kScanTile = (int64_t)kScanBlock * kScanPer;
+
+__device__ inline int lane_id() { return (int)__lane_id(); }
+
+// Inclusive scan across the 64 lanes of a wavefront.
+template <typename T>
+__device__ inline T wave_incl_scan(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread across a 256-thread block;
+// *total receives the block sum.  Uses 4 + 1 LDS words.
+template <typename T>
+__device__ inline T block_excl_scan(T v, T* total) {
+  __shared__ T wsum[kScanBlock / kWave];
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  T inc = wave_incl_scan(v);
+  if (lane == kWave - 1) wsum[wv] = inc;
+  __syncthreads();
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kScanBlock / kWave; ++i) {
+    if (i < wv) off += wsum[i];
+    tot += wsum[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+template <typename In>
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const In* __restrict__ in, int64_t n,
+                                                            int64_t* __restrict__ block_sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i)
+    if (base + i < n) s += (int64_t)in[base + i];
+  int64_t tot;
+  block_excl_scan<int64_t>(s, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of nb block sums by one block (nb is at most a few 10^5).
+__global__ void __launch_bounds__(kScanBlock) k_scan_blocks(int64_t* __restrict__ bs, int64_t nb,
+                                                            int64_t* __restrict__ grand_total) {
+  const int64_t per = (nb + kScanBlock - 1) / kScanBlock;
+  const int64_t b0 = (int64_t)threadIdx.x * per;
+  int64_t s = 0;
+  for (int64_t i = 0; i < per; ++i)
+    if (b0 + i < nb) s += bs[b0 + i];
+  int64_t tot;
+  int64_t off = block_excl_scan<int64_t>(s, &tot);
+  for (int64_t i = 0; i < per; ++i)
+    if (b0 + i < nb) {
+      int64_t v = bs[b0 + i];
+      bs[b0 + i] = off;
+      off += v;
+    }
+  if (threadIdx.x == 0 && grand_total) *grand_total = tot;
+}
+
+template <typename In, typename Out>
+__global__ void __launch_bounds__(kScanBlock) k_scan_down(const In* __restrict__ in, int64_t n,
+                                                          const int64_t* __restrict__ bs,
+                                                          Out* __restrict__ out) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  In v[kScanPer];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : (In)0;
+    s += (int64_t)v[i];
+  }
+  int64_t tot;
+  int64_t off = block_excl_scan<int64_t>(s, &tot) + bs[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (base + i < n) out[base + i] = (Out)off;
+    off += (int64_t)v[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stable counting-sort pass.  The input is cut into chunks of `chunk` items,
+// one wavefront per chunk.  Pass 1 counts each chunk's buckets; an exclusive
+// scan over the bucket-major count matrix gives every (bucket, chunk) its
+// first output slot; pass 2 walks each chunk in order, 64 items at a time, and
+// ranks equal buckets inside the step by lane order (ballots over the bucket's
+// bits), so equal keys keep their input order.
+//
+// Op provides:  __device__ uint32_t bucket(int64_t k) const;
+//               __device__ void move(int64_t k, int64_t pos) const;
+constexpr int kCsBlock = 256;
+constexpr int kCsWaves = kCsBlock / kWave;
+
+template <class Op>
+__global__ void __launch_bounds__(kCsBlock) k_cs_hist(Op op, int64_t n, int32_t nbuckets, int64_t chunk,
+                                                      int64_t nchunks, int32_t* __restrict__ hist) {
+  extern __shared__ int32_t cs_cnt[];
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  const int64_t c = (int64_t)blockIdx.x * kCsWaves + wv;
+  int32_t* cnt = cs_cnt + wv * nbuckets;
+  for (int i = lane; i < nbuckets; i += kWave) cnt[i] = 0;
+  __syncthreads();
+  if (c < nchunks) {
+    const int64_t end = min(n, (c + 1) * chunk);
+    for (int64_t k = c * chunk + lane; k < end; k += kWave) atomicAdd(&cnt[op.bucket(k)], 1);
+  }
+  __syncthreads();
+  if (c < nchunks)
+    for (int i = lane; i < nbuckets; i += kWave) hist[(int64_t)i * nchunks + c] = cnt[i];
+}
+
+template <class Op>
+__global__ void __launch_bounds__(kCsBlock) k_cs_scatter(Op op, int64_t n, int32_t nbuckets, int32_t nbits,
+                                                         int64_t chunk, int64_t nchunks,
+                                                         const int64_t* __restrict__ offs) {
+  extern __shared__ int64_t cs_run[];
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  const int64_t c = (int64_t)blockIdx.x * kCsWaves + wv;
+  if (c >= nchunks) return;  // whole wavefront leaves; no block barrier below
+  int64_t* run = cs_run + wv * nbuckets;
+  for (int i = lane; i < nbuckets; i += kWave) run[i] = offs[(int64_t)i * nchunks + c];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int64_t end = min(n, (c + 1) * chunk);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t base = c * chunk; base < end; base += kWave) {
+    const int64_t k = base + lane;
+    const bool valid = k < end;
+    const uint32_t b = valid ? op.bucket(k) : 0u;
+    uint64_t peers = __ballot(valid);
+    for (int bit = 0; bit < nbits; ++bit) {
+      const bool set = (b >> bit) & 1u;
+      const uint64_t bal = __ballot(set);
+      peers &= set ? bal : ~bal;
+    }
+    const int64_t pos = valid ? run[b] + (int64_t)__popcll(peers & lt) : 0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (valid) op.move(k, pos);
+    if (valid && (peers >> lane) == 1ull) run[b] += (int64_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+}
+
+}  // namespace tc

@@ -1,0 +1,732 @@
+// Products with a built handle and the power iterations on top of them.
+//
+// Tile pass (Section 3.1, Solution 3): one wavefront per workload.
+//   row-major:    the wavefront walks one row at a time, lanes striding the
+//                 padded row, then a cross-lane sum; lane 0 updates y.
+//   column-major: lane r owns row r of the rectangle and walks its columns;
+//                 consecutive lanes read consecutive addresses.
+//   chunk:        one piece of a split heavy row; its sum goes to a partial
+//                 slot that is added to y after the last tile.
+// Tiles run in order, one launch each (dense tiles, then the sparse tile), so
+// every row's y entry is read-modified-written at most once per tile and
+// never by two wavefronts at once (Section 3.1: a kernel per tile).  Products
+// are exact in FP64 and each row's per-tile sum is accumulated in FP64, then
+// added to the FP32 y once per tile.
+#include <algorithm>
+#include <cmath>
+
+#include "tc_internal.h"
+
+namespace tc {
+
+namespace {
+
+constexpr int kB = 256;
+constexpr int kWpb = kB / kWave;  // workloads per block
+
+inline unsigned nblk(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+__device__ inline int lane_id() { return (int)__lane_id(); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__device__ inline void add_to_y(float* y, int32_t row, double s) { y[row] = (float)((double)y[row] + s); }
+
+__global__ void __launch_bounds__(kB) k_tile_spmv(const Wl* __restrict__ wl, int64_t n_wl,
+                                                  const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                  const int32_t* __restrict__ rowid, const float* __restrict__ x,
+                                                  float* __restrict__ y, double* __restrict__ partial) {
+  const int lane = lane_id();
+  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (j >= n_wl) return;
+  const Wl d = wl[j];
+  const int layout = d.info & 3;
+  if (layout == kCM) {
+    const int64_t hp = d.h_pad;
+    for (int32_t r0 = 0; r0 < d.n_rows; r0 += kWave) {
+      const int32_t r = r0 + lane;
+      if (r < d.n_rows) {
+        const int32_t* ip = idx + d.data_off + r;
+        const float* vp = val + d.data_off + r;
+        double acc = 0.0;
+        int32_t c = 0;
+        for (; c + 4 <= d.w_pad; c += 4) {
+          const int32_t i0 = ip[(c + 0) * hp], i1 = ip[(c + 1) * hp], i2 = ip[(c + 2) * hp], i3 = ip[(c + 3) * hp];
+          const float v0 = vp[(c + 0) * hp], v1 = vp[(c + 1) * hp], v2 = vp[(c + 2) * hp], v3 = vp[(c + 3) * hp];
+          const float x0 = x[i0], x1 = x[i1], x2 = x[i2], x3 = x[i3];
+          acc = fma((double)v0, (double)x0, acc);
+          acc = fma((double)v1, (double)x1, acc);
+          acc = fma((double)v2, (double)x2, acc);
+          acc = fma((double)v3, (double)x3, acc);
+        }
+        for (; c < d.w_pad; ++c) acc = fma((double)vp[c * hp], (double)x[ip[c * hp]], acc);
+        add_to_y(y, rowid[d.rowid_off + r], acc);
+      }
+    }
+  } else {
+    const int64_t wp = d.w_pad;
+    for (int32_t r = 0; r < d.n_rows; ++r) {
+      const int64_t base = d.data_off + r * wp;
+      double acc = 0.0;
+      int64_t c = lane;
+      for (; c + 3 * kWave < wp; c += 4 * kWave) {
+        const int32_t i0 = idx[base + c], i1 = idx[base + c + kWave], i2 = idx[base + c + 2 * kWave],
+                      i3 = idx[base + c + 3 * kWave];
+        const float v0 = val[base + c], v1 = val[base + c + kWave], v2 = val[base + c + 2 * kWave],
+                    v3 = val[base + c + 3 * kWave];
+        const float x0 = x[i0], x1 = x[i1], x2 = x[i2], x3 = x[i3];
+        acc = fma((double)v0, (double)x0, acc);
+        acc = fma((double)v1, (double)x1, acc);
+        acc = fma((double)v2, (double)x2, acc);
+        acc = fma((double)v3, (double)x3, acc);
+      }
+      for (; c < wp; c += kWave) acc = fma((double)val[base + c], (double)x[idx[base + c]], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        if (layout == kChunk)
+          partial[d.info >> 2] = acc;
+        else
+          add_to_y(y, rowid[d.rowid_off + r], acc);
+      }
+    }
+  }
+}
+
+// Sum of every split row's chunks in (tile, chunk) order, added to y.
+__global__ void k_split_combine(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
+                                float* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const SplitRow s = sr[i];
+  double acc = 0.0;
+  for (int32_t q = 0; q < s.n_slots; ++q) acc += partial[s.slot_begin + q];
+  add_to_y(y, s.row, acc);
+}
+
+// ---- multiple right-hand sides: X is n x k row-major, column block of QB
+template <int QB>
+__global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int64_t n_wl,
+                                                  const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                  const int32_t* __restrict__ rowid, const float* __restrict__ X,
+                                                  float* __restrict__ Y, int32_t k, double* __restrict__ partial) {
+  const int lane = lane_id();
+  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (j >= n_wl) return;
+  const int32_t q0 = blockIdx.y * QB;
+  const int32_t nq = min(QB, k - q0);
+  const Wl d = wl[j];
+  const int layout = d.info & 3;
+  double acc[QB];
+  if (layout == kCM) {
+    const int64_t hp = d.h_pad;
+    for (int32_t r0 = 0; r0 < d.n_rows; r0 += kWave) {
+      const int32_t r = r0 + lane;
+      if (r >= d.n_rows) continue;
+#pragma unroll
+      for (int q = 0; q < QB; ++q) acc[q] = 0.0;
+      for (int32_t c = 0; c < d.w_pad; ++c) {
+        const int64_t e = d.data_off + (int64_t)c * hp + r;
+        const double v = (double)val[e];
+        const float* xr = X + (int64_t)idx[e] * k + q0;
+#pragma unroll
+        for (int q = 0; q < QB; ++q)
+          if (q < nq) acc[q] = fma(v, (double)xr[q], acc[q]);
+      }
+      const int64_t row = rowid[d.rowid_off + r];
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+        if (q < nq) add_to_y(Y + row * k + q0, q, acc[q]);
+    }
+  } else {
+    const int64_t wp = d.w_pad;
+    for (int32_t r = 0; r < d.n_rows; ++r) {
+      const int64_t base = d.data_off + r * wp;
+#pragma unroll
+      for (int q = 0; q < QB; ++q) acc[q] = 0.0;
+      for (int64_t c = lane; c < wp; c += kWave) {
+        const double v = (double)val[base + c];
+        const float* xr = X + (int64_t)idx[base + c] * k + q0;
+#pragma unroll
+        for (int q = 0; q < QB; ++q)
+          if (q < nq) acc[q] = fma(v, (double)xr[q], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < QB; ++q) acc[q] = wave_sum(acc[q]);
+      if (lane == 0) {
+        if (layout == kChunk) {
+          for (int q = 0; q < nq; ++q) partial[(int64_t)(d.info >> 2) * k + q0 + q] = acc[q];
+        } else {
+          const int64_t row = rowid[d.rowid_off + r];
+          for (int q = 0; q < nq; ++q) add_to_y(Y + row * k + q0, q, acc[q]);
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_split_combine_mm(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
+                                   float* __restrict__ Y, int32_t k) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * k) return;
+  const int64_t i = t / k;
+  const int32_t q = (int32_t)(t % k);
+  const SplitRow s = sr[i];
+  double acc = 0.0;
+  for (int32_t u = 0; u < s.n_slots; ++u) acc += partial[(int64_t)(s.slot_begin + u) * k + q];
+  add_to_y(Y + (int64_t)s.row * k, q, acc);
+}
+
+// ---- plain CSR baseline: one thread per row (FP64 accumulation)
+__global__ void k_csr_scalar(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             const float* __restrict__ val, int64_t n_rows, const float* __restrict__ x,
+                             float* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  double acc = 0.0;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc = fma((double)val[k], (double)x[col[k]], acc);
+  y[i] = (float)acc;
+}
+
+// ---- vector kernels
+__global__ void k_fill_f32(float* __restrict__ a, int64_t n, float v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// out[k*row_stride + q] = in[perm[k]*row_stride + q]   (rows gathered)
+__global__ void k_gather_rows(const float* __restrict__ in, const int32_t* __restrict__ perm, int64_t n, int32_t w,
+                              float* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * w) return;
+  const int64_t k = t / w;
+  const int32_t q = (int32_t)(t % w);
+  out[t] = in[(int64_t)perm[k] * w + q];
+}
+
+__global__ void k_set_f64(double* p, double v) { *p = v; }
+
+template <int NV>
+__device__ inline void block_sum_store(double (&v)[NV], double* out_base, int64_t stride) {
+  __shared__ double sm[NV][kB / kWave];
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = wave_sum(v[q]);
+    if (lane == 0) sm[q][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kB / kWave; ++w) s += sm[q][w];
+      out_base[q * stride] = s;
+    }
+  }
+}
+
+constexpr int kRedBlocks = 1024;
+
+// Sum of nparts consecutive partials for each of nv quantities, fixed order.
+__global__ void k_finish(const double* __restrict__ parts, int nparts, int nv, double* __restrict__ out) {
+  __shared__ double sm[kB];
+  for (int q = 0; q < nv; ++q) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kB) s += parts[(int64_t)q * nparts + i];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < kB; ++i) t += sm[i];
+      out[q] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// PageRank update (Eq. 6 with uniform dangling mass), fused with the L1
+// change and the dangling mass of the new iterate:
+//   p'_i = c (y_i + d/n) + (1-c)/n
+__global__ void __launch_bounds__(kB) k_pr_update(const float* __restrict__ y, float* __restrict__ p, int64_t n,
+                                                  int64_t dang_begin, double c, const double* __restrict__ dmass,
+                                                  double* __restrict__ parts) {
+  const double dn = *dmass / (double)n;
+  const double tele = (1.0 - c) / (double)n;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+    const float pn = (float)(c * ((double)y[i] + dn) + tele);
+    v[0] += fabs((double)pn - (double)p[i]);
+    if (i >= dang_begin) v[1] += (double)pn;
+    p[i] = pn;
+  }
+  block_sum_store<2>(v, parts + blockIdx.x, gridDim.x);
+}
+
+// sum of p over the dangling range (first iteration)
+__global__ void __launch_bounds__(kB) k_range_sum(const float* __restrict__ p, int64_t b, int64_t e,
+                                                  double* __restrict__ parts) {
+  double v[1] = {0.0};
+  for (int64_t i = b + (int64_t)blockIdx.x * kB + threadIdx.x; i < e; i += (int64_t)gridDim.x * kB) v[0] += (double)p[i];
+  block_sum_store<1>(v, parts + blockIdx.x, gridDim.x);
+}
+
+// HITS: sums of the two halves of y
+__global__ void __launch_bounds__(kB) k_hits_sums(const float* __restrict__ y, const int32_t* __restrict__ rowinv,
+                                                  int64_t n2, int64_t n, double* __restrict__ parts) {
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n2; i += (int64_t)gridDim.x * kB)
+  {
+    if (rowinv[i] >= n)
+      v[1] += (double)y[i];
+    else
+      v[0] += (double)y[i];
+  }
+  block_sum_store<2>(v, parts + blockIdx.x, gridDim.x);
+}
+
+// HITS: x' = y / (sum of its half), L1 change
+__global__ void __launch_bounds__(kB) k_hits_update(const float* __restrict__ y, float* __restrict__ x,
+                                                    const int32_t* __restrict__ rowinv, int64_t n2, int64_t n,
+                                                    const double* __restrict__ sums, double* __restrict__ parts,
+                                                    int* __restrict__ err) {
+  const double sa = sums[0], sh = sums[1];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (sa == 0.0 || sh == 0.0)) *err = 1;
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n2; i += (int64_t)gridDim.x * kB) {
+    const double s = rowinv[i] >= n ? sh : sa;
+    const float xn = s != 0.0 ? (float)((double)y[i] / s) : 0.0f;
+    v[0] += fabs((double)xn - (double)x[i]);
+    x[i] = xn;
+  }
+  block_sum_store<1>(v, parts + blockIdx.x, gridDim.x);
+}
+
+// RWR: R' = c Y + (1-c) E, per-column L1 change (nq columns of k at q0)
+__global__ void __launch_bounds__(kB) k_rwr_update(const float* __restrict__ Y, float* __restrict__ R, int64_t n,
+                                                   int32_t k, double c, const int32_t* __restrict__ seeds,
+                                                   double* __restrict__ parts, int nblocks) {
+  // thread layout: each thread owns one column q (threadIdx.x % k) of rows
+  // spaced by the grid; k <= 256
+  const int32_t q = threadIdx.x % k;
+  const int32_t rpb = kB / k;  // rows per block step
+  const int32_t rr = threadIdx.x / k;
+  __shared__ double sm[kB];
+  double s = 0.0;
+  if (rr < rpb) {
+    const int32_t seed = seeds[q];
+    for (int64_t i = (int64_t)blockIdx.x * rpb + rr; i < n; i += (int64_t)gridDim.x * rpb) {
+      const int64_t e = i * k + q;
+      const float rn = (float)(c * (double)Y[e] + (i == seed ? (1.0 - c) : 0.0));
+      s += fabs((double)rn - (double)R[e]);
+      R[e] = rn;
+    }
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double t = 0.0;
+    for (int32_t u = 0; u < rpb; ++u) t += sm[u * k + threadIdx.x];
+    parts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = t;
+  }
+}
+
+__global__ void k_rwr_init(float* __restrict__ R, int64_t n, int32_t k, const int32_t* __restrict__ seeds) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * k) return;
+  const int64_t i = t / k;
+  const int32_t q = (int32_t)(t % k);
+  R[t] = (i == seeds[q]) ? 1.0f : 0.0f;
+}
+
+__global__ void k_map_ids(const int32_t* __restrict__ ids, const int32_t* __restrict__ map, int32_t k,
+                          int32_t* __restrict__ out) {
+  for (int32_t q = threadIdx.x; q < k; q += blockDim.x) out[q] = map[ids[q]];
+}
+
+__global__ void k_max_of(const double* __restrict__ v, int n, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, v[i]);
+    *out = m;
+  }
+}
+
+// ------------------------------------------------------------ host side
+struct Err {
+  tc_status st;
+  std::string msg;
+};
+
+#define HIPC(call)                                                          \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) throw Err{TC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+void* workspace(tc_handle* h, size_t bytes, hipStream_t st) {
+  if (bytes <= h->ws_bytes) return h->d_ws;
+  HIPC(hipStreamSynchronize(st));
+  if (h->d_ws) HIPC(hipFree(h->d_ws));
+  h->d_ws = nullptr;
+  h->ws_bytes = 0;
+  if (hipMalloc(&h->d_ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    h->d_ws = nullptr;
+    throw Err{TC_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed"};
+  }
+  h->ws_bytes = bytes;
+  return h->d_ws;
+}
+
+hipEvent_t next_event(tc_handle* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+template <typename... KArgs, typename... Args>
+void launch_tile(tc_handle* h, void (*kern)(KArgs...), dim3 grid, hipStream_t st, Args... args) {
+  if (h->timing) {
+    hipEvent_t a = next_event(h), b = next_event(h);
+    hipExtLaunchKernelGGL(kern, grid, dim3(kB), 0, st, a, b, 0, args...);
+    h->tile_launches++;
+  } else {
+    hipLaunchKernelGGL(kern, grid, dim3(kB), 0, st, args...);
+  }
+  HIPC(hipGetLastError());
+}
+
+// y := A x in internal ids (x: n_cols, y: n_rows)
+void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st) {
+  if (h->n_rows > 0) {
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk(h->n_rows, kB)), dim3(kB), 0, st, y, h->n_rows, 0.0f);
+    HIPC(hipGetLastError());
+  }
+  for (int t = 0; t < h->n_tiles; ++t) {
+    const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];
+    if (e == b) continue;
+    launch_tile(h, k_tile_spmv, dim3(nblk(e - b, kWpb)), st, (const Wl*)(h->d_wl + b), (int64_t)(e - b),
+                (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, x, y, h->d_partial);
+  }
+  if (h->n_split_rows > 0) {
+    hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
+                       h->n_split_rows, h->d_partial, y);
+    HIPC(hipGetLastError());
+  }
+  h->spmv_calls++;
+}
+
+void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st) {
+  constexpr int QB = 8;
+  if (h->n_rows > 0) {
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk(h->n_rows * k, kB)), dim3(kB), 0, st, Y, h->n_rows * k, 0.0f);
+    HIPC(hipGetLastError());
+  }
+  for (int t = 0; t < h->n_tiles; ++t) {
+    const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];
+    if (e == b) continue;
+    launch_tile(h, k_tile_spmm<QB>, dim3(nblk(e - b, kWpb), (k + QB - 1) / QB), st, (const Wl*)(h->d_wl + b),
+                (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, X, Y,
+                k, h->d_partial);
+  }
+  if (h->n_split_rows > 0) {
+    hipLaunchKernelGGL(k_split_combine_mm, dim3(nblk(h->n_split_rows * k, kB)), dim3(kB), 0, st, h->d_split,
+                       h->n_split_rows, h->d_partial, Y, k);
+    HIPC(hipGetLastError());
+  }
+  h->spmv_calls++;
+}
+
+void gather_rows(const float* in, const int32_t* perm, int64_t n, int32_t w, float* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3(nblk(n * w, kB)), dim3(kB), 0, st, in, perm, n, w, out);
+  HIPC(hipGetLastError());
+}
+
+double read_f64(const double* d, hipStream_t st) {
+  double v = 0.0;
+  HIPC(hipMemcpyAsync(&v, d, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  return v;
+}
+
+void need_square(const tc_handle* h, const char* who) {
+  if (!h->relabel || h->n_rows != h->n_cols)
+    throw Err{TC_EINVAL, std::string(who) + ": needs a square matrix built with row relabelling"};
+}
+
+template <class F>
+tc_status guarded(const char* who, F&& f) {
+  try {
+    return f();
+  } catch (const Err& e) {
+    set_error(std::string(who) + ": " + e.msg);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error(std::string(who) + ": host allocation failed");
+    return TC_ENOMEM;
+  }
+}
+
+}  // namespace
+}  // namespace tc
+
+using namespace tc;
+
+extern "C" tc_status tc_spmv_internal(const tc_handle* hc, const float* x, float* y, tc_stream_t stream) {
+  return guarded("tc_spmv_internal", [&]() -> tc_status {
+    if (!hc || (!x && hc->n_cols > 0) || (!y && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    if ((const void*)x == (const void*)y && hc->n_rows > 0) throw Err{TC_EINVAL, "x and y must not alias"};
+    spmv_internal(const_cast<tc_handle*>(hc), x, y, (hipStream_t)stream);
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_spmv(const tc_handle* hc, const float* x, float* y, tc_stream_t stream) {
+  return guarded("tc_spmv", [&]() -> tc_status {
+    if (!hc || (!x && hc->n_cols > 0) || (!y && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    if ((const void*)x == (const void*)y && hc->n_rows > 0) throw Err{TC_EINVAL, "x and y must not alias"};
+    tc_handle* h = const_cast<tc_handle*>(hc);
+    hipStream_t st = (hipStream_t)stream;
+    gather_rows(x, h->d_cperm, h->n_cols, 1, h->d_xbuf, st);
+    if (h->relabel) {
+      spmv_internal(h, h->d_xbuf, h->d_ybuf, st);
+      gather_rows(h->d_ybuf, h->d_rowmap, h->n_rows, 1, y, st);
+    } else {
+      spmv_internal(h, h->d_xbuf, y, st);
+    }
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_spmm(const tc_handle* hc, const float* X, float* Y, int32_t k, tc_stream_t stream) {
+  return guarded("tc_spmm", [&]() -> tc_status {
+    if (!hc || (!X && hc->n_cols > 0) || (!Y && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    if (k < 1 || k > 256) throw Err{TC_EINVAL, "k must be in [1, 256]"};
+    if ((const void*)X == (const void*)Y && hc->n_rows > 0) throw Err{TC_EINVAL, "X and Y must not alias"};
+    tc_handle* h = const_cast<tc_handle*>(hc);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t xb = sizeof(float) * (size_t)h->n_cols * k, yb = sizeof(float) * (size_t)h->n_rows * k;
+    char* ws = (char*)workspace(h, ((xb + 255) / 256) * 256 + yb, st);
+    float* Xi = (float*)ws;
+    float* Yi = (float*)(ws + ((xb + 255) / 256) * 256);
+    gather_rows(X, h->d_cperm, h->n_cols, k, Xi, st);
+    if (h->relabel) {
+      spmm_internal(h, Xi, Yi, k, st);
+      gather_rows(Yi, h->d_rowmap, h->n_rows, k, Y, st);
+    } else {
+      spmm_internal(h, Xi, Y, k, st);
+    }
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_csr_spmv(const tc_csr* A, const float* x, float* y, tc_stream_t stream) {
+  return guarded("tc_csr_spmv", [&]() -> tc_status {
+    if (!A || !A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)) || (!x && A->n_cols > 0) ||
+        (!y && A->n_rows > 0))
+      throw Err{TC_EINVAL, "NULL argument"};
+    if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) throw Err{TC_EINVAL, "negative size"};
+    if (A->n_rows > 0) {
+      hipLaunchKernelGGL(k_csr_scalar, dim3(nblk(A->n_rows, kB)), dim3(kB), 0, (hipStream_t)stream, A->row_ptr,
+                         A->col_idx, A->val, A->n_rows, x, y);
+      HIPC(hipGetLastError());
+    }
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_t max_iter, int32_t check_every,
+                                 float* p_out, int32_t* iters, double* resid, tc_stream_t stream) {
+  return guarded("tc_pagerank", [&]() -> tc_status {
+    if (!hc || (!p_out && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    if (!(c >= 0.0f && c <= 1.0f) || max_iter < 0) throw Err{TC_EINVAL, "need 0 <= c <= 1 and max_iter >= 0"};
+    need_square(hc, "tc_pagerank");
+    tc_handle* h = const_cast<tc_handle*>(hc);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = h->n_rows;
+    if (check_every < 1) check_every = 1;
+    float* p = h->d_xbuf;
+    float* y = h->d_ybuf;
+    double* parts = h->d_red;                  // 2 * kRedBlocks
+    double* res = h->d_red + 2 * kRedBlocks;   // [resid, dangling mass]
+    int32_t it = 0;
+    double r = 0.0;
+    bool conv = false;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, kB)), dim3(kB), 0, st, p, n, (float)(1.0 / (double)n));
+      HIPC(hipGetLastError());
+      hipLaunchKernelGGL(k_range_sum, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)p, n - h->n_dangling, n,
+                         parts + kRedBlocks);
+      HIPC(hipGetLastError());
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)(parts + kRedBlocks), kRedBlocks, 1,
+                         res + 1);
+      HIPC(hipGetLastError());
+      for (it = 0; it < max_iter;) {
+        spmv_internal(h, p, y, st);
+        hipLaunchKernelGGL(k_pr_update, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)y, p, n,
+                           n - h->n_dangling, (double)c, (const double*)(res + 1), parts);
+        HIPC(hipGetLastError());
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)parts, kRedBlocks, 2, res);
+        HIPC(hipGetLastError());
+        ++it;
+        if (tol > 0.0f && (it % check_every == 0 || it == max_iter)) {
+          r = read_f64(res, st);
+          if (r <= (double)tol) {
+            conv = true;
+            break;
+          }
+        }
+      }
+      if (it > 0) r = read_f64(res, st);
+      gather_rows(p, h->d_rowmap, n, 1, p_out, st);
+    }
+    if (iters) *iters = it;
+    if (resid) *resid = r;
+    if (tol > 0.0f && !conv && n > 0) {
+      set_error("tc_pagerank: tolerance not reached in max_iter iterations");
+      return TC_ENOTCONV;
+    }
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_hits(const tc_handle* hc, float tol, int32_t max_iter, int32_t check_every, float* auth,
+                             float* hub, int32_t* iters, double* resid, tc_stream_t stream) {
+  return guarded("tc_hits", [&]() -> tc_status {
+    if (!hc || ((!auth || !hub) && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    if (max_iter < 0) throw Err{TC_EINVAL, "max_iter < 0"};
+    need_square(hc, "tc_hits");
+    if (hc->n_rows % 2) throw Err{TC_EINVAL, "the HITS matrix must be 2n x 2n"};
+    tc_handle* h = const_cast<tc_handle*>(hc);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n2 = h->n_rows, n = n2 / 2;
+    if (check_every < 1) check_every = 1;
+    float* x = h->d_xbuf;
+    float* y = h->d_ybuf;
+    double* parts = h->d_red;
+    double* sums = h->d_red + 2 * kRedBlocks;       // [s_a, s_h]
+    double* res = h->d_red + 2 * kRedBlocks + 2;    // resid
+    int* err = (int*)workspace(h, 256, st);
+    int32_t it = 0;
+    double r = 0.0;
+    bool conv = false;
+    if (n2 > 0) {
+      HIPC(hipMemsetAsync(err, 0, sizeof(int), st));
+      hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n2, kB)), dim3(kB), 0, st, x, n2, (float)(1.0 / (double)n));
+      HIPC(hipGetLastError());
+      for (it = 0; it < max_iter;) {
+        spmv_internal(h, x, y, st);
+        hipLaunchKernelGGL(k_hits_sums, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)y,
+                           (const int32_t*)h->d_rowinv, n2, n, parts);
+        HIPC(hipGetLastError());
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)parts, kRedBlocks, 2, sums);
+        HIPC(hipGetLastError());
+        hipLaunchKernelGGL(k_hits_update, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)y, x,
+                           (const int32_t*)h->d_rowinv, n2, n, (const double*)sums, parts, err);
+        HIPC(hipGetLastError());
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)parts, kRedBlocks, 1, res);
+        HIPC(hipGetLastError());
+        ++it;
+        if (tol > 0.0f && (it % check_every == 0 || it == max_iter)) {
+          r = read_f64(res, st);
+          if (r <= (double)tol) {
+            conv = true;
+            break;
+          }
+        }
+      }
+      int herr = 0;
+      HIPC(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+      if (herr) throw Err{TC_EINVAL, "a half of the iterate sums to zero (graph without edges?)"};
+      if (it > 0) r = read_f64(res, st);
+      gather_rows(x, h->d_rowmap, n, 1, auth, st);
+      gather_rows(x, h->d_rowmap + n, n, 1, hub, st);
+    }
+    if (iters) *iters = it;
+    if (resid) *resid = r;
+    if (tol > 0.0f && !conv && n2 > 0) {
+      set_error("tc_hits: tolerance not reached in max_iter iterations");
+      return TC_ENOTCONV;
+    }
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k, float c, float tol,
+                            int32_t max_iter, int32_t check_every, float* R_out, int32_t* iters, double* resid,
+                            tc_stream_t stream) {
+  return guarded("tc_rwr", [&]() -> tc_status {
+    if (!hc || !seeds || (!R_out && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    if (k < 1 || k > 256) throw Err{TC_EINVAL, "k must be in [1, 256]"};
+    if (!(c >= 0.0f && c <= 1.0f) || max_iter < 0) throw Err{TC_EINVAL, "need 0 <= c <= 1 and max_iter >= 0"};
+    need_square(hc, "tc_rwr");
+    tc_handle* h = const_cast<tc_handle*>(hc);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = h->n_rows;
+    for (int32_t q = 0; q < k; ++q)
+      if (seeds[q] < 0 || seeds[q] >= n) throw Err{TC_EINVAL, "seed out of range"};
+    if (check_every < 1) check_every = 1;
+    const int nb = 256;  // reduction blocks
+    const size_t vb = ((sizeof(float) * (size_t)n * k + 255) / 256) * 256;
+    const size_t need = 2 * vb + sizeof(double) * ((size_t)nb * k + k + 8) + 2 * sizeof(int32_t) * k;
+    char* ws = (char*)workspace(h, need, st);
+    float* Rm = (float*)ws;
+    float* Ym = (float*)(ws + vb);
+    double* parts = (double*)(ws + 2 * vb);
+    double* colres = parts + (size_t)nb * k;
+    double* mx = colres + k;
+    int32_t* rawseeds = (int32_t*)(mx + 8);
+    int32_t* dseeds = rawseeds + k;
+    // internal ids of the seeds
+    HIPC(hipMemcpyAsync(rawseeds, seeds, sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_map_ids, dim3(1), dim3(kB), 0, st, (const int32_t*)rawseeds, (const int32_t*)h->d_rowmap, k,
+                       dseeds);
+    HIPC(hipGetLastError());
+    int32_t it = 0;
+    double r = 0.0;
+    bool conv = false;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_rwr_init, dim3(nblk(n * k, kB)), dim3(kB), 0, st, Rm, n, k, (const int32_t*)dseeds);
+      HIPC(hipGetLastError());
+      for (it = 0; it < max_iter;) {
+        if (k == 1)
+          spmv_internal(h, Rm, Ym, st);
+        else
+          spmm_internal(h, Rm, Ym, k, st);
+        hipLaunchKernelGGL(k_rwr_update, dim3(nb), dim3(kB), 0, st, (const float*)Ym, Rm, n, k, (double)c,
+                           (const int32_t*)dseeds, parts, nb);
+        HIPC(hipGetLastError());
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)parts, nb, k, colres);
+        HIPC(hipGetLastError());
+        hipLaunchKernelGGL(k_max_of, dim3(1), dim3(64), 0, st, (const double*)colres, k, mx);
+        HIPC(hipGetLastError());
+        ++it;
+        if (tol > 0.0f && (it % check_every == 0 || it == max_iter)) {
+          r = read_f64(mx, st);
+          if (r <= (double)tol) {
+            conv = true;
+            break;
+          }
+        }
+      }
+      if (it > 0) r = read_f64(mx, st);
+      gather_rows(Rm, h->d_rowmap, n, k, R_out, st);
+    }
+    if (iters) *iters = it;
+    if (resid) *resid = r;
+    if (tol > 0.0f && !conv && n > 0) {
+      set_error("tc_rwr: tolerance not reached in max_iter iterations");
+      return TC_ENOTCONV;
+    }
+    return TC_OK;
+  });
+}

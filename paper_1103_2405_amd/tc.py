@@ -1,0 +1,313 @@
+"""Python binding of libtcspmv (include/tcspmv.h): argument marshalling only.
+
+Device memory and streams come from PyTorch; every computation runs in the
+library's HIP kernels.  If the library is missing or cannot be loaded, every
+call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtcspmv.so")
+DEFAULT_PERF_TABLE = os.path.join(_HERE, "data", "perf_table_gfx950.txt")
+
+TC_OK, TC_EINVAL, TC_ENOMEM, TC_EHIP, TC_ENOTCONV, TC_EUNSUPPORTED = range(6)
+_STATUS = {1: "TC_EINVAL", 2: "TC_ENOMEM", 3: "TC_EHIP", 4: "TC_ENOTCONV", 5: "TC_EUNSUPPORTED"}
+
+
+class TcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+class NotConverged(TcError):
+    pass
+
+
+vp = ctypes.c_void_p
+i32, i64 = ctypes.c_int32, ctypes.c_int64
+
+
+class CCsr(ctypes.Structure):
+    _fields_ = [("n_rows", i64), ("n_cols", i64), ("nnz", i64),
+                ("row_ptr", vp), ("col_idx", vp), ("val", vp)]
+
+
+class CBuildOpts(ctypes.Structure):
+    _fields_ = [("tile_width", i32), ("n_tiles", i32), ("wl_policy", i32), ("wl_all", i32),
+                ("wl_per_tile", vp), ("n_wl_per_tile", i32), ("wave", i32), ("split_len", i32),
+                ("camping_pad", i32), ("relabel", i32), ("max_act_warp", i32),
+                ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
+
+
+class CInfo(ctypes.Structure):
+    _fields_ = [("n_rows", i64), ("n_cols", i64), ("nnz", i64),
+                ("tile_width", i32), ("wave", i32), ("split_len", i32), ("relabel", i32),
+                ("n_dense_tiles", i32), ("n_tiles", i32),
+                ("n_workloads", i64), ("nnz_pad", i64), ("n_rowid", i64), ("n_rows_sorted", i64),
+                ("n_split_rows", i64), ("n_partials", i64), ("n_dangling", i64), ("device_bytes", i64),
+                ("build_us", ctypes.c_double)]
+
+
+_VIEW_FIELDS = [("cperm", np.int32, "n_cols"), ("rowmap", np.int32, "n_rows"),
+                ("tile_col_begin", np.int64, "n_tiles"), ("tile_col_end", np.int64, "n_tiles"),
+                ("tile_nnz", np.int64, "n_tiles"), ("tile_wl", np.int64, "n_tiles"),
+                ("tile_row_off", np.int64, "n_tiles+1"), ("rows_sorted", np.int32, "n_rows_sorted"),
+                ("rows_len", np.int32, "n_rows_sorted"),
+                ("wl_tile", np.int32, "n_workloads"), ("wl_layout", np.int32, "n_workloads"),
+                ("wl_w", np.int32, "n_workloads"), ("wl_w_pad", np.int32, "n_workloads"),
+                ("wl_h_pad", np.int32, "n_workloads"), ("wl_row_begin", np.int32, "n_workloads"),
+                ("wl_n_rows", np.int32, "n_workloads"), ("wl_chunk", np.int32, "n_workloads"),
+                ("wl_n_chunks", np.int32, "n_workloads"), ("wl_data_off", np.int64, "n_workloads"),
+                ("wl_rowid_off", np.int64, "n_workloads"), ("idx", np.int32, "nnz_pad"),
+                ("val", np.float32, "nnz_pad"), ("rowid", np.int32, "n_rowid")]
+
+
+class CFormatView(ctypes.Structure):
+    _fields_ = [(name, vp) for name, _, _ in _VIEW_FIELDS]
+
+
+class CTiming(ctypes.Structure):
+    _fields_ = [("tile_kernel_ms", ctypes.c_double), ("tile_launches", i64), ("spmv_calls", i64)]
+
+
+EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_internal", "tc_spmm",
+            "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
+            "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtcspmv.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libtcspmv.so is not built (%s); run python -m paper_1103_2405_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.tc_build_opts_default.argtypes = [P(CBuildOpts)]
+    lib.tc_build_opts_default.restype = None
+    lib.tc_build_tiled.argtypes = [P(CCsr), P(CBuildOpts), vp, P(vp)]
+    lib.tc_spmv.argtypes = [vp, vp, vp, vp]
+    lib.tc_spmv_internal.argtypes = [vp, vp, vp, vp]
+    lib.tc_spmm.argtypes = [vp, vp, vp, i32, vp]
+    lib.tc_pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_float, i32, i32, vp, P(i32), P(ctypes.c_double), vp]
+    lib.tc_hits.argtypes = [vp, ctypes.c_float, i32, i32, vp, vp, P(i32), P(ctypes.c_double), vp]
+    lib.tc_rwr.argtypes = [vp, vp, i32, ctypes.c_float, ctypes.c_float, i32, i32, vp, P(i32),
+                           P(ctypes.c_double), vp]
+    lib.tc_csr_spmv.argtypes = [P(CCsr), vp, vp, vp]
+    lib.tc_handle_info.argtypes = [vp, P(CInfo)]
+    lib.tc_export_format.argtypes = [vp, P(CFormatView)]
+    lib.tc_set_timing.argtypes = [vp, i32]
+    lib.tc_get_timing.argtypes = [vp, P(CTiming)]
+    lib.tc_destroy.argtypes = [vp]
+    lib.tc_destroy.restype = None
+    lib.tc_last_error.argtypes = []
+    lib.tc_last_error.restype = ctypes.c_char_p
+    for f in EXPORTED:
+        if f not in ("tc_build_opts_default", "tc_destroy", "tc_last_error"):
+            getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int, what: str):
+    if st != TC_OK:
+        msg = (load_library().tc_last_error() or b"").decode(errors="replace")
+        cls = NotConverged if st == TC_ENOTCONV else TcError
+        raise cls(st, msg or what)
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev(a, dtype, device) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=dtype)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+    return t.contiguous()
+
+
+class DeviceCsr:
+    """CSR arrays resident on the GPU (row_ptr int64, col int32, val float32)."""
+
+    def __init__(self, csr, device="cuda"):
+        n_rows, n_cols, rp, col, val = csr
+        self.n_rows, self.n_cols = int(n_rows), int(n_cols)
+        self.row_ptr = _dev(rp, torch.int64, device)
+        self.col = _dev(col, torch.int32, device)
+        self.val = _dev(val, torch.float32, device)
+        self.nnz = int(self.col.numel())
+
+    def c(self) -> CCsr:
+        return CCsr(self.n_rows, self.n_cols, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                    self.val.data_ptr())
+
+
+def csr_spmv(A: DeviceCsr, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Plain CSR SpMV (one thread per row) -- the baseline kernel."""
+    lib = load_library()
+    if y is None:
+        y = torch.empty(A.n_rows, dtype=torch.float32, device=x.device)
+    c = A.c()
+    _check(lib.tc_csr_spmv(ctypes.byref(c), _ptr(x), _ptr(y), _stream(stream)), "tc_csr_spmv")
+    return y
+
+
+class TiledMatrix:
+    """A matrix in the tiled composite format (the library handle)."""
+
+    def __init__(self, csr, tile_width: int = 0, n_tiles: int = -1, wl: Optional[Sequence[int] | int] = None,
+                 wave: int = 64, split_len: int = -1, camping_pad: bool = False, relabel: int = -1,
+                 max_act_warp: int = 0, perf_table: Optional[str] = "default", stream=None):
+        lib = load_library()
+        A = csr if isinstance(csr, DeviceCsr) else DeviceCsr(csr)
+        self.n_rows, self.n_cols, self.nnz = A.n_rows, A.n_cols, A.nnz
+        o = CBuildOpts()
+        lib.tc_build_opts_default(ctypes.byref(o))
+        o.tile_width, o.n_tiles, o.wave, o.split_len = tile_width, n_tiles, wave, split_len
+        o.camping_pad, o.relabel, o.max_act_warp = int(camping_pad), relabel, max_act_warp
+        keep = None
+        if wl is None:
+            o.wl_policy = 0
+        elif isinstance(wl, (int, np.integer)):
+            o.wl_policy, o.wl_all = 2, int(wl)
+        else:
+            keep = (ctypes.c_int32 * len(wl))(*[int(v) for v in wl])
+            o.wl_policy, o.wl_per_tile, o.n_wl_per_tile = 1, ctypes.cast(keep, vp), len(wl)
+        if perf_table == "default":
+            perf_table = DEFAULT_PERF_TABLE if os.path.exists(DEFAULT_PERF_TABLE) else None
+        self.perf_table = perf_table
+        o.perf_table = perf_table.encode() if perf_table else None
+        h = vp()
+        c = A.c()
+        _check(lib.tc_build_tiled(ctypes.byref(c), ctypes.byref(o), _stream(stream), ctypes.byref(h)),
+               "tc_build_tiled")
+        self._h = h
+        del keep
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().tc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("handle is closed")
+        return self._h
+
+    # -- queries
+    def info(self) -> dict:
+        inf = CInfo()
+        _check(load_library().tc_handle_info(self.handle, ctypes.byref(inf)), "tc_handle_info")
+        return {name: getattr(inf, name) for name, _ in CInfo._fields_}
+
+    def export_format(self) -> dict:
+        """Host copies of the whole format (keys as the reference builder's)."""
+        inf = self.info()
+        sizes = dict(inf)
+        sizes["n_tiles+1"] = inf["n_tiles"] + 1
+        arrays, view = {}, CFormatView()
+        for name, dt, sz in _VIEW_FIELDS:
+            a = np.zeros(max(int(sizes[sz]), 0), dt)
+            arrays[name] = a
+            setattr(view, name, a.ctypes.data_as(vp) if a.size else None)
+        _check(load_library().tc_export_format(self.handle, ctypes.byref(view)), "tc_export_format")
+        arrays.update(T=inf["n_dense_tiles"], n_tiles_total=inf["n_tiles"], nnz_pad=inf["nnz_pad"],
+                      W=inf["tile_width"], S=inf["wave"], split_len=inf["split_len"],
+                      relabel=bool(inf["relabel"]), n_rows=inf["n_rows"], n_cols=inf["n_cols"])
+        return arrays
+
+    # -- products
+    def spmv(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """y := A x (caller's ids)."""
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=torch.float32, device=x.device)
+        _check(load_library().tc_spmv(self.handle, _ptr(x), _ptr(y), _stream(stream)), "tc_spmv")
+        return y
+
+    def spmv_internal(self, x: torch.Tensor, y: torch.Tensor, stream=None) -> torch.Tensor:
+        _check(load_library().tc_spmv_internal(self.handle, _ptr(x), _ptr(y), _stream(stream)), "tc_spmv_internal")
+        return y
+
+    def spmm(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Y := A X for X (n_cols x k, row-major)."""
+        X = X.contiguous()
+        k = X.shape[1]
+        if Y is None:
+            Y = torch.empty((self.n_rows, k), dtype=torch.float32, device=X.device)
+        _check(load_library().tc_spmm(self.handle, _ptr(X), _ptr(Y), k, _stream(stream)), "tc_spmm")
+        return Y
+
+    # -- drivers
+    def pagerank(self, c: float = 0.85, tol: float = 0.0, max_iter: int = 50, check_every: int = 1,
+                 out: Optional[torch.Tensor] = None, stream=None, raise_not_converged: bool = True):
+        p = out if out is not None else torch.empty(self.n_rows, dtype=torch.float32, device="cuda")
+        it, res = i32(0), ctypes.c_double(0.0)
+        st = load_library().tc_pagerank(self.handle, c, tol, max_iter, check_every, _ptr(p), ctypes.byref(it),
+                                        ctypes.byref(res), _stream(stream))
+        if st != TC_ENOTCONV or raise_not_converged:
+            _check(st, "tc_pagerank")
+        return p, it.value, res.value
+
+    def hits(self, tol: float = 0.0, max_iter: int = 50, check_every: int = 1, stream=None):
+        n = self.n_rows // 2
+        a = torch.empty(n, dtype=torch.float32, device="cuda")
+        h = torch.empty(n, dtype=torch.float32, device="cuda")
+        it, res = i32(0), ctypes.c_double(0.0)
+        _check(load_library().tc_hits(self.handle, tol, max_iter, check_every, _ptr(a), _ptr(h), ctypes.byref(it),
+                                      ctypes.byref(res), _stream(stream)), "tc_hits")
+        return a, h, it.value, res.value
+
+    def rwr(self, seeds, c: float = 0.85, tol: float = 0.0, max_iter: int = 30, check_every: int = 1,
+            stream=None):
+        s = np.ascontiguousarray(seeds, np.int32)
+        k = len(s)
+        R = torch.empty((self.n_rows, k), dtype=torch.float32, device="cuda")
+        it, res = i32(0), ctypes.c_double(0.0)
+        _check(load_library().tc_rwr(self.handle, s.ctypes.data_as(vp), k, c, tol, max_iter, check_every, _ptr(R),
+                                     ctypes.byref(it), ctypes.byref(res), _stream(stream)), "tc_rwr")
+        return R, it.value, res.value
+
+    # -- timing of the tile kernels
+    def set_timing(self, enable: bool):
+        _check(load_library().tc_set_timing(self.handle, int(enable)), "tc_set_timing")
+
+    def get_timing(self) -> dict:
+        t = CTiming()
+        _check(load_library().tc_get_timing(self.handle, ctypes.byref(t)), "tc_get_timing")
+        return {"tile_kernel_ms": t.tile_kernel_ms, "tile_launches": t.tile_launches, "spmv_calls": t.spmv_calls}
+
+
+def build_tiled(csr, **opts) -> TiledMatrix:
+    return TiledMatrix(csr, **opts)

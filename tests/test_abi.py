@@ -1,0 +1,48 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no GPU work: symbol lookup only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tcspmv.h")
+LIB = os.path.join(ROOT, "paper_1103_2405_amd", "libtcspmv.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("tc_build_tiled", "tc_spmv", "tc_spmm", "tc_pagerank", "tc_hits", "tc_rwr", "tc_export_format",
+              "tc_handle_info", "tc_destroy", "tc_last_error", "tc_csr_spmv"):
+        assert f in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run python -m paper_1103_2405_amd.build)")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_knows_every_symbol():
+    from paper_1103_2405_amd import tc
+    assert set(tc.EXPORTED) == set(declared_functions())
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_null_arguments_rejected_without_gpu_work():
+    from paper_1103_2405_amd import tc
+    lib = tc.load_library()
+    assert lib.tc_build_tiled(None, None, None, None) == tc.TC_EINVAL
+    assert b"NULL" in lib.tc_last_error()
+    assert lib.tc_handle_info(None, None) == tc.TC_EINVAL
+    assert lib.tc_spmv(None, None, None, None) == tc.TC_EINVAL
+    lib.tc_destroy(None)

@@ -1,0 +1,278 @@
+"""GPU parity: the HIP library against the oracle, through the C ABI.
+
+  format   every metadata array, every packed index and every packed value
+           bit-exact against the reference builder
+  SpMV     |y - y_ref|_i <= 1e-5 (|A| |x|)_i per entry (FP64 oracle), and
+           bit-exact on dyadic inputs (every order of summation is exact)
+  drivers  L1 distance of iterates at equal iteration counts <= 1e-6
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from oracle import ref_format as rf
+from oracle.autotune import PerfTable
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on a GPU machine only
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1103_2405_amd import TcError, TiledMatrix, DeviceCsr, csr_spmv  # noqa: E402
+from paper_1103_2405_amd import tc as tcmod  # noqa: E402
+
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+FMT_KEYS = ["cperm", "rowmap", "tile_col_begin", "tile_col_end", "tile_nnz", "tile_wl", "tile_row_off",
+            "rows_sorted", "rows_len", "wl_tile", "wl_layout", "wl_w", "wl_w_pad", "wl_h_pad", "wl_row_begin",
+            "wl_n_rows", "wl_chunk", "wl_n_chunks", "wl_data_off", "wl_rowid_off", "idx", "rowid"]
+
+
+def assert_same_format(g, r):
+    assert g["T"] == r["T"] and g["n_tiles_total"] == r["n_tiles_total"] and g["nnz_pad"] == r["nnz_pad"]
+    for k in FMT_KEYS:
+        a, b = np.asarray(g[k]), np.asarray(r[k])
+        assert a.shape == b.shape, (k, a.shape, b.shape)
+        assert np.array_equal(a.astype(np.int64), b.astype(np.int64)), k
+    assert np.array_equal(g["val"].view(np.uint32), r["val"].view(np.uint32)), "val"
+
+
+def build_both(csr, W, wl=None, S=64, split_len=8192, n_tiles=-1, camping_pad=False, table_path=None,
+               max_act_warp=8192):
+    say("build", csr[0], csr[1], len(csr[3]), "W", W, "wl", wl if not isinstance(wl, list) else wl[:3], "S", S,
+        "split", split_len)
+    wl_list = wl if wl is None or isinstance(wl, list) else [wl] * 4096
+    ref = rf.build(csr, W=W, n_tiles=n_tiles, wl=wl_list, S=S, split_len=split_len, camping_pad=camping_pad,
+                   table=PerfTable.load(table_path) if table_path else None, max_act_warp=max_act_warp)
+    gm = TiledMatrix(csr, tile_width=W, n_tiles=n_tiles, wl=wl, wave=S, split_len=split_len,
+                     camping_pad=camping_pad, perf_table=table_path, max_act_warp=max_act_warp)
+    return gm, ref
+
+
+def check_spmv(gm, csr, x, exact=False):
+    xt = torch.from_numpy(x).cuda()
+    y = gm.spmv(xt).cpu().numpy().astype(np.float64)
+    ref = oracle.spmv(csr, x)
+    if exact:
+        assert np.array_equal(y, ref)
+        return
+    bound = TOL * oracle.absmv(csr, x)
+    err = np.abs(y - ref)
+    bad = np.flatnonzero(err > bound)
+    assert bad.size == 0, (bad[:10], err[bad[:10]], bound[bad[:10]])
+
+
+# ------------------------------------------------------------------ format
+def test_format_figure1_example():
+    from test_ref_format import load_fig1
+    csr, p, expect = load_fig1()
+    gm, ref = build_both(csr, W=p["W"], wl=[p["WL"]] * 3, S=p["S"], split_len=0)
+    assert_same_format(gm.export_format(), ref)
+    check_spmv(gm, csr, np.arange(1, 9, dtype=np.float32), exact=True)
+
+
+@pytest.mark.parametrize("seed,n,density,W,wl,S,split", [
+    (0, 300, 0.03, 16, 64, 64, 0),
+    (1, 300, 0.03, 7, 12, 4, 0),
+    (2, 500, 0.02, 32, 200, 64, 40),
+    (3, 200, 0.05, 5, 3, 2, 6),
+    (4, 1000, 0.01, 100, 500, 64, 100),
+    (5, 2000, 0.005, 256, 1000, 64, 64),
+])
+def test_format_bit_exact_small(seed, n, density, W, wl, S, split):
+    csr = gg.random_csr(n, n, density, seed, power=1.1)
+    gm, ref = build_both(csr, W=W, wl=wl, S=S, split_len=split)
+    assert_same_format(gm.export_format(), ref)
+
+
+def test_format_rectangular_and_camping_pad():
+    csr = gg.random_csr(300, 900, 0.01, 7, power=1.0)
+    gm, ref = build_both(csr, W=64, wl=256, S=64, split_len=32, camping_pad=True)
+    g = gm.export_format()
+    assert not g["relabel"]
+    assert_same_format(g, ref)
+    check_spmv(gm, csr, gg.uniform_f32(900, 1))
+
+
+def test_format_rmat14_several_tiles():
+    g = gg.rmat(14, 16, seed=14)
+    csr = gg.pagerank_matrix(g)
+    for W, wl, split in [(1024, 2048, 512), (4096, 512, 8192), (1 << 14, 4096, 256)]:
+        gm, ref = build_both(csr, W=W, wl=wl, split_len=split)
+        assert_same_format(gm.export_format(), ref)
+        check_spmv(gm, csr, gg.uniform_f32(g.n, 101))
+
+
+def _write_table(path):
+    # a synthetic table (not measured): favours wide rows and tall columns
+    with open(path, "w") as f:
+        for kind, scale in (("dense", 1.0), ("sparse", 0.8)):
+            for lw in range(16):
+                for lh in range(16):
+                    w, h = 2 ** lw, 2 ** lh
+                    v = int(1e6 * scale * (w * h) / (w * h + 512 + 40 * min(w, h)))
+                    f.write("%s %d %d %d\n" % (kind, lw, lh, max(v, 1)))
+
+
+def test_autotuned_workload_sizes_match_reference(tmp_path):
+    path = str(tmp_path / "table.txt")
+    _write_table(path)
+    g = gg.rmat(13, 16, seed=3)
+    csr = gg.pagerank_matrix(g)
+    gm, ref = build_both(csr, W=1024, wl=None, split_len=1024, table_path=path, max_act_warp=64)
+    fmt = gm.export_format()
+    assert list(fmt["tile_wl"]) == list(ref["tile_wl"])
+    assert len(set(ref["tile_wl"])) > 1
+    assert_same_format(fmt, ref)
+    check_spmv(gm, csr, gg.uniform_f32(g.n, 5))
+
+
+# ------------------------------------------------------------------- SpMV
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_spmv_dyadic_bit_exact(seed):
+    csr = gg.random_csr(3000, 3000, 0.004, seed, values="dyadic", power=1.2)
+    x = ((np.arange(3000) * 7 + seed) % 7 - 3).astype(np.float32)
+    gm = TiledMatrix(csr, tile_width=256, wl=300, split_len=16)
+    check_spmv(gm, csr, x, exact=True)
+
+
+def test_spmv_rmat14_default_options():
+    g = gg.rmat(14, 16, seed=14)
+    csr = gg.pagerank_matrix(g)
+    gm = TiledMatrix(csr)
+    say(gm.info())
+    check_spmv(gm, csr, gg.uniform_f32(g.n, 101))
+
+
+def test_spmv_signed_values_and_ragged_tiles():
+    csr = gg.random_csr(5000, 4000, 0.003, 9, power=1.3)
+    n_rows, n_cols, rp, col, val = csr
+    val = (val - 0.5).astype(np.float32)
+    csr = (n_rows, n_cols, rp, col, val)
+    x = (gg.uniform_f32(n_cols, 2) * 2 - 1).astype(np.float32)
+    for W in (100, 999, 4000):
+        check_spmv(TiledMatrix(csr, tile_width=W, wl=256, split_len=64), csr, x)
+
+
+def test_spmm_matches_oracle():
+    g = gg.rmat(12, 16, seed=4)
+    csr = gg.rwr_matrix(g)
+    gm = TiledMatrix(csr, tile_width=512, wl=1024, split_len=256)
+    for k in (1, 3, 8, 13):
+        X = np.stack([gg.uniform_f32(g.n, 10 + q) for q in range(k)], axis=1)
+        Y = gm.spmm(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+        ref = oracle.spmm(csr, X)
+        bound = TOL * oracle.spmm((csr[0], csr[1], csr[2], csr[3], np.abs(csr[4])), np.abs(X))
+        assert np.all(np.abs(Y - ref) <= bound), k
+
+
+def test_csr_baseline_matches_oracle():
+    g = gg.rmat(14, 16, seed=14)
+    csr = gg.pagerank_matrix(g)
+    x = gg.uniform_f32(g.n, 101)
+    y = csr_spmv(DeviceCsr(csr), torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(y - oracle.spmv(csr, x)) <= TOL * oracle.absmv(csr, x))
+
+
+# ------------------------------------------------------------ edge cases
+def test_empty_and_tiny_matrices():
+    # no entries at all
+    csr = (5, 7, np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    gm = TiledMatrix(csr, tile_width=4)
+    y = gm.spmv(torch.ones(7, device="cuda"))
+    assert torch.all(y == 0)
+    # 1 x 1
+    csr = (1, 1, np.array([0, 1], np.int64), np.array([0], np.int32), np.array([2.5], np.float32))
+    gm = TiledMatrix(csr, tile_width=1)
+    assert gm.spmv(torch.full((1,), 2.0, device="cuda")).item() == 5.0
+    # a single dense row (one heavy row split into many chunks)
+    n = 20000
+    csr = (3, n, np.array([0, 0, n, n], np.int64), np.arange(n, dtype=np.int32), gg.uniform_f32(n, 3))
+    check_spmv(TiledMatrix(csr, tile_width=4096, split_len=1000), csr, gg.uniform_f32(n, 4))
+
+
+def test_invalid_csr_rejected():
+    bad_rp = (3, 3, np.array([0, 2, 1, 3], np.int64), np.array([0, 1, 2], np.int32), np.ones(3, np.float32))
+    with pytest.raises(TcError) as e:
+        TiledMatrix(bad_rp)
+    assert e.value.status == tcmod.TC_EINVAL
+    bad_col = (2, 2, np.array([0, 1, 2], np.int64), np.array([0, 2], np.int32), np.ones(2, np.float32))
+    with pytest.raises(TcError) as e:
+        TiledMatrix(bad_col)
+    assert e.value.status == tcmod.TC_EINVAL
+    bad_end = (2, 2, np.array([0, 1, 1], np.int64), np.array([0, 1], np.int32), np.ones(2, np.float32))
+    with pytest.raises(TcError):
+        TiledMatrix(bad_end)
+
+
+def test_aliasing_rejected():
+    csr = gg.random_csr(50, 50, 0.1, 1)
+    gm = TiledMatrix(csr, tile_width=16)
+    x = torch.ones(50, device="cuda")
+    with pytest.raises(TcError):
+        gm.spmv(x, x)
+
+
+# ---------------------------------------------------------------- drivers
+def test_pagerank_rmat14_50_iterations():
+    g = gg.rmat(14, 16, seed=14)
+    csr = gg.pagerank_matrix(g)
+    gm = TiledMatrix(csr)
+    p, it, res = gm.pagerank(0.85, 0.0, 50)
+    pref, _, rref = oracle.pagerank(csr, 0.85, 0.0, 50)
+    assert it == 50
+    d = np.abs(p.cpu().numpy().astype(np.float64) - pref).sum()
+    say("pagerank L1 diff", d, "resid", res, rref[-1])
+    assert d <= 1e-6
+    assert abs(res - rref[-1]) <= 1e-6
+
+
+def test_pagerank_converges_to_tolerance():
+    g = gg.rmat(12, 16, seed=1)
+    csr = gg.pagerank_matrix(g)
+    gm = TiledMatrix(csr, tile_width=256)
+    p, it, res = gm.pagerank(0.85, 1e-6, 500, check_every=5)
+    assert res <= 1e-6 and it % 5 == 0
+    pref, itr, _ = oracle.pagerank(csr, 0.85, 0.0, it)
+    assert np.abs(p.cpu().numpy() - pref).sum() <= 1e-6
+    with pytest.raises(tcmod.NotConverged):
+        gm.pagerank(0.85, 1e-12, 3)
+
+
+def test_hits_matches_oracle():
+    g = gg.rmat(12, 16, seed=7)
+    csr = gg.hits_matrix(g)
+    gm = TiledMatrix(csr, tile_width=1024)
+    a, h, it, res = gm.hits(0.0, 30)
+    x, _, rref = oracle.hits(csr, 0.0, 30)
+    n = g.n
+    d = np.abs(a.cpu().numpy() - x[:n]).sum() + np.abs(h.cpu().numpy() - x[n:]).sum()
+    say("hits L1 diff", d)
+    assert d <= 1e-6
+    empty = gg.hits_matrix(gg.from_edges(4, [], []))
+    with pytest.raises(TcError):
+        TiledMatrix(empty).hits(0.0, 2)
+
+
+def test_rwr_matches_oracle():
+    g = gg.rmat(12, 16, seed=8)
+    csr = gg.rwr_matrix(g)
+    gm = TiledMatrix(csr, tile_width=1024)
+    seeds = gg.rwr_seeds(g, 5, 40)
+    for k in (1, 5):
+        R, it, res = gm.rwr(seeds[:k], 0.85, 0.0, 30)
+        Rref, _, rr = oracle.rwr(csr, seeds[:k], 0.85, 0.0, 30)
+        d = np.abs(R.cpu().numpy() - Rref).sum(axis=0)
+        say("rwr L1 diff per column", d)
+        assert np.all(d <= 1e-6)
