@@ -65,7 +65,8 @@ typedef struct {
 
 /* Build options (tc_build_opts_default fills the defaults). */
 typedef struct {
-  int32_t tile_width;         /* W, columns per dense tile (Solution 1); 0 = library default */
+  int32_t tile_width;         /* W, columns per dense tile (Solution 1); 0 = 2^23 (32 MB of x,
+                                 measured best on MI355X for power-law graphs up to 2^23 nodes) */
   int32_t n_tiles;            /* -1: Algorithm 1 decides; >= 0: that many dense tiles (clipped) */
   int32_t wl_policy;          /* 0: Algorithm 2 per tile; 1: wl_per_tile; 2: wl_all for every tile */
   int32_t wl_all;             /* workload size for wl_policy 2 */
@@ -75,7 +76,9 @@ typedef struct {
   int32_t wave;               /* padding multiple S of workloads; 0 = 64 (the wavefront width) */
   int32_t split_len;          /* rows longer than this many entries in a tile are split
                                  across wavefronts in chunks of this size; 0 = never
-                                 (the paper's rule); -1 = default 8192 */
+                                 (the paper's rule); -1 = automatic per tile (default):
+                                 the tile's nnz per resident wavefront, rounded up to a
+                                 multiple of the wave width, within [wave, 8192] */
   int32_t camping_pad;        /* 1: 64 pad elements after workloads whose size is a multiple
                                  of 512 (Solution 3, partition camping); default 0 */
   int32_t relabel;            /* -1: relabel rows like columns when square; 0: keep row ids */
@@ -90,7 +93,7 @@ typedef struct {
 /* Sizes and parameters of a built handle (host struct filled by tc_handle_info). */
 typedef struct {
   int64_t n_rows, n_cols, nnz;
-  int32_t tile_width, wave, split_len, relabel;
+  int32_t tile_width, wave, split_len, relabel;  /* split_len as given (-1 = automatic) */
   int32_t n_dense_tiles;      /* T of Algorithm 1 */
   int32_t n_tiles;            /* T plus one if a sparse tile exists */
   int64_t n_workloads;
@@ -113,6 +116,7 @@ typedef struct {
   int64_t* tile_col_end;      /* [n_tiles] one past the last */
   int64_t* tile_nnz;          /* [n_tiles] */
   int64_t* tile_wl;           /* [n_tiles] workload size used */
+  int64_t* tile_split;        /* [n_tiles] split length used (0 = none) */
   int64_t* tile_row_off;      /* [n_tiles + 1] offsets into rows_sorted */
   int32_t* rows_sorted;       /* [n_rows_sorted] each tile's rows by decreasing length */
   int32_t* rows_len;          /* [n_rows_sorted] the row's entries in that tile */
@@ -149,8 +153,8 @@ void tc_build_opts_default(tc_build_opts* opts);
  * owns all its device memory; A may be freed once this call returns.
  * Synchronises `stream`.  Errors: TC_EINVAL for a NULL argument, negative
  * sizes, a non-monotone row_ptr, row_ptr[n_rows] != nnz, a column id out of
- * range or an unusable option; TC_EUNSUPPORTED for nnz >= 2^31 or sizes that
- * do not fit 32-bit ids; TC_ENOMEM; TC_EHIP. */
+ * range or an unusable option; TC_EUNSUPPORTED for nnz >= 2^31, n_rows >= 2^30 or
+ * n_cols >= 2^31 - 1; TC_ENOMEM; TC_EHIP. */
 tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, tc_stream_t stream,
                          tc_handle** out);
 

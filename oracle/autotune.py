@@ -21,7 +21,10 @@ its mean throughput (Eq. 3) and the tile's time is the sum over rounds (Eq. 2).
 Readings where the paper is silent (each also listed in the design notes):
   * heavy rows longer than split_len are cut into chunks of split_len entries
     (one-row row-major workloads) and do not take part in the WL bounds; the
-    lower bound is the first row that is not split;
+    lower bound is the first row that is not split.  With the automatic rule a
+    tile's split length is its nnz divided by the number of resident
+    wavefronts, rounded up to a multiple of S and kept in [S, 8192]
+    (`tile_split_len`), so that no row is longer than one wavefront's share;
   * h = max(1, floor(WL / w)); a column-major workload then takes
     ceil(h / S) * S real rows when that many remain;
   * the throughput table is a full grid over powers of two of w and h; a shape
@@ -169,6 +172,19 @@ def choose_wl(lengths: Sequence[int], tile_nnz: int, table: PerfTable, kind: str
             best = wl
         wl += low
     return best
+
+
+SPLIT_CAP = 8192
+
+
+def tile_split_len(split_len: int, tile_nnz: int, max_act_warp: int, S: int) -> int:
+    """Split length used for one tile: -1 = automatic (per-wavefront share of
+    the tile, rounded up to a multiple of S, within [S, 8192]); 0 = no split;
+    otherwise the given length."""
+    if split_len >= 0:
+        return split_len
+    share = -(-tile_nnz // max_act_warp)
+    return min(SPLIT_CAP, max(S, ceil_to(share, S)))
 
 
 def count_tiles(clen_sorted: np.ndarray, W: int) -> int:

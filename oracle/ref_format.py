@@ -27,11 +27,11 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-from .autotune import RM, CM, PerfTable, choose_wl, count_tiles, partition_rows
+from .autotune import RM, CM, PerfTable, choose_wl, count_tiles, partition_rows, tile_split_len
 
 
 def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S: int = 64,
-          split_len: int = 8192, camping_pad: bool = False, relabel: Optional[bool] = None,
+          split_len: int = -1, camping_pad: bool = False, relabel: Optional[bool] = None,
           table: Optional[PerfTable] = None, max_act_warp: int = 8192) -> dict:
     n_rows, n_cols, rp, col, val = csr
     rp = np.asarray(rp, np.int64)
@@ -69,7 +69,7 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
 
     tile_row_off = [0]
     rows_sorted, rows_len = [], []
-    wl_used = []
+    wl_used, split_used = [], []
     W_ = {k: [] for k in ("tile", "layout", "w", "w_pad", "h_pad", "row_begin", "n_rows",
                           "chunk", "n_chunks")}
     seg_lists = []  # per tile: (sorted segment starts into `order`, lengths)
@@ -92,14 +92,16 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
         seg_lists.append((tstart[t] + sstart, slen, srow))
         # a6: workload size and partition
         kind = "dense" if t < T else "sparse"
+        split_t = tile_split_len(split_len, int(tcount[t]), max_act_warp, S)
+        split_used.append(split_t)
         if wl is not None:
             WLt = int(wl[t])
         elif table is not None:
-            WLt = choose_wl(slen.tolist(), int(tcount[t]), table, kind, max_act_warp, S, split_len)
+            WLt = choose_wl(slen.tolist(), int(tcount[t]), table, kind, max_act_warp, S, split_t)
         else:
             raise ValueError("give wl or a table")
         wl_used.append(WLt)
-        for p in partition_rows(slen.tolist(), WLt, S, split_len):
+        for p in partition_rows(slen.tolist(), WLt, S, split_t):
             layout, w, w_pad, h_pad, rb, nr, ch, nch = p
             for k, v in zip(("tile", "layout", "w", "w_pad", "h_pad", "row_begin", "n_rows",
                              "chunk", "n_chunks"),
@@ -133,7 +135,7 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
         ro = int(rowid_off[j])
         if ch >= 0:
             s0 = int(seg_start_all[rb])
-            c0 = ch * split_len
+            c0 = ch * split_used[int(wlarr["tile"][j])]
             cw = int(wlarr["w"][j])
             src = order[s0 + c0: s0 + c0 + cw]
             idx_out[off:off + cw] = cpos[col[src]]
@@ -155,6 +157,7 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
 
     return dict(
         n_rows=n_rows, n_cols=n_cols, nnz=nnz, W=W, S=S, split_len=split_len, T=T,
+        tile_split=np.asarray(split_used, np.int64),
         n_tiles_total=ntiles, relabel=bool(relabel),
         clen=clen, cperm=cperm.astype(np.int32), cpos=cpos.astype(np.int32),
         rowmap=rmap.astype(np.int32),

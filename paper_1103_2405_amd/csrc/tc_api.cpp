@@ -70,6 +70,9 @@ extern "C" tc_status tc_export_format(const tc_handle* h, tc_format_view* v) {
   chk(d2h(v->idx, h->d_idx, h->nnz_pad));
   chk(d2h(v->val, h->d_val, h->nnz_pad));
   chk(d2h(v->rowid, h->d_rowid, h->n_rowid));
+  if (v->rowid)  // the first-writer flag is an implementation detail of the kernels
+    for (int64_t k = 0; k < h->n_rowid; ++k)
+      if (v->rowid[k] >= 0) v->rowid[k] &= ~kAddFlag;
   if (e != hipSuccess) {
     set_error(std::string("tc_export_format: ") + hipGetErrorString(e));
     return TC_EHIP;
@@ -79,6 +82,7 @@ extern "C" tc_status tc_export_format(const tc_handle* h, tc_format_view* v) {
     if (v->tile_col_end) v->tile_col_end[t] = h->tile_col_end[t];
     if (v->tile_nnz) v->tile_nnz[t] = h->tile_nnz[t];
     if (v->tile_wl) v->tile_wl[t] = h->tile_wl[t];
+    if (v->tile_split) v->tile_split[t] = h->tile_split[t];
   }
   if (v->tile_row_off)
     for (int t = 0; t <= h->n_tiles; ++t) v->tile_row_off[t] = h->tile_row_off.empty() ? 0 : h->tile_row_off[t];

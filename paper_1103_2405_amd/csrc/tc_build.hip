@@ -298,10 +298,33 @@ __global__ void k_run_emit(const int32_t* __restrict__ flags, const int32_t* __r
   }
 }
 
+// first tile in which each row sits in a workload that is not a split chunk
+__global__ void k_first_touch(const int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_len,
+                              const int32_t* __restrict__ seg_row, int64_t nseg, const int64_t* __restrict__ split_t,
+                              int32_t* __restrict__ first, int32_t* __restrict__ touched) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  const int32_t t = seg_tile[s], r = seg_row[s];
+  touched[r] = 1;
+  const int64_t sp = split_t[t];
+  if (!(sp > 0 && (int64_t)seg_len[s] > sp)) atomicMin(&first[r], t);
+}
+
+__global__ void k_not(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] ? 0 : 1;
+}
+
+__global__ void k_compact_idx(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos, int64_t n,
+                              int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flags[i]) out[pos[i]] = (int32_t)i;
+}
+
 struct PackWl {
   int64_t data_off, rowid_off;
   int32_t w_pad, h_pad, n_rows, layout;
-  int32_t row_begin, chunk, tile_first, extra;
+  int32_t row_begin, chunk_off, chunk_len, tile_first, extra, tile;
 };
 
 // a7: one wavefront per workload writes its rectangle, its pads and row ids.
@@ -310,18 +333,17 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
                                              const int32_t* __restrict__ rows_len,
                                              const int32_t* __restrict__ rows_sorted,
                                              const int32_t* __restrict__ b_icol, const float* __restrict__ b_val,
-                                             int32_t split_len, int32_t* __restrict__ idx, float* __restrict__ val,
-                                             int32_t* __restrict__ rowid) {
+                                             const int32_t* __restrict__ first, int32_t* __restrict__ idx,
+                                             float* __restrict__ val, int32_t* __restrict__ rowid) {
   const int lane = lane_id();
   const int64_t j = (int64_t)blockIdx.x * (kB / kWave) + threadIdx.x / kWave;
   if (j >= n_wl) return;
   const PackWl d = wls[j];
   const int64_t off = d.data_off;
-  if (d.chunk >= 0) {
+  if (d.chunk_off >= 0) {
     const int32_t s = d.row_begin;
-    const int64_t c0 = (int64_t)d.chunk * split_len;
-    const int64_t st = (int64_t)srt_start[s] + c0;
-    const int64_t L = min((int64_t)split_len, (int64_t)rows_len[s] - c0);
+    const int64_t st = (int64_t)srt_start[s] + d.chunk_off;
+    const int64_t L = d.chunk_len;
     for (int64_t c = lane; c < d.w_pad; c += kWave) {
       const bool real = c < L;
       idx[off + c] = real ? b_icol[st + c] : d.tile_first;
@@ -339,7 +361,10 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
         idx[base + c] = real ? b_icol[st + c] : d.tile_first;
         val[base + c] = real ? b_val[st + c] : 0.0f;
       }
-      if (lane == 0) rowid[d.rowid_off + r] = rows_sorted[s];
+      if (lane == 0) {
+        const int32_t row = rows_sorted[s];
+        rowid[d.rowid_off + r] = row | (first[row] == d.tile ? 0 : kAddFlag);
+      }
     }
   } else {
     for (int32_t r = lane; r < d.h_pad; r += kWave) {
@@ -351,7 +376,7 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
         L = rows_len[s];
         row = rows_sorted[s];
       }
-      rowid[d.rowid_off + r] = row;
+      rowid[d.rowid_off + r] = row < 0 ? row : (row | (first[row] == d.tile ? 0 : kAddFlag));
       for (int32_t c = 0; c < d.w_pad; ++c) {
         const int64_t e = off + (int64_t)c * d.h_pad + r;
         const bool real = c < L;
@@ -613,6 +638,18 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   }
   h->tile_nnz.resize(ntiles);
   for (int t = 0; t < ntiles; ++t) h->tile_nnz[t] = tstart[t + 1] - tstart[t];
+  h->tile_split.assign(ntiles, 0);
+  for (int t = 0; t < ntiles; ++t) h->tile_split[t] = tile_split_len(h->split_len, h->tile_nnz[t], h->max_act_warp, h->S);
+  int64_t* d_split_t = tmp.get<int64_t>(ntiles);
+  if (ntiles > 0)
+    HIPX(hipMemcpyAsync(d_split_t, h->tile_split.data(), sizeof(int64_t) * ntiles, hipMemcpyHostToDevice, st));
+  int32_t* first = tmp.get<int32_t>(n_rows);
+  int32_t* touched = tmp.get<int32_t>(n_rows);
+  if (n_rows > 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, first, n_rows, (int32_t)0x7fffffff);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, touched, n_rows, (int32_t)0);
+    HIPX(hipGetLastError());
+  }
 
   // ---- a5: segments (tile, row) and their sort by decreasing length
   int64_t nseg = 0;
@@ -637,6 +674,9 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipGetLastError());
     tmp.release(flags);
     tmp.release(pos);
+    hipLaunchKernelGGL(k_first_touch, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg,
+                       (const int64_t*)d_split_t, first, touched);
+    HIPX(hipGetLastError());
     const int32_t maxlen = dev_max(seg_len, nseg, tmp, st);
     const int lb = bits_for((uint64_t)maxlen);
     const int rb = bits_for((uint64_t)(n_rows > 1 ? n_rows - 1 : 0));
@@ -706,6 +746,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       runs.push_back(LenRun{run_len[ri], end - run_pos[ri]});
       ++ri;
     }
+    const int64_t split_t = h->tile_split[t];
+    pp.split_len = (int32_t)split_t;
     int64_t WLt;
     if (o->wl_policy == 1) {
       if (t >= o->n_wl_per_tile) throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
@@ -742,6 +784,17 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipMemcpyAsync(chunk_row.data(), d_r, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
   }
+  std::vector<int32_t> chunk_first(chunk_wl.size());
+  if (!chunk_wl.empty()) {
+    const int64_t nc = (int64_t)chunk_wl.size();
+    int32_t* d_at = tmp.get<int32_t>(nc);
+    int32_t* d_r = tmp.get<int32_t>(nc);
+    HIPX(hipMemcpyAsync(d_at, chunk_row.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gather_i32, dim3(nblk(nc, kB)), dim3(kB), 0, st, first, d_at, nc, d_r);
+    HIPX(hipGetLastError());
+    HIPX(hipMemcpyAsync(chunk_first.data(), d_r, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+  }
   std::vector<size_t> ord(chunk_wl.size());
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return chunk_row[a] < chunk_row[b]; });
@@ -750,7 +803,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   for (size_t q = 0; q < ord.size(); ++q) {
     slot_of[ord[q]] = (int32_t)q;
     if (q == 0 || chunk_row[ord[q]] != chunk_row[ord[q - 1]])
-      srows.push_back(SplitRow{chunk_row[ord[q]], (int32_t)q, 0, 0});
+      srows.push_back(SplitRow{chunk_row[ord[q]], (int32_t)q, 0, chunk_first[ord[q]] == 0x7fffffff ? 1 : 0});
     srows.back().n_slots++;
   }
   h->n_slots = (int64_t)chunk_wl.size();
@@ -770,8 +823,9 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     int32_t info = w.layout;
     if (w.chunk >= 0) info = kChunk | (slot_of[cq++] << 2);
     dwl[j] = Wl{doff, roff, w.w_pad, w.h_pad, w.n_rows, info};
-    pwl[j] = PackWl{doff, roff, w.w_pad, w.h_pad, w.n_rows, w.layout, w.row_begin, w.chunk,
-                    (int32_t)h->tile_col_begin[w.tile], extra};
+    const int32_t coff = w.chunk >= 0 ? (int32_t)(w.chunk * h->tile_split[w.tile]) : -1;
+    pwl[j] = PackWl{doff, roff, w.w_pad, w.h_pad, w.n_rows, w.layout, w.row_begin, coff, w.w,
+                    (int32_t)h->tile_col_begin[w.tile], extra, w.tile};
     doff += area + extra;
     roff += w.h_pad;
   }
@@ -789,7 +843,19 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipMemcpyAsync(d_pwl, pwl.data(), sizeof(PackWl) * nwl, hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(h->d_wl, dwl.data(), sizeof(Wl) * nwl, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_pack, dim3(nblk(nwl, kB / kWave)), dim3(kB), 0, st, d_pwl, nwl, srt_start, rows_len,
-                       rows_sorted, b_icol, b_val, h->split_len, h->d_idx, h->d_val, h->d_rowid);
+                       rows_sorted, b_icol, b_val, (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid);
+    HIPX(hipGetLastError());
+  }
+  // rows without any entry: every product writes their zero
+  if (n_rows > 0) {
+    int32_t* ef = tmp.get<int32_t>(n_rows);
+    int32_t* ep = tmp.get<int32_t>(n_rows);
+    hipLaunchKernelGGL(k_not, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, (const int32_t*)touched, n_rows, ef);
+    HIPX(hipGetLastError());
+    h->n_empty = excl_scan<int32_t, int32_t>(ef, n_rows, ep, tmp, st);
+    h->d_empty = hold<int32_t>(h, h->n_empty);
+    hipLaunchKernelGGL(k_compact_idx, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, (const int32_t*)ef,
+                       (const int32_t*)ep, n_rows, h->d_empty);
     HIPX(hipGetLastError());
   }
   h->d_split = hold<SplitRow>(h, (int64_t)srows.size());
@@ -799,6 +865,13 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->d_xbuf = hold<float>(h, std::max(n_rows, n_cols));
   h->d_ybuf = hold<float>(h, std::max(n_rows, n_cols));
   h->d_red = hold<double>(h, 4096);
+  h->d_counters = hold<unsigned long long>(h, std::max<int64_t>(ntiles, 1));
+  {
+    int dev = 0, cus = 0;
+    HIPX(hipGetDevice(&dev));
+    HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    h->n_cu = cus > 0 ? cus : 256;
+  }
   HIPX(hipStreamSynchronize(st));
 }
 
@@ -832,8 +905,8 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
     set_error("tc_build_tiled: negative size");
     return TC_EINVAL;
   }
-  if (A->nnz >= ((int64_t)1 << 31) || A->n_rows >= ((int64_t)1 << 31) - 1 || A->n_cols >= ((int64_t)1 << 31) - 1) {
-    set_error("tc_build_tiled: sizes must fit 32-bit ids (nnz < 2^31)");
+  if (A->nnz >= ((int64_t)1 << 31) || A->n_rows >= ((int64_t)1 << 30) || A->n_cols >= ((int64_t)1 << 31) - 1) {
+    set_error("tc_build_tiled: sizes must fit 32-bit ids (nnz < 2^31, n_rows < 2^30)");
     return TC_EUNSUPPORTED;
   }
   if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val))) {
@@ -853,9 +926,9 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   h->n_rows = A->n_rows;
   h->n_cols = A->n_cols;
   h->nnz = A->nnz;
-  h->W = o->tile_width > 0 ? o->tile_width : (1 << 20);
+  h->W = o->tile_width > 0 ? o->tile_width : (1 << 23);
   h->S = o->wave > 0 ? o->wave : 64;
-  h->split_len = o->split_len < 0 ? 8192 : o->split_len;
+  h->split_len = o->split_len < 0 ? -1 : o->split_len;
   h->camping_pad = o->camping_pad != 0;
   h->relabel = o->relabel < 0 ? (A->n_rows == A->n_cols) : (o->relabel != 0);
   h->max_act_warp = o->max_act_warp > 0 ? o->max_act_warp : 8192;

@@ -8,11 +8,16 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tcspmv.h"
+#include "tcspmv.h"
 
 namespace tc {
 
 constexpr int kWave = 64;
+
+// Row ids stored in `rowid` carry bit 30 when an earlier tile already wrote
+// that row of y (the tile adds); without it the tile is the row's first
+// writer and stores.  Rows are therefore limited to 2^30.
+constexpr int32_t kAddFlag = 1 << 30;
 
 // Workload layouts (Solution 3): row-major rectangles run one row at a time
 // across the wavefront, column-major ones give each lane its own row; a chunk
@@ -35,7 +40,7 @@ struct SplitRow {
   int32_t row;        // internal row id
   int32_t slot_begin; // first partial slot
   int32_t n_slots;    // chunks over all tiles, in (tile, chunk) order
-  int32_t pad_;
+  int32_t store;      // 1: no tile wrote the row, so the sum is stored, not added
 };
 
 // Host-side workload record (also what the format export returns).
@@ -72,6 +77,10 @@ int64_t choose_wl(const std::vector<LenRun>& runs, int64_t tile_nnz, const PerfT
                   bool sparse_tile, const PartitionParams& p);
 double model_time(const std::vector<LenRun>& runs, int64_t wl, const PerfTable& table,
                   bool sparse_tile, const PartitionParams& p);
+// Split length of one tile: split_len >= 0 is used as given (0 = never
+// split); -1 picks the tile's per-wavefront share of entries, rounded up to a
+// multiple of S and kept within [S, 8192].
+int64_t tile_split_len(int32_t split_len, int64_t tile_nnz, int64_t max_act_warp, int32_t S);
 // Greedy packing of a tile into workloads (Solution 3); appends to `out`.
 // row_base is the index of the tile's first row in the global sorted-row list.
 void partition_tile(const std::vector<LenRun>& runs, int64_t wl, int32_t tile, int64_t row_base,
@@ -93,7 +102,7 @@ struct tc_handle {
   double build_us = 0.0;
 
   // host copies of small metadata
-  std::vector<int64_t> tile_col_begin, tile_col_end, tile_nnz, tile_wl, tile_row_off;
+  std::vector<int64_t> tile_col_begin, tile_col_end, tile_nnz, tile_wl, tile_split, tile_row_off;
   std::vector<int64_t> tile_wl_begin;  // workloads of tile t: [tile_wl_begin[t], tile_wl_begin[t+1])
   std::vector<tc::HostWl> wls;
 
@@ -114,6 +123,10 @@ struct tc_handle {
   float* d_xbuf = nullptr;          // internal-space x for spmv on user vectors
   float* d_ybuf = nullptr;
   double* d_red = nullptr;          // reduction scratch
+  unsigned long long* d_counters = nullptr;  // per-tile work counters of the persistent pass
+  int32_t* d_empty = nullptr;       // internal rows without any entry (zeroed by every product)
+  int64_t n_empty = 0;
+  int n_cu = 256;                   // compute units of the device
   int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
 
   // allocator

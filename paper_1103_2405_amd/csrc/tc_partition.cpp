@@ -7,7 +7,9 @@
 //
 // Readings where the paper is silent:
 //  - rows longer than split_len are cut into chunks of split_len entries, each
-//    a one-row row-major workload; they take no part in the size bounds;
+//    a one-row row-major workload; they take no part in the size bounds (the
+//    automatic split length is the tile's share per resident wavefront, so
+//    that Algorithm 2's lower bound cannot exceed its upper bound by much);
 //  - h = max(1, floor(WL / w)); a column-major workload pads h to a multiple
 //    of S and then takes that many real rows when they remain;
 //  - the table is a grid over powers of two of the padded (w, h); a shape is
@@ -106,6 +108,12 @@ void walk(const std::vector<LenRun>& runs, int64_t wl, const PartitionParams& p,
 }  // namespace
 
 void set_error(const std::string& msg) { g_err = msg; }
+
+int64_t tile_split_len(int32_t split_len, int64_t tile_nnz, int64_t max_act_warp, int32_t S) {
+  if (split_len >= 0) return split_len;
+  const int64_t share = (tile_nnz + max_act_warp - 1) / max_act_warp;
+  return std::min<int64_t>(8192, std::max<int64_t>(S, ceil_to(share, S)));
+}
 const char* get_error() { return g_err.c_str(); }
 
 int64_t PerfTable::perf(bool sparse_tile, int64_t w, int64_t h) const {

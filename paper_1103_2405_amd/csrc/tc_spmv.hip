@@ -14,6 +14,7 @@
 // added to the FP32 y once per tile.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "tc_internal.h"
 
@@ -36,6 +37,276 @@ __device__ inline double wave_sum(double v) {
 
 __device__ inline void add_to_y(float* y, int32_t row, double s) { y[row] = (float)((double)y[row] + s); }
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Streams of the matrix are read once per product: non-temporal loads keep
+// them from evicting x and y from the caches.
+__device__ inline int32_t ld_nt(const int32_t* p) { return __builtin_nontemporal_load(p); }
+__device__ inline float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ inline v4i ld_nt4(const int32_t* p) { return __builtin_nontemporal_load((const v4i*)p); }
+__device__ inline v4f ld_nt4(const float* p) { return __builtin_nontemporal_load((const v4f*)p); }
+
+// Cross-lane moves of a double through DPP (two 32-bit halves).  Lanes whose
+// source is outside the row read 0 (bound_ctrl), rows outside ROWMASK add 0.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xf, true);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xf, true);
+  return __hiloint2double(h2, l2);
+}
+
+// Sum over each DPP row of 16 lanes; the total lands in the row's lane 15.
+__device__ inline double row16_sum(double v) {
+  v += dpp_f64<0x111>(v);  // row_shr:1
+  v += dpp_f64<0x112>(v);  // row_shr:2
+  v += dpp_f64<0x114>(v);  // row_shr:4
+  v += dpp_f64<0x118>(v);  // row_shr:8
+  return v;
+}
+// ... over 32 lanes (total in lanes 31 and 63)
+__device__ inline double row32_sum(double v) {
+  v = row16_sum(v);
+  return v + dpp_f64<0x142, 0xa>(v);
+}
+// ... over the wavefront (total in lane 63)
+__device__ inline double wave_total(double v) {
+  v = row16_sum(v);
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+template <class G>
+__device__ inline double dot4(v4i i, v4f v, const G& xg) {
+  const float x0 = xg(i.x), x1 = xg(i.y), x2 = xg(i.z), x3 = xg(i.w);
+  double s = (double)v.x * (double)x0;
+  s = fma((double)v.y, (double)x1, s);
+  s = fma((double)v.z, (double)x2, s);
+  return fma((double)v.w, (double)x3, s);
+}
+
+// Row-major rectangle with 64-element-aligned rows (S a multiple of 64):
+// every lane reads 4 consecutive entries (16 bytes) per 256-entry chunk.
+//   w_pad = 64:  a chunk holds 4 rows, 16 lanes each -> sums per DPP row
+//   w_pad = 128: a chunk holds 2 rows, 32 lanes each
+//   otherwise:   one row at a time, chunks of 256 (last one masked)
+// Two chunks are in flight per iteration (8 gathers per lane).
+template <class G>
+__device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict__ idx,
+                               const float* __restrict__ val, const int32_t* __restrict__ rowid,
+                               const G& x, float* __restrict__ y, double* __restrict__ partial,
+                               bool chunk) {
+  const int64_t off = d.data_off;
+  const int32_t wp = d.w_pad, nr = d.n_rows;
+  if (wp == 64 || wp == 128) {
+    const int lpr = wp >> 2;             // lanes per row
+    const int rpc = kWave / lpr;         // rows per chunk
+    const int my = lane / lpr;           // my row inside the chunk
+    const int nchunk = (nr + rpc - 1) / rpc;
+    for (int q = 0; q < nchunk; q += 2) {
+      const int ra = q * rpc + my, rb = (q + 1) * rpc + my;
+      const bool oka = ra < nr, okb = rb < nr;
+      double sa = 0.0, sb = 0.0;
+      v4i ia, ib;
+      v4f va, vb;
+      if (oka) {
+        ia = ld_nt4(idx + off + (int64_t)q * 256 + 4 * lane);
+        va = ld_nt4(val + off + (int64_t)q * 256 + 4 * lane);
+      }
+      if (okb) {
+        ib = ld_nt4(idx + off + (int64_t)(q + 1) * 256 + 4 * lane);
+        vb = ld_nt4(val + off + (int64_t)(q + 1) * 256 + 4 * lane);
+      }
+      if (oka) sa = dot4(ia, va, x);
+      if (okb) sb = dot4(ib, vb, x);
+      if (wp == 64) {
+        sa = row16_sum(sa);
+        sb = row16_sum(sb);
+      } else {
+        sa = row32_sum(sa);
+        sb = row32_sum(sb);
+      }
+      if ((lane % lpr) == lpr - 1) {
+        if (chunk) {
+          if (oka) partial[d.info >> 2] = sa;
+        } else {
+          if (oka) x.addy(y, ld_nt(rowid + d.rowid_off + ra), sa);
+          if (okb) x.addy(y, ld_nt(rowid + d.rowid_off + rb), sb);
+        }
+      }
+    }
+    return;
+  }
+  for (int32_t r = 0; r < nr; ++r) {
+    const int64_t base = off + (int64_t)r * wp;
+    double acc = 0.0;
+    int32_t c = 4 * lane;
+    for (; c + 256 < wp; c += 512) {
+      const v4i ia = ld_nt4(idx + base + c), ib = ld_nt4(idx + base + c + 256);
+      const v4f va = ld_nt4(val + base + c), vb = ld_nt4(val + base + c + 256);
+      acc += dot4(ia, va, x) + dot4(ib, vb, x);
+    }
+    if (c < wp) acc += dot4(ld_nt4(idx + base + c), ld_nt4(val + base + c), x);
+    acc = wave_total(acc);
+    if (lane == kWave - 1) {
+      if (chunk)
+        partial[d.info >> 2] = acc;
+      else
+        x.addy(y, ld_nt(rowid + d.rowid_off + r), acc);
+    }
+  }
+}
+
+// Column-major rectangle: lane owns rows r = 64 u + lane; U row blocks and C
+// columns are in flight together (U * C independent gathers per lane).
+template <int U, int C, class G>
+__device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict__ idx,
+                               const float* __restrict__ val, const int32_t* __restrict__ rowid,
+                               const G& x, float* __restrict__ y) {
+  const int64_t off = d.data_off, hp = d.h_pad;
+  const int32_t w = d.w_pad, nr = d.n_rows;
+  for (int32_t r0 = 0; r0 < nr; r0 += U * kWave) {
+    double acc[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[u] = 0.0;
+      ok[u] = r0 + u * kWave + lane < nr;
+    }
+    int32_t c = 0;
+    for (; c + C <= w; c += C) {
+      int32_t ii[U][C];
+      float vv[U][C];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+          if (ok[u]) {
+            const int64_t e = off + (int64_t)(c + k) * hp + r0 + u * kWave + lane;
+            ii[u][k] = ld_nt(idx + e);
+            vv[u][k] = ld_nt(val + e);
+          }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+          if (ok[u]) acc[u] = fma((double)vv[u][k], (double)x(ii[u][k]), acc[u]);
+    }
+    for (; c < w; ++c) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) {
+          const int64_t e = off + (int64_t)c * hp + r0 + u * kWave + lane;
+          acc[u] = fma((double)ld_nt(val + e), (double)x(ld_nt(idx + e)), acc[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) x.addy(y, ld_nt(rowid + d.rowid_off + r0 + u * kWave + lane), acc[u]);
+  }
+}
+
+// Any layout, any padding (used when the rectangle is not 64-aligned).
+template <class G>
+__device__ inline void generic_wl(const Wl& d, int lane, int layout, const int32_t* __restrict__ idx,
+                                  const float* __restrict__ val, const int32_t* __restrict__ rowid,
+                                  const G& x, float* __restrict__ y, double* __restrict__ partial) {
+  if (layout == kCM) {
+    const int64_t hp = d.h_pad;
+    for (int32_t r = lane; r < d.n_rows; r += kWave) {
+      double acc = 0.0;
+      for (int32_t c = 0; c < d.w_pad; ++c) {
+        const int64_t e = d.data_off + (int64_t)c * hp + r;
+        acc = fma((double)val[e], (double)x(idx[e]), acc);
+      }
+      x.addy(y, rowid[d.rowid_off + r], acc);
+    }
+    return;
+  }
+  const int64_t wp = d.w_pad;
+  for (int32_t r = 0; r < d.n_rows; ++r) {
+    const int64_t base = d.data_off + r * wp;
+    double acc = 0.0;
+    for (int64_t c = lane; c < wp; c += kWave) acc = fma((double)val[base + c], (double)x(idx[base + c]), acc);
+    acc = wave_total(acc);
+    if (lane == kWave - 1) {
+      if (layout == kChunk)
+        partial[d.info >> 2] = acc;
+      else
+        x.addy(y, rowid[d.rowid_off + r], acc);
+    }
+  }
+}
+
+// y update of one row by a tile: the row's first writer stores fl32(s); a
+// later tile (kAddFlag in the row id) stores fl32(y + s).  With NT the
+// accesses are non-temporal.
+template <bool NT>
+__device__ inline void addy_policy(float* y, int32_t rid, double s) {
+  if (rid & kAddFlag) {
+    const int32_t row = rid & ~kAddFlag;
+    if (NT) {
+      const float o = __builtin_nontemporal_load(y + row);
+      __builtin_nontemporal_store((float)((double)o + s), y + row);
+    } else {
+      y[row] = (float)((double)y[row] + s);
+    }
+  } else {
+    if (NT)
+      __builtin_nontemporal_store((float)s, y + rid);
+    else
+      y[rid] = (float)s;
+  }
+}
+
+// x as read by a tile: straight from global memory (through L1/L2) ...
+template <bool NT>
+struct GlobalX {
+  const float* __restrict__ x;
+  __device__ float operator()(int32_t i) const { return x[i]; }
+  __device__ void addy(float* y, int32_t row, double s) const { addy_policy<NT>(y, row, s); }
+};
+// ... or with the tile's first `lw` columns staged in LDS (the hottest ones:
+// columns are sorted by decreasing length, so a tile's head carries most of
+// its entries).
+struct StagedX {
+  const float* __restrict__ x;
+  const float* xs;
+  int32_t cb, lw;
+  __device__ float operator()(int32_t i) const {
+    const uint32_t k = (uint32_t)(i - cb);
+    return k < (uint32_t)lw ? xs[k] : x[i];
+  }
+  __device__ void addy(float* y, int32_t row, double s) const { addy_policy<true>(y, row, s); }
+};
+
+template <class G>
+__device__ inline void run_workload(const Wl& d, int lane, const int32_t* __restrict__ idx,
+                                    const float* __restrict__ val, const int32_t* __restrict__ rowid, const G& x,
+                                    float* __restrict__ y, double* __restrict__ partial) {
+  const int layout = d.info & 3;
+  const bool aligned = (d.data_off & 3) == 0;
+  if (layout == kCM && (d.h_pad & 63) == 0) {
+    const int32_t blocks = (d.n_rows + kWave - 1) / kWave;
+    if (blocks >= 8)
+      cm_rows<8, 1>(d, lane, idx, val, rowid, x, y);
+    else if (blocks >= 4)
+      cm_rows<4, 2>(d, lane, idx, val, rowid, x, y);
+    else if (blocks >= 2)
+      cm_rows<2, 4>(d, lane, idx, val, rowid, x, y);
+    else
+      cm_rows<1, 8>(d, lane, idx, val, rowid, x, y);
+  } else if (layout != kCM && aligned && (d.w_pad & 63) == 0) {
+    rm_wide(d, lane, idx, val, rowid, x, y, partial, layout == kChunk);
+  } else {
+    generic_wl(d, lane, layout, idx, val, rowid, x, y, partial);
+  }
+}
+
+// One wavefront per workload of the tile (grid = workloads / 4).
+template <bool YNT>
 __global__ void __launch_bounds__(kB) k_tile_spmv(const Wl* __restrict__ wl, int64_t n_wl,
                                                   const int32_t* __restrict__ idx, const float* __restrict__ val,
                                                   const int32_t* __restrict__ rowid, const float* __restrict__ x,
@@ -44,59 +315,36 @@ __global__ void __launch_bounds__(kB) k_tile_spmv(const Wl* __restrict__ wl, int
   const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (j >= n_wl) return;
   const Wl d = wl[j];
-  const int layout = d.info & 3;
-  if (layout == kCM) {
-    const int64_t hp = d.h_pad;
-    for (int32_t r0 = 0; r0 < d.n_rows; r0 += kWave) {
-      const int32_t r = r0 + lane;
-      if (r < d.n_rows) {
-        const int32_t* ip = idx + d.data_off + r;
-        const float* vp = val + d.data_off + r;
-        double acc = 0.0;
-        int32_t c = 0;
-        for (; c + 4 <= d.w_pad; c += 4) {
-          const int32_t i0 = ip[(c + 0) * hp], i1 = ip[(c + 1) * hp], i2 = ip[(c + 2) * hp], i3 = ip[(c + 3) * hp];
-          const float v0 = vp[(c + 0) * hp], v1 = vp[(c + 1) * hp], v2 = vp[(c + 2) * hp], v3 = vp[(c + 3) * hp];
-          const float x0 = x[i0], x1 = x[i1], x2 = x[i2], x3 = x[i3];
-          acc = fma((double)v0, (double)x0, acc);
-          acc = fma((double)v1, (double)x1, acc);
-          acc = fma((double)v2, (double)x2, acc);
-          acc = fma((double)v3, (double)x3, acc);
-        }
-        for (; c < d.w_pad; ++c) acc = fma((double)vp[c * hp], (double)x[ip[c * hp]], acc);
-        add_to_y(y, rowid[d.rowid_off + r], acc);
-      }
-    }
-  } else {
-    const int64_t wp = d.w_pad;
-    for (int32_t r = 0; r < d.n_rows; ++r) {
-      const int64_t base = d.data_off + r * wp;
-      double acc = 0.0;
-      int64_t c = lane;
-      for (; c + 3 * kWave < wp; c += 4 * kWave) {
-        const int32_t i0 = idx[base + c], i1 = idx[base + c + kWave], i2 = idx[base + c + 2 * kWave],
-                      i3 = idx[base + c + 3 * kWave];
-        const float v0 = val[base + c], v1 = val[base + c + kWave], v2 = val[base + c + 2 * kWave],
-                    v3 = val[base + c + 3 * kWave];
-        const float x0 = x[i0], x1 = x[i1], x2 = x[i2], x3 = x[i3];
-        acc = fma((double)v0, (double)x0, acc);
-        acc = fma((double)v1, (double)x1, acc);
-        acc = fma((double)v2, (double)x2, acc);
-        acc = fma((double)v3, (double)x3, acc);
-      }
-      for (; c < wp; c += kWave) acc = fma((double)val[base + c], (double)x[idx[base + c]], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        if (layout == kChunk)
-          partial[d.info >> 2] = acc;
-        else
-          add_to_y(y, rowid[d.rowid_off + r], acc);
-      }
-    }
+  run_workload(d, lane, idx, val, rowid, GlobalX<YNT>{x}, y, partial);
+}
+
+// Persistent tile pass: a few workgroups per CU stage the tile's hot x head
+// [cb, cb + lw) in LDS, then every wavefront takes workloads from the tile's
+// counter until none is left (each wavefront leaves once the counter passes
+// n_wl, so the grid always drains).  The counter must be 0 at launch.
+constexpr int kPB = 1024;  // threads of a persistent workgroup
+__global__ void __launch_bounds__(kPB) k_tile_persist(const Wl* __restrict__ wl, int64_t n_wl,
+                                                      const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                      const int32_t* __restrict__ rowid, const float* __restrict__ x,
+                                                      float* __restrict__ y, double* __restrict__ partial,
+                                                      int32_t cb, int32_t lw, unsigned long long* __restrict__ counter) {
+  extern __shared__ float xs[];
+  for (int32_t k = threadIdx.x; k < lw; k += blockDim.x) xs[k] = x[cb + k];
+  __syncthreads();
+  const int lane = lane_id();
+  const StagedX xg{x, xs, cb, lw};
+  for (;;) {
+    unsigned long long jj = 0;
+    if (lane == 0) jj = atomicAdd(counter, 1ull);
+    const int64_t j = (int64_t)__shfl(jj, 0, kWave);
+    if (j >= n_wl) break;
+    const Wl d = wl[j];
+    run_workload(d, lane, idx, val, rowid, xg, y, partial);
   }
 }
 
-// Sum of every split row's chunks in (tile, chunk) order, added to y.
+// Sum of every split row's chunks in (tile, chunk) order, added to y (or
+// stored when no tile wrote the row).
 __global__ void k_split_combine(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
                                 float* __restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,7 +352,10 @@ __global__ void k_split_combine(const SplitRow* __restrict__ sr, int64_t n, cons
   const SplitRow s = sr[i];
   double acc = 0.0;
   for (int32_t q = 0; q < s.n_slots; ++q) acc += partial[s.slot_begin + q];
-  add_to_y(y, s.row, acc);
+  if (s.store)
+    y[s.row] = (float)acc;
+  else
+    add_to_y(y, s.row, acc);
 }
 
 // ---- multiple right-hand sides: X is n x k row-major, column block of QB
@@ -136,7 +387,7 @@ __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int
         for (int q = 0; q < QB; ++q)
           if (q < nq) acc[q] = fma(v, (double)xr[q], acc[q]);
       }
-      const int64_t row = rowid[d.rowid_off + r];
+      const int64_t row = rowid[d.rowid_off + r] & ~kAddFlag;
 #pragma unroll
       for (int q = 0; q < QB; ++q)
         if (q < nq) add_to_y(Y + row * k + q0, q, acc[q]);
@@ -160,7 +411,7 @@ __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int
         if (layout == kChunk) {
           for (int q = 0; q < nq; ++q) partial[(int64_t)(d.info >> 2) * k + q0 + q] = acc[q];
         } else {
-          const int64_t row = rowid[d.rowid_off + r];
+          const int64_t row = rowid[d.rowid_off + r] & ~kAddFlag;
           for (int q = 0; q < nq; ++q) add_to_y(Y + row * k + q0, q, acc[q]);
         }
       }
@@ -392,28 +643,75 @@ hipEvent_t next_event(tc_handle* h) {
 }
 
 template <typename... KArgs, typename... Args>
-void launch_tile(tc_handle* h, void (*kern)(KArgs...), dim3 grid, hipStream_t st, Args... args) {
+void launch_tile(tc_handle* h, void (*kern)(KArgs...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t st,
+                 Args... args) {
   if (h->timing) {
     hipEvent_t a = next_event(h), b = next_event(h);
-    hipExtLaunchKernelGGL(kern, grid, dim3(kB), 0, st, a, b, 0, args...);
+    hipExtLaunchKernelGGL(kern, grid, block, shmem, st, a, b, 0, args...);
     h->tile_launches++;
   } else {
-    hipLaunchKernelGGL(kern, grid, dim3(kB), 0, st, args...);
+    hipLaunchKernelGGL(kern, grid, block, shmem, st, args...);
   }
   HIPC(hipGetLastError());
 }
 
+// Start of a product: zero the rows no tile writes, reset the tile counters.
+__global__ void k_begin_spmv(float* __restrict__ y, const int32_t* __restrict__ empty, int64_t n_empty,
+                             unsigned long long* __restrict__ counters, int32_t nt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_empty) y[empty[i]] = 0.0f;
+  if (i < nt) counters[i] = 0ull;
+}
+
+// Launch shape of the tile passes (defaults from measurement; the
+// environment variables TC_LDS_FLOATS and TC_PERSIST override them).
+struct TileConfig {
+  int persist = 0;
+  int lds_floats = 32768;
+  int y_nt = 1;
+};
+TileConfig tile_config() {
+  static TileConfig cfg = [] {
+    TileConfig c;
+    if (const char* e = getenv("TC_PERSIST")) c.persist = atoi(e);
+    if (const char* e = getenv("TC_LDS_FLOATS")) c.lds_floats = atoi(e);
+    if (const char* e = getenv("TC_Y_NT")) c.y_nt = atoi(e);
+    int dev = 0, maxsh = 65536;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxsh = 65536;
+    c.lds_floats = std::max(0, std::min(c.lds_floats, maxsh / 4));
+    return c;
+  }();
+  return cfg;
+}
+
 // y := A x in internal ids (x: n_cols, y: n_rows)
 void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st) {
-  if (h->n_rows > 0) {
-    hipLaunchKernelGGL(k_fill_f32, dim3(nblk(h->n_rows, kB)), dim3(kB), 0, st, y, h->n_rows, 0.0f);
+  const TileConfig cfg = tile_config();
+  const int64_t nz = std::max<int64_t>(h->n_empty, h->n_tiles);
+  if (nz > 0) {
+    hipLaunchKernelGGL(k_begin_spmv, dim3(nblk(nz, kB)), dim3(kB), 0, st, y, (const int32_t*)h->d_empty, h->n_empty,
+                       h->d_counters, (int32_t)h->n_tiles);
     HIPC(hipGetLastError());
   }
   for (int t = 0; t < h->n_tiles; ++t) {
     const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];
     if (e == b) continue;
-    launch_tile(h, k_tile_spmv, dim3(nblk(e - b, kWpb)), st, (const Wl*)(h->d_wl + b), (int64_t)(e - b),
-                (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, x, y, h->d_partial);
+    if (cfg.persist) {
+      const int32_t cb = (int32_t)h->tile_col_begin[t];
+      const int32_t lw = (int32_t)std::min<int64_t>(cfg.lds_floats, h->tile_col_end[t] - cb);
+      const int64_t wpb = kPB / kWave;
+      const int64_t grid = std::min<int64_t>((int64_t)h->n_cu, (e - b + wpb - 1) / wpb);
+      if (lw > 32768 / 2) HIPC(hipFuncSetAttribute((const void*)k_tile_persist,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, lw * 4));
+      launch_tile(h, k_tile_persist, dim3((unsigned)grid), dim3(kPB), (uint32_t)(lw * 4), st,
+                  (const Wl*)(h->d_wl + b), (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
+                  (const int32_t*)h->d_rowid, x, y, h->d_partial, cb, lw, h->d_counters + t);
+    } else {
+      launch_tile(h, cfg.y_nt ? k_tile_spmv<true> : k_tile_spmv<false>, dim3(nblk(e - b, kWpb)), dim3(kB), 0, st,
+                  (const Wl*)(h->d_wl + b), (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
+                  (const int32_t*)h->d_rowid, x, y, h->d_partial);
+    }
   }
   if (h->n_split_rows > 0) {
     hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
@@ -432,7 +730,8 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
   for (int t = 0; t < h->n_tiles; ++t) {
     const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];
     if (e == b) continue;
-    launch_tile(h, k_tile_spmm<QB>, dim3(nblk(e - b, kWpb), (k + QB - 1) / QB), st, (const Wl*)(h->d_wl + b),
+    launch_tile(h, k_tile_spmm<QB>, dim3(nblk(e - b, kWpb), (k + QB - 1) / QB), dim3(kB), 0, st,
+                (const Wl*)(h->d_wl + b),
                 (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, X, Y,
                 k, h->d_partial);
   }

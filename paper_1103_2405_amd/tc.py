@@ -59,6 +59,7 @@ class CInfo(ctypes.Structure):
 _VIEW_FIELDS = [("cperm", np.int32, "n_cols"), ("rowmap", np.int32, "n_rows"),
                 ("tile_col_begin", np.int64, "n_tiles"), ("tile_col_end", np.int64, "n_tiles"),
                 ("tile_nnz", np.int64, "n_tiles"), ("tile_wl", np.int64, "n_tiles"),
+                ("tile_split", np.int64, "n_tiles"),
                 ("tile_row_off", np.int64, "n_tiles+1"), ("rows_sorted", np.int32, "n_rows_sorted"),
                 ("rows_len", np.int32, "n_rows_sorted"),
                 ("wl_tile", np.int32, "n_workloads"), ("wl_layout", np.int32, "n_workloads"),
@@ -232,13 +233,16 @@ class TiledMatrix:
         _check(load_library().tc_handle_info(self.handle, ctypes.byref(inf)), "tc_handle_info")
         return {name: getattr(inf, name) for name, _ in CInfo._fields_}
 
-    def export_format(self) -> dict:
-        """Host copies of the whole format (keys as the reference builder's)."""
+    def export_format(self, metadata_only: bool = False) -> dict:
+        """Host copies of the whole format (keys as the reference builder's).
+        metadata_only skips the per-entry and per-row arrays."""
         inf = self.info()
         sizes = dict(inf)
         sizes["n_tiles+1"] = inf["n_tiles"] + 1
         arrays, view = {}, CFormatView()
         for name, dt, sz in _VIEW_FIELDS:
+            if metadata_only and sz in ("nnz_pad", "n_rowid", "n_rows_sorted", "n_rows", "n_cols"):
+                continue
             a = np.zeros(max(int(sizes[sz]), 0), dt)
             arrays[name] = a
             setattr(view, name, a.ctypes.data_as(vp) if a.size else None)

@@ -34,7 +34,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-FMT_KEYS = ["cperm", "rowmap", "tile_col_begin", "tile_col_end", "tile_nnz", "tile_wl", "tile_row_off",
+FMT_KEYS = ["cperm", "rowmap", "tile_col_begin", "tile_col_end", "tile_nnz", "tile_wl", "tile_split", "tile_row_off",
             "rows_sorted", "rows_len", "wl_tile", "wl_layout", "wl_w", "wl_w_pad", "wl_h_pad", "wl_row_begin",
             "wl_n_rows", "wl_chunk", "wl_n_chunks", "wl_data_off", "wl_rowid_off", "idx", "rowid"]
 
@@ -48,7 +48,7 @@ def assert_same_format(g, r):
     assert np.array_equal(g["val"].view(np.uint32), r["val"].view(np.uint32)), "val"
 
 
-def build_both(csr, W, wl=None, S=64, split_len=8192, n_tiles=-1, camping_pad=False, table_path=None,
+def build_both(csr, W, wl=None, S=64, split_len=-1, n_tiles=-1, camping_pad=False, table_path=None,
                max_act_warp=8192):
     say("build", csr[0], csr[1], len(csr[3]), "W", W, "wl", wl if not isinstance(wl, list) else wl[:3], "S", S,
         "split", split_len)
@@ -108,7 +108,7 @@ def test_format_rectangular_and_camping_pad():
 def test_format_rmat14_several_tiles():
     g = gg.rmat(14, 16, seed=14)
     csr = gg.pagerank_matrix(g)
-    for W, wl, split in [(1024, 2048, 512), (4096, 512, 8192), (1 << 14, 4096, 256)]:
+    for W, wl, split in [(1024, 2048, 512), (4096, 512, 8192), (1 << 14, 4096, 256), (2048, 300, -1)]:
         gm, ref = build_both(csr, W=W, wl=wl, split_len=split)
         assert_same_format(gm.export_format(), ref)
         check_spmv(gm, csr, gg.uniform_f32(g.n, 101))
@@ -130,12 +130,13 @@ def test_autotuned_workload_sizes_match_reference(tmp_path):
     _write_table(path)
     g = gg.rmat(13, 16, seed=3)
     csr = gg.pagerank_matrix(g)
-    gm, ref = build_both(csr, W=1024, wl=None, split_len=1024, table_path=path, max_act_warp=64)
-    fmt = gm.export_format()
-    assert list(fmt["tile_wl"]) == list(ref["tile_wl"])
-    assert len(set(ref["tile_wl"])) > 1
-    assert_same_format(fmt, ref)
-    check_spmv(gm, csr, gg.uniform_f32(g.n, 5))
+    for split, mw in ((1024, 64), (-1, 128)):
+        gm, ref = build_both(csr, W=1024, wl=None, split_len=split, table_path=path, max_act_warp=mw)
+        fmt = gm.export_format()
+        assert list(fmt["tile_wl"]) == list(ref["tile_wl"])
+        assert len(set(ref["tile_wl"])) > 1
+        assert_same_format(fmt, ref)
+        check_spmv(gm, csr, gg.uniform_f32(g.n, 5))
 
 
 # ------------------------------------------------------------------- SpMV
