@@ -77,6 +77,62 @@ def cpu_baseline(csr, budget_s: float):
                       "%.1f s; same byte formula" % (iters, dt)}
 
 
+def rwr_batched(c: float = 0.85, tol: float = 1e-6, ks=(1, 8, 32, 64)):
+    """Batched RWR (multi-RHS SpMM) on the symmetrised R-MAT scale-20 graph:
+    queries/s for k one-hot restart vectors solved together to an L1 change of
+    tol, against k sequential single-query solves with (a) the plain CSR SpMV
+    kernel and (b) the tiled single-vector SpMV."""
+    import torch
+    import graphgen as gg
+    from paper_1103_2405_amd import DeviceCsr, TiledMatrix, csr_spmv
+    g = gg.rmat(20, 16, seed=20)
+    W = gg.rwr_matrix(g)
+    seeds = gg.rwr_seeds(g, max(ks), 40)
+    A = DeviceCsr(W)
+    tm = TiledMatrix(A)
+    out = {"graph": "symmetrised rmat-20", "nnz": int(A.nnz), "c": c, "tol": tol}
+    for k in ks:
+        tm.rwr(seeds[:k], c, tol, 500, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it, res = tm.rwr(seeds[:k], c, tol, 500, 10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["k%d" % k] = {"queries_per_s": round(k / dt, 2), "iters": it, "ms": round(dt * 1e3, 2)}
+    # (b) k sequential tiled single-vector solves (k = 32)
+    k = 32
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(k):
+        tm.rwr(seeds[q:q + 1], c, tol, 500, 10)
+    torch.cuda.synchronize()
+    tiled_seq = k / (time.perf_counter() - t0)
+    # (a) k sequential solves with the plain CSR kernel (vector update by torch)
+    n = A.n_rows
+    r = torch.empty(n, device="cuda")
+    y = torch.empty(n, device="cuda")
+    t0 = time.perf_counter()
+    for q in range(k):
+        s = int(seeds[q])
+        r.zero_()
+        r[s] = 1.0
+        for it in range(500):
+            csr_spmv(A, r, y)
+            y.mul_(c)
+            y[s] += 1.0 - c
+            d = float((y - r).abs().sum()) if (it + 1) % 10 == 0 else 1.0
+            r, y = y, r
+            if d <= tol:
+                break
+    torch.cuda.synchronize()
+    csr_seq = k / (time.perf_counter() - t0)
+    b = out["k32"]["queries_per_s"]
+    out.update(csr_loop_queries_per_s=round(csr_seq, 2), tiled_loop_queries_per_s=round(tiled_seq, 2),
+               speedup_k32_vs_csr_loop=round(b / csr_seq, 2), speedup_k32_vs_tiled_loop=round(b / tiled_seq, 2))
+    tm.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +145,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-timing", action="store_true", help="skip the per-launch kernel timing")
+    ap.add_argument("--no-rwr", action="store_true", help="skip the batched RWR measurement")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -179,6 +236,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    rwr = None
+    if not args.no_rwr:
+        del A
+        torch.cuda.empty_cache()
+        rwr = rwr_batched()
+        log("batched rwr:", json.dumps(rwr))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(csr, args.cpu_budget)
@@ -197,6 +261,7 @@ def main():
         "pagerank_spmv_gbps": round(args.iters * spmv_bytes / (pr_ms / 1e3) / 1e9, 1),
         "csr_baseline_spmv_gbps": round(spmv_bytes / (csr_ms / 1e3) / 1e9, 1),
         "roofline": roofline,
+        "rwr_batched": rwr,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

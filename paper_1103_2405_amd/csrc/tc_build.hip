@@ -115,17 +115,84 @@ __global__ void k_iota(int32_t* a, int64_t n) {
   if (i < n) a[i] = (int32_t)i;
 }
 
-// a1: column lengths (one atomic per entry).
-__global__ void k_col_count(const int32_t* __restrict__ col, int64_t nnz, int32_t* __restrict__ clen) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nnz) atomicAdd(&clen[col[k]], 1);
+// a1: column lengths.  A power-law column can hold 10^5-10^6 entries, and
+// atomics on one address serialise, so the hottest columns (found from a
+// 1/64 sample) are counted in a per-block LDS hash table and flushed once per
+// block; every other entry adds to its column directly.
+constexpr int kHotCap = 4096;           // hot columns counted in LDS
+constexpr int kHotSlots = 2 * kHotCap;  // open-addressing table (load <= 1/2)
+constexpr int kSampleStep = 64;
+
+__global__ void k_col_sample(const int32_t* __restrict__ col, int64_t nnz, int32_t* __restrict__ samp) {
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kSampleStep;
+  if (k < nnz) atomicAdd(&samp[col[k]], 1);
 }
 
-__global__ void k_max_i32(const int32_t* __restrict__ a, int64_t n, int32_t* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t v = i < n ? a[i] : 0;
+// number of columns whose sampled count is >= 2^b, for b = 0..31
+__global__ void k_sample_hist(const int32_t* __restrict__ samp, int64_t n, unsigned long long* __restrict__ ge) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t v = i < n ? samp[i] : 0;
+  for (int b = 0; b < 31; ++b) {
+    const uint64_t m = __ballot(v >= (1 << b));
+    if (lane_id() == 0 && m) atomicAdd(&ge[b], (unsigned long long)__popcll(m));
+    if (!m) break;
+  }
+}
+
+__global__ void k_ge_flags(const int32_t* __restrict__ samp, int64_t n, int32_t thr, int32_t* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = samp[i] >= thr;
+}
+
+__global__ void k_compact_idx(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos, int64_t n,
+                              int32_t* __restrict__ out);
+
+__device__ inline uint32_t hot_hash(int32_t c) { return ((uint32_t)c * 2654435761u) >> 19; }  // 13 bits
+
+__global__ void __launch_bounds__(256) k_col_count_hot(const int32_t* __restrict__ col, int64_t nnz,
+                                                       const int32_t* __restrict__ hot, int32_t n_hot,
+                                                       int32_t* __restrict__ clen) {
+  __shared__ int32_t key[kHotSlots];
+  __shared__ int32_t cnt[kHotSlots];
+  for (int i = threadIdx.x; i < kHotSlots; i += blockDim.x) {
+    key[i] = -1;
+    cnt[i] = 0;
+  }
+  __syncthreads();
+  for (int32_t h = threadIdx.x; h < n_hot; h += blockDim.x) {  // keys are distinct
+    uint32_t s = hot_hash(hot[h]) & (kHotSlots - 1);
+    while (atomicCAS(&key[s], -1, hot[h]) != -1) s = (s + 1) & (kHotSlots - 1);
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride) {
+    const int32_t c = col[k];
+    uint32_t s = hot_hash(c) & (kHotSlots - 1);
+    int32_t kk;
+    while ((kk = key[s]) != c && kk != -1) s = (s + 1) & (kHotSlots - 1);
+    if (kk == c)
+      atomicAdd(&cnt[s], 1);
+    else
+      atomicAdd(&clen[c], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHotSlots; i += blockDim.x)
+    if (key[i] != -1 && cnt[i]) atomicAdd(&clen[key[i]], cnt[i]);
+}
+
+// maximum of a non-negative array: grid-stride, one atomic per block
+__global__ void __launch_bounds__(256) k_max_i32(const int32_t* __restrict__ a, int64_t n, int32_t* out) {
+  __shared__ int32_t wm[256 / kWave];
+  int32_t v = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v = max(v, a[i]);
   for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
-  if (lane_id() == 0) atomicMax(out, v);
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / kWave; ++w) v = max(v, wm[w]);
+    atomicMax(out, v);
+  }
 }
 
 __global__ void k_count_eq(const int32_t* __restrict__ a, int64_t n, int32_t v, unsigned long long* out) {
@@ -484,7 +551,7 @@ void cs_pass(const Op& op, int64_t n, int nbits, Tmp& tmp, hipStream_t st) {
 int32_t dev_max(const int32_t* a, int64_t n, Tmp& tmp, hipStream_t st) {
   int32_t* d = tmp.get<int32_t>(1);
   HIPX(hipMemsetAsync(d, 0, sizeof(int32_t), st));
-  if (n > 0) hipLaunchKernelGGL(k_max_i32, dim3(nblk(n, kB)), dim3(kB), 0, st, a, n, d);
+  if (n > 0) hipLaunchKernelGGL(k_max_i32, dim3((unsigned)std::min<int64_t>(1024, nblk(n, kB))), dim3(kB), 0, st, a, n, d);
   HIPX(hipGetLastError());
   int32_t v = 0;
   HIPX(hipMemcpyAsync(&v, d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -519,8 +586,41 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->d_clen = clen;
   if (n_cols > 0) {
     HIPX(hipMemsetAsync(clen, 0, sizeof(int32_t) * n_cols, st));
-    if (nnz > 0) hipLaunchKernelGGL(k_col_count, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, nnz, clen);
-    HIPX(hipGetLastError());
+    int32_t n_hot = 0;
+    int32_t* hot = nullptr;
+    if (nnz >= (int64_t)kSampleStep * 1024) {
+      int32_t* samp = tmp.get<int32_t>(n_cols);
+      unsigned long long* ge = tmp.get<unsigned long long>(32);
+      HIPX(hipMemsetAsync(samp, 0, sizeof(int32_t) * n_cols, st));
+      HIPX(hipMemsetAsync(ge, 0, sizeof(unsigned long long) * 32, st));
+      const int64_t ns = (nnz + kSampleStep - 1) / kSampleStep;
+      hipLaunchKernelGGL(k_col_sample, dim3(nblk(ns, kB)), dim3(kB), 0, st, A->col_idx, nnz, samp);
+      hipLaunchKernelGGL(k_sample_hist, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, (const int32_t*)samp, n_cols, ge);
+      HIPX(hipGetLastError());
+      unsigned long long hge[32];
+      HIPX(hipMemcpyAsync(hge, ge, sizeof(hge), hipMemcpyDeviceToHost, st));
+      HIPX(hipStreamSynchronize(st));
+      int b = 2;  // at least 4 sampled hits (about 256 entries) to be worth a slot
+      while (b < 31 && hge[b] > (unsigned long long)kHotCap) ++b;
+      if (b < 31 && hge[b] > 0) {
+        int32_t* fl = tmp.get<int32_t>(n_cols);
+        int32_t* ps = tmp.get<int32_t>(n_cols);
+        hipLaunchKernelGGL(k_ge_flags, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, (const int32_t*)samp, n_cols,
+                           (int32_t)1 << b, fl);
+        HIPX(hipGetLastError());
+        n_hot = (int32_t)excl_scan<int32_t, int32_t>(fl, n_cols, ps, tmp, st);
+        hot = tmp.get<int32_t>(n_hot);
+        hipLaunchKernelGGL(k_compact_idx, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, (const int32_t*)fl,
+                           (const int32_t*)ps, n_cols, hot);
+        HIPX(hipGetLastError());
+      }
+    }
+    if (nnz > 0) {
+      const unsigned grid = (unsigned)std::min<int64_t>(2048, nblk(nnz, kB));
+      hipLaunchKernelGGL(k_col_count_hot, dim3(grid), dim3(256), 0, st, A->col_idx, nnz, (const int32_t*)hot, n_hot,
+                         clen);
+      HIPX(hipGetLastError());
+    }
   }
   const int32_t maxclen = dev_max(clen, n_cols, tmp, st);
 

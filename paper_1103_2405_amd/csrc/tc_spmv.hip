@@ -358,65 +358,90 @@ __global__ void k_split_combine(const SplitRow* __restrict__ sr, int64_t n, cons
     add_to_y(y, s.row, acc);
 }
 
-// ---- multiple right-hand sides: X is n x k row-major, column block of QB
-template <int QB>
+// ---- multiple right-hand sides (Y := A X, X n_cols x k row-major)
+// Lanes map to columns of X: a group of kg lanes (k rounded up to a power of
+// two, at most 64) takes one matrix row at a time and reads that row's
+// entries as broadcasts, so every gathered X row is one contiguous read of k
+// floats (a whole 128-byte line at k = 32) instead of 4 useful bytes.
+// 64 / kg groups share a wavefront; blockIdx.y selects a chunk of 64 columns
+// when k > 64.  Pad entries (value 0) are skipped.
+__device__ inline void addY(float* __restrict__ Y, int32_t rid, int32_t k, int32_t col, double s) {
+  if (rid & kAddFlag) {
+    float* p = Y + (int64_t)(rid & ~kAddFlag) * k + col;
+    *p = (float)((double)*p + s);
+  } else {
+    Y[(int64_t)rid * k + col] = (float)s;
+  }
+}
+
 __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int64_t n_wl,
                                                   const int32_t* __restrict__ idx, const float* __restrict__ val,
                                                   const int32_t* __restrict__ rowid, const float* __restrict__ X,
-                                                  float* __restrict__ Y, int32_t k, double* __restrict__ partial) {
+                                                  float* __restrict__ Y, int32_t k, int32_t kg,
+                                                  double* __restrict__ partial) {
   const int lane = lane_id();
   const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (j >= n_wl) return;
-  const int32_t q0 = blockIdx.y * QB;
-  const int32_t nq = min(QB, k - q0);
+  const int groups = kWave / kg;
+  const int g = lane / kg;
+  const int32_t col = (int32_t)blockIdx.y * kWave + lane % kg;
+  const bool act = col < k;
   const Wl d = wl[j];
   const int layout = d.info & 3;
-  double acc[QB];
+  const int64_t off = d.data_off;
   if (layout == kCM) {
     const int64_t hp = d.h_pad;
-    for (int32_t r0 = 0; r0 < d.n_rows; r0 += kWave) {
-      const int32_t r = r0 + lane;
-      if (r >= d.n_rows) continue;
-#pragma unroll
-      for (int q = 0; q < QB; ++q) acc[q] = 0.0;
+    for (int32_t r0 = g; r0 < d.n_rows; r0 += 2 * groups) {
+      const int32_t r1 = r0 + groups;
+      const bool ok1 = r1 < d.n_rows;
+      double a0 = 0.0, a1 = 0.0;
       for (int32_t c = 0; c < d.w_pad; ++c) {
-        const int64_t e = d.data_off + (int64_t)c * hp + r;
-        const double v = (double)val[e];
-        const float* xr = X + (int64_t)idx[e] * k + q0;
-#pragma unroll
-        for (int q = 0; q < QB; ++q)
-          if (q < nq) acc[q] = fma(v, (double)xr[q], acc[q]);
+        const int64_t e0 = off + (int64_t)c * hp + r0, e1 = off + (int64_t)c * hp + r1;
+        const float v0 = ld_nt(val + e0), v1 = ok1 ? ld_nt(val + e1) : 0.0f;
+        const int32_t i0 = ld_nt(idx + e0), i1 = ok1 ? ld_nt(idx + e1) : 0;
+        if (act && v0 != 0.0f) a0 = fma((double)v0, (double)X[(int64_t)i0 * k + col], a0);
+        if (act && v1 != 0.0f) a1 = fma((double)v1, (double)X[(int64_t)i1 * k + col], a1);
       }
-      const int64_t row = rowid[d.rowid_off + r] & ~kAddFlag;
-#pragma unroll
-      for (int q = 0; q < QB; ++q)
-        if (q < nq) add_to_y(Y + row * k + q0, q, acc[q]);
+      if (act) {
+        addY(Y, ld_nt(rowid + d.rowid_off + r0), k, col, a0);
+        if (ok1) addY(Y, ld_nt(rowid + d.rowid_off + r1), k, col, a1);
+      }
     }
   } else {
     const int64_t wp = d.w_pad;
-    for (int32_t r = 0; r < d.n_rows; ++r) {
-      const int64_t base = d.data_off + r * wp;
+    for (int32_t r = g; r < d.n_rows; r += groups) {
+      const int64_t base = off + (int64_t)r * wp;
+      double acc = 0.0;
+      int64_t c = 0;
+      for (; c + 4 <= wp; c += 4) {
+        float v[4];
+        int32_t ii[4];
 #pragma unroll
-      for (int q = 0; q < QB; ++q) acc[q] = 0.0;
-      for (int64_t c = lane; c < wp; c += kWave) {
-        const double v = (double)val[base + c];
-        const float* xr = X + (int64_t)idx[base + c] * k + q0;
-#pragma unroll
-        for (int q = 0; q < QB; ++q)
-          if (q < nq) acc[q] = fma(v, (double)xr[q], acc[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < QB; ++q) acc[q] = wave_sum(acc[q]);
-      if (lane == 0) {
-        if (layout == kChunk) {
-          for (int q = 0; q < nq; ++q) partial[(int64_t)(d.info >> 2) * k + q0 + q] = acc[q];
-        } else {
-          const int64_t row = rowid[d.rowid_off + r] & ~kAddFlag;
-          for (int q = 0; q < nq; ++q) add_to_y(Y + row * k + q0, q, acc[q]);
+        for (int u = 0; u < 4; ++u) {
+          v[u] = ld_nt(val + base + c + u);
+          ii[u] = ld_nt(idx + base + c + u);
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (act && v[u] != 0.0f) acc = fma((double)v[u], (double)X[(int64_t)ii[u] * k + col], acc);
+      }
+      for (; c < wp; ++c) {
+        const float v = ld_nt(val + base + c);
+        if (act && v != 0.0f) acc = fma((double)v, (double)X[(int64_t)ld_nt(idx + base + c) * k + col], acc);
+      }
+      if (act) {
+        if (layout == kChunk)
+          partial[(int64_t)(d.info >> 2) * k + col] = acc;
+        else
+          addY(Y, ld_nt(rowid + d.rowid_off + r), k, col, acc);
       }
     }
   }
+}
+
+__global__ void k_begin_spmm(float* __restrict__ Y, const int32_t* __restrict__ empty, int64_t n_empty, int32_t k) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_empty * k) Y[(int64_t)empty[t / k] * k + t % k] = 0.0f;
 }
 
 __global__ void k_split_combine_mm(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
@@ -428,7 +453,10 @@ __global__ void k_split_combine_mm(const SplitRow* __restrict__ sr, int64_t n, c
   const SplitRow s = sr[i];
   double acc = 0.0;
   for (int32_t u = 0; u < s.n_slots; ++u) acc += partial[(int64_t)(s.slot_begin + u) * k + q];
-  add_to_y(Y + (int64_t)s.row * k, q, acc);
+  if (s.store)
+    Y[(int64_t)s.row * k + q] = (float)acc;
+  else
+    add_to_y(Y + (int64_t)s.row * k, q, acc);
 }
 
 // ---- plain CSR baseline: one thread per row (FP64 accumulation)
@@ -668,7 +696,7 @@ __global__ void k_begin_spmv(float* __restrict__ y, const int32_t* __restrict__ 
 struct TileConfig {
   int persist = 0;
   int lds_floats = 32768;
-  int y_nt = 1;
+  int y_nt = 0;
 };
 TileConfig tile_config() {
   static TileConfig cfg = [] {
@@ -722,18 +750,19 @@ void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st) {
 }
 
 void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st) {
-  constexpr int QB = 8;
-  if (h->n_rows > 0) {
-    hipLaunchKernelGGL(k_fill_f32, dim3(nblk(h->n_rows * k, kB)), dim3(kB), 0, st, Y, h->n_rows * k, 0.0f);
+  int32_t kg = 1;
+  while (kg < k && kg < kWave) kg <<= 1;
+  if (h->n_empty > 0) {
+    hipLaunchKernelGGL(k_begin_spmm, dim3(nblk(h->n_empty * k, kB)), dim3(kB), 0, st, Y, (const int32_t*)h->d_empty,
+                       h->n_empty, k);
     HIPC(hipGetLastError());
   }
   for (int t = 0; t < h->n_tiles; ++t) {
     const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];
     if (e == b) continue;
-    launch_tile(h, k_tile_spmm<QB>, dim3(nblk(e - b, kWpb), (k + QB - 1) / QB), dim3(kB), 0, st,
-                (const Wl*)(h->d_wl + b),
-                (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, X, Y,
-                k, h->d_partial);
+    launch_tile(h, k_tile_spmm, dim3(nblk(e - b, kWpb), (k + kWave - 1) / kWave), dim3(kB), 0, st,
+                (const Wl*)(h->d_wl + b), (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
+                (const int32_t*)h->d_rowid, X, Y, k, kg, h->d_partial);
   }
   if (h->n_split_rows > 0) {
     hipLaunchKernelGGL(k_split_combine_mm, dim3(nblk(h->n_split_rows * k, kB)), dim3(kB), 0, st, h->d_split,

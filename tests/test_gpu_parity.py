@@ -170,7 +170,7 @@ def test_spmm_matches_oracle():
     g = gg.rmat(12, 16, seed=4)
     csr = gg.rwr_matrix(g)
     gm = TiledMatrix(csr, tile_width=512, wl=1024, split_len=256)
-    for k in (1, 3, 8, 13):
+    for k in (1, 3, 8, 13, 32, 64, 100):
         X = np.stack([gg.uniform_f32(g.n, 10 + q) for q in range(k)], axis=1)
         Y = gm.spmm(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
         ref = oracle.spmm(csr, X)
@@ -270,8 +270,8 @@ def test_rwr_matches_oracle():
     g = gg.rmat(12, 16, seed=8)
     csr = gg.rwr_matrix(g)
     gm = TiledMatrix(csr, tile_width=1024)
-    seeds = gg.rwr_seeds(g, 5, 40)
-    for k in (1, 5):
+    seeds = gg.rwr_seeds(g, 32, 40)
+    for k in (1, 5, 32):
         R, it, res = gm.rwr(seeds[:k], 0.85, 0.0, 30)
         Rref, _, rr = oracle.rwr(csr, seeds[:k], 0.85, 0.0, 30)
         d = np.abs(R.cpu().numpy() - Rref).sum(axis=0)
