@@ -83,6 +83,10 @@ typedef struct {
                                  of 512 (Solution 3, partition camping); default 0 */
   int32_t relabel;            /* -1: relabel rows like columns when square; 0: keep row ids */
   int32_t max_act_warp;       /* resident wavefronts assumed by the model (Eq. 1); 0 = 8192 */
+  int32_t xcd_groups;         /* 0: tiles of Algorithm 1 run one after the other (default);
+                                 G > 0: MI355X schedule -- tile 0 = columns [0, W), then G
+                                 column ranges holding equal numbers of entries, run together
+                                 with range g pinned to XCD g-1 and summed afterwards */
   const char* perf_table;     /* path of a throughput table for the model; NULL = built-in */
   /* optional device allocator for the handle's buffers; NULL = hipMalloc / hipFree */
   void* (*alloc)(size_t bytes, void* ctx);
@@ -94,6 +98,7 @@ typedef struct {
 typedef struct {
   int64_t n_rows, n_cols, nnz;
   int32_t tile_width, wave, split_len, relabel;  /* split_len as given (-1 = automatic) */
+  int32_t xcd_groups, pad_;
   int32_t n_dense_tiles;      /* T of Algorithm 1 */
   int32_t n_tiles;            /* T plus one if a sparse tile exists */
   int64_t n_workloads;

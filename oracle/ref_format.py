@@ -30,9 +30,27 @@ import numpy as np
 from .autotune import RM, CM, PerfTable, choose_wl, count_tiles, partition_rows, tile_split_len
 
 
+def xcd_boundaries(clen_sorted: np.ndarray, W: int, groups: int) -> list:
+    """Column ranges of the XCD schedule: the head [0, W) as one tile, then the
+    remaining columns cut into `groups` ranges holding equal numbers of
+    entries (range g ends at the first column where the entries after W reach
+    ceil(g * rest / groups))."""
+    n_cols = len(clen_sorted)
+    head = min(W, n_cols)
+    pre = np.concatenate([[0], np.cumsum(clen_sorted[head:], dtype=np.int64)])
+    rest = int(pre[-1])
+    bounds = [0, head]
+    for g in range(1, groups):
+        need = -(-(g * rest) // groups)
+        c = head + int(np.searchsorted(pre, need, side="left"))
+        bounds.append(max(min(c, n_cols), bounds[-1]))
+    bounds.append(n_cols)
+    return bounds
+
+
 def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S: int = 64,
           split_len: int = -1, camping_pad: bool = False, relabel: Optional[bool] = None,
-          table: Optional[PerfTable] = None, max_act_warp: int = 8192) -> dict:
+          table: Optional[PerfTable] = None, max_act_warp: int = 8192, xcd_groups: int = 0) -> dict:
     n_rows, n_cols, rp, col, val = csr
     rp = np.asarray(rp, np.int64)
     col = np.asarray(col, np.int32)
@@ -52,17 +70,24 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
     rmap = cpos.copy() if relabel else np.arange(n_rows, dtype=np.int64)
 
     # a3: Algorithm 1
-    NT = -(-n_cols // W)
-    T = min(n_tiles, NT) if n_tiles >= 0 else count_tiles(clen[cperm], W)
-    ranges = [(t * W, min((t + 1) * W, n_cols)) for t in range(T)]
-    if T * W < n_cols:
-        ranges.append((T * W, n_cols))
+    if xcd_groups > 0:
+        # MI355X schedule: hot head tile, then column ranges of equal entries
+        b = xcd_boundaries(clen[cperm], W, xcd_groups)
+        ranges = [(b[i], b[i + 1]) for i in range(len(b) - 1)]
+        T = 1
+    else:
+        NT = -(-n_cols // W)
+        T = min(n_tiles, NT) if n_tiles >= 0 else count_tiles(clen[cperm], W)
+        ranges = [(t * W, min((t + 1) * W, n_cols)) for t in range(T)]
+        if T * W < n_cols:
+            ranges.append((T * W, n_cols))
     ntiles = len(ranges)
+    starts = np.asarray([r[0] for r in ranges[1:]], np.int64)
 
     # a4: stable bucketing of entries by tile
     row_of = np.repeat(np.arange(n_rows, dtype=np.int64), np.diff(rp))
     icol = cpos[col] if nnz else np.zeros(0, np.int64)
-    tile_of = np.minimum(icol // W, T)
+    tile_of = np.searchsorted(starts, icol, side="right") if nnz else np.zeros(0, np.int64)
     order = np.argsort(tile_of, kind="stable")
     tcount = np.bincount(tile_of, minlength=ntiles) if nnz else np.zeros(ntiles, np.int64)
     tstart = np.concatenate([[0], np.cumsum(tcount)])
@@ -156,7 +181,7 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
         val_out[dest] = val[src]
 
     return dict(
-        n_rows=n_rows, n_cols=n_cols, nnz=nnz, W=W, S=S, split_len=split_len, T=T,
+        n_rows=n_rows, n_cols=n_cols, nnz=nnz, W=W, S=S, split_len=split_len, T=T, xcd_groups=xcd_groups,
         tile_split=np.asarray(split_used, np.int64),
         n_tiles_total=ntiles, relabel=bool(relabel),
         clen=clen, cperm=cperm.astype(np.int32), cpos=cpos.astype(np.int32),

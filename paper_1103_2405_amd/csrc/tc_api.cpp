@@ -24,6 +24,7 @@ extern "C" tc_status tc_handle_info(const tc_handle* h, tc_info* info) {
   info->wave = h->S;
   info->split_len = h->split_len;
   info->relabel = h->relabel ? 1 : 0;
+  info->xcd_groups = h->xcd_groups;
   info->n_dense_tiles = h->T;
   info->n_tiles = h->n_tiles;
   info->n_workloads = h->n_wl;

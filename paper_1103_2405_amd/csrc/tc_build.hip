@@ -233,6 +233,19 @@ __global__ void k_rowmap(const int32_t* __restrict__ cpos, int64_t n_rows, int r
   }
 }
 
+// smallest i in [0, n) with a[i] >= key[g] (a non-decreasing), for g = 1..G-1
+__global__ void k_lower_bound(const int64_t* __restrict__ a, int64_t n, const int64_t* __restrict__ key, int G,
+                              int64_t* __restrict__ out) {
+  const int g = threadIdx.x;
+  if (g < 1 || g >= G) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key[g]) lo = mid + 1; else hi = mid;
+  }
+  out[g] = lo;
+}
+
 __global__ void k_strided(const int32_t* __restrict__ a, int64_t stride, int64_t cnt, int32_t* __restrict__ out) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < cnt) out[t] = a[t * stride];
@@ -273,33 +286,48 @@ __global__ void k_icol(const int32_t* __restrict__ col, const int32_t* __restric
   if (k < nnz) icol[k] = cpos[col[k]];
 }
 
-__device__ inline int32_t tile_of(int32_t icol, int32_t W, int32_t T) { return min(icol / W, T); }
+// Tile of an internal column: fixed-width tiles (icol / W, the columns past
+// the T dense tiles forming tile T) or explicit tile starts (tiles 1..ns).
+struct TileMap {
+  int32_t W, T;
+  const int32_t* starts;  // NULL for fixed width
+  int32_t ns;
+  __device__ int32_t operator()(int32_t icol) const {
+    if (!starts) return min(icol / W, T);
+    int32_t lo = 0, hi = ns;  // number of starts <= icol
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (starts[mid] <= icol) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  }
+};
 
 // first position of each tile in the bucketed entries (tile ids are sorted)
-__global__ void k_tile_bounds(const int32_t* __restrict__ b_icol, int64_t nnz, int32_t W, int32_t T, int32_t ntiles,
+__global__ void k_tile_bounds(const int32_t* __restrict__ b_icol, int64_t nnz, TileMap tm, int32_t ntiles,
                               int64_t* __restrict__ tstart) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > ntiles) return;
   int64_t lo = 0, hi = nnz;
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
-    if (tile_of(b_icol[mid], W, T) < t) lo = mid + 1; else hi = mid;
+    if (tm(b_icol[mid]) < t) lo = mid + 1; else hi = mid;
   }
   tstart[t] = lo;
 }
 
 // a5: segment heads = first entry of each (tile, row) pair
 __global__ void k_seg_flags(const int32_t* __restrict__ b_icol, const int32_t* __restrict__ b_row, int64_t nnz,
-                            int32_t W, int32_t T, int32_t* __restrict__ flags) {
+                            TileMap tm, int32_t* __restrict__ flags) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
-  int f = k == 0 || b_row[k] != b_row[k - 1] || tile_of(b_icol[k], W, T) != tile_of(b_icol[k - 1], W, T);
+  int f = k == 0 || b_row[k] != b_row[k - 1] || tm(b_icol[k]) != tm(b_icol[k - 1]);
   flags[k] = f;
 }
 
 __global__ void k_seg_emit(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos,
                            const int32_t* __restrict__ b_icol, const int32_t* __restrict__ b_row,
-                           const int32_t* __restrict__ rowmap, int64_t nnz, int32_t W, int32_t T,
+                           const int32_t* __restrict__ rowmap, int64_t nnz, TileMap tm,
                            int32_t* __restrict__ seg_start, int32_t* __restrict__ seg_row,
                            int32_t* __restrict__ seg_tile) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,7 +335,7 @@ __global__ void k_seg_emit(const int32_t* __restrict__ flags, const int32_t* __r
   int32_t s = pos[k];
   seg_start[s] = (int32_t)k;
   seg_row[s] = rowmap[b_row[k]];
-  seg_tile[s] = tile_of(b_icol[k], W, T);
+  seg_tile[s] = tm(b_icol[k]);
 }
 
 __global__ void k_seg_len(const int32_t* __restrict__ seg_start, int64_t nseg, int64_t nnz, int32_t* __restrict__ seg_len) {
@@ -375,6 +403,11 @@ __global__ void k_first_touch(const int32_t* __restrict__ seg_tile, const int32_
   touched[r] = 1;
   const int64_t sp = split_t[t];
   if (!(sp > 0 && (int64_t)seg_len[s] > sp)) atomicMin(&first[r], t);
+}
+
+__global__ void k_ne(const int32_t* __restrict__ a, int64_t n, int32_t v, int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] != v;
 }
 
 __global__ void k_not(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
@@ -493,9 +526,9 @@ struct TileOp {
   int32_t* icol_out;
   float* val_out;
   int32_t* row_out;
-  int32_t W, T;
+  TileMap tm;
   int shift;
-  __device__ uint32_t bucket(int64_t k) const { return ((uint32_t)tile_of(icol_in[k], W, T) >> shift) & 255u; }
+  __device__ uint32_t bucket(int64_t k) const { return ((uint32_t)tm(icol_in[k]) >> shift) & 255u; }
   __device__ void move(int64_t k, int64_t p) const {
     icol_out[p] = icol_in[k];
     val_out[p] = val_in[k];
@@ -665,29 +698,62 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipGetLastError());
   }
 
-  // ---- a3: Algorithm 1
+  // ---- a3: Algorithm 1 (or the XCD schedule's column ranges)
   const int32_t W = h->W;
   const int64_t NT = (n_cols + W - 1) / W;
   int32_t T = 0;
-  if (o->n_tiles >= 0) {
-    T = (int32_t)std::min<int64_t>(o->n_tiles, NT);
-  } else if (NT > 0) {
-    int32_t* samp = tmp.get<int32_t>(NT);
-    hipLaunchKernelGGL(k_strided, dim3(nblk(NT, kB)), dim3(kB), 0, st, clen_sorted, (int64_t)W, NT, samp);
+  int32_t ntiles = 0;
+  std::vector<int32_t> starts;  // tiles 1..ntiles-1
+  if (h->xcd_groups > 0 && n_cols > 0) {
+    // head tile [0, min(W, n_cols)), then xcd_groups ranges of equal entries
+    const int64_t head = std::min<int64_t>(W, n_cols);
+    const int64_t m = n_cols - head;
+    int64_t* pre = tmp.get<int64_t>(m + 1);
+    const int64_t rest = excl_scan<int32_t, int64_t>(clen_sorted + head, m, pre, tmp, st);
+    HIPX(hipMemcpyAsync(pre + m, &rest, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    const int G = h->xcd_groups;
+    int64_t* need = tmp.get<int64_t>(G);
+    int64_t* cut = tmp.get<int64_t>(G);
+    std::vector<int64_t> hneed(G, 0), hcut(G, 0);
+    for (int g = 1; g < G; ++g) hneed[g] = (g * rest + G - 1) / G;
+    HIPX(hipMemcpyAsync(need, hneed.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(64), 0, st, (const int64_t*)pre, m + 1, (const int64_t*)need, G,
+                       cut);
     HIPX(hipGetLastError());
-    std::vector<int32_t> hs(NT);
-    HIPX(hipMemcpyAsync(hs.data(), samp, sizeof(int32_t) * NT, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(hcut.data(), cut, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
-    while (T < NT && hs[T] >= 2) ++T;
+    starts.push_back((int32_t)head);
+    for (int g = 1; g < G; ++g) starts.push_back((int32_t)std::max<int64_t>(head + hcut[g], starts.back()));
+    T = 1;
+    ntiles = 1 + G;
+  } else {
+    if (o->n_tiles >= 0) {
+      T = (int32_t)std::min<int64_t>(o->n_tiles, NT);
+    } else if (NT > 0) {
+      int32_t* samp = tmp.get<int32_t>(NT);
+      hipLaunchKernelGGL(k_strided, dim3(nblk(NT, kB)), dim3(kB), 0, st, clen_sorted, (int64_t)W, NT, samp);
+      HIPX(hipGetLastError());
+      std::vector<int32_t> hs(NT);
+      HIPX(hipMemcpyAsync(hs.data(), samp, sizeof(int32_t) * NT, hipMemcpyDeviceToHost, st));
+      HIPX(hipStreamSynchronize(st));
+      while (T < NT && hs[T] >= 2) ++T;
+    }
+    ntiles = (int32_t)(T + ((int64_t)T * W < n_cols ? 1 : 0));
+    for (int t = 1; t < ntiles; ++t) starts.push_back((int32_t)std::min<int64_t>((int64_t)t * W, n_cols));
   }
-  const int32_t ntiles = (int32_t)(T + ((int64_t)T * W < n_cols ? 1 : 0));
   h->T = T;
   h->n_tiles = ntiles;
   h->tile_col_begin.resize(ntiles);
   h->tile_col_end.resize(ntiles);
   for (int t = 0; t < ntiles; ++t) {
-    h->tile_col_begin[t] = (int64_t)t * W;
-    h->tile_col_end[t] = t < T ? std::min<int64_t>((int64_t)(t + 1) * W, n_cols) : n_cols;
+    h->tile_col_begin[t] = t == 0 ? 0 : starts[t - 1];
+    h->tile_col_end[t] = t + 1 < ntiles ? starts[t] : n_cols;
+  }
+  TileMap tmap{W, T, nullptr, 0};
+  if (h->xcd_groups > 0 && ntiles > 1) {
+    int32_t* d_starts = tmp.get<int32_t>(ntiles - 1);
+    HIPX(hipMemcpyAsync(d_starts, starts.data(), sizeof(int32_t) * (ntiles - 1), hipMemcpyHostToDevice, st));
+    tmap = TileMap{W, T, d_starts, ntiles - 1};
   }
 
   // ---- a4: bucket entries by tile (stable)
@@ -721,7 +787,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
         const int s = p & 1;
         if (!bv[s]) bv[s] = tmp.get<float>(nnz);
         const int nb = std::min(8, tb - sh);
-        cs_pass(TileOp{ci, cv, cr, bi[s], bv[s], br[s], W, T, sh}, nnz, nb, tmp, st);
+        cs_pass(TileOp{ci, cv, cr, bi[s], bv[s], br[s], tmap, sh}, nnz, nb, tmp, st);
         ci = bi[s];
         cr = br[s];
         cv = bv[s];
@@ -731,7 +797,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       b_val = (float*)cv;
     }
     int64_t* d_ts = tmp.get<int64_t>(ntiles + 1);
-    hipLaunchKernelGGL(k_tile_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, b_icol, nnz, W, T, ntiles, d_ts);
+    hipLaunchKernelGGL(k_tile_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, b_icol, nnz, tmap, ntiles, d_ts);
     HIPX(hipGetLastError());
     HIPX(hipMemcpyAsync(tstart.data(), d_ts, sizeof(int64_t) * (ntiles + 1), hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
@@ -760,14 +826,14 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   if (nnz > 0) {
     int32_t* flags = tmp.get<int32_t>(nnz);
     int32_t* pos = tmp.get<int32_t>(nnz);
-    hipLaunchKernelGGL(k_seg_flags, dim3(nblk(nnz, kB)), dim3(kB), 0, st, b_icol, b_row, nnz, W, T, flags);
+    hipLaunchKernelGGL(k_seg_flags, dim3(nblk(nnz, kB)), dim3(kB), 0, st, b_icol, b_row, nnz, tmap, flags);
     HIPX(hipGetLastError());
     nseg = excl_scan<int32_t, int32_t>(flags, nnz, pos, tmp, st);
     int32_t* seg_start = tmp.get<int32_t>(nseg);
     int32_t* seg_row = tmp.get<int32_t>(nseg);
     int32_t* seg_tile = tmp.get<int32_t>(nseg);
     int32_t* seg_len = tmp.get<int32_t>(nseg);
-    hipLaunchKernelGGL(k_seg_emit, dim3(nblk(nnz, kB)), dim3(kB), 0, st, flags, pos, b_icol, b_row, rowmap, nnz, W, T,
+    hipLaunchKernelGGL(k_seg_emit, dim3(nblk(nnz, kB)), dim3(kB), 0, st, flags, pos, b_icol, b_row, rowmap, nnz, tmap,
                        seg_start, seg_row, seg_tile);
     HIPX(hipGetLastError());
     hipLaunchKernelGGL(k_seg_len, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_start, nseg, nnz, seg_len);
@@ -863,6 +929,9 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     partition_tile(runs, WLt, t, trow[t], pp, &wls);
   }
   h->tile_wl_begin[ntiles] = (int64_t)wls.size();
+  h->d_tile_wl_begin = hold<int64_t>(h, ntiles + 1);
+  HIPX(hipMemcpyAsync(h->d_tile_wl_begin, h->tile_wl_begin.data(), sizeof(int64_t) * (ntiles + 1),
+                      hipMemcpyHostToDevice, st));
   const int64_t nwl = (int64_t)wls.size();
   h->n_wl = nwl;
 
@@ -958,6 +1027,20 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
                        (const int32_t*)ep, n_rows, h->d_empty);
     HIPX(hipGetLastError());
   }
+  if (h->xcd_groups > 0 && n_rows > 0) {
+    // rows tile 0 does not write: zeroed before the private copies are added
+    int32_t* zf = tmp.get<int32_t>(n_rows);
+    int32_t* zp = tmp.get<int32_t>(n_rows);
+    hipLaunchKernelGGL(k_ne, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, (const int32_t*)first, n_rows, 0, zf);
+    HIPX(hipGetLastError());
+    h->n_zero0 = excl_scan<int32_t, int32_t>(zf, n_rows, zp, tmp, st);
+    h->d_zero0 = hold<int32_t>(h, h->n_zero0);
+    hipLaunchKernelGGL(k_compact_idx, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, (const int32_t*)zf,
+                       (const int32_t*)zp, n_rows, h->d_zero0);
+    HIPX(hipGetLastError());
+    h->d_ypriv = hold<float>(h, (int64_t)h->xcd_groups * n_rows);
+    HIPX(hipMemsetAsync(h->d_ypriv, 0, sizeof(float) * (size_t)h->xcd_groups * n_rows, st));
+  }
   h->d_split = hold<SplitRow>(h, (int64_t)srows.size());
   h->d_partial = hold<double>(h, std::max<int64_t>(h->n_slots, 1) * 256);
   if (!srows.empty())
@@ -1013,7 +1096,7 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
     set_error("tc_build_tiled: NULL CSR array");
     return TC_EINVAL;
   }
-  if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->max_act_warp < 0 || o->wl_policy < 0 ||
+  if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->xcd_groups < 0 || o->xcd_groups > 64 || o->max_act_warp < 0 || o->wl_policy < 0 ||
       o->wl_policy > 2 || (o->wl_policy == 1 && !o->wl_per_tile) || (o->relabel > 0 && A->n_rows != A->n_cols)) {
     set_error("tc_build_tiled: invalid option");
     return TC_EINVAL;
@@ -1032,6 +1115,7 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   h->camping_pad = o->camping_pad != 0;
   h->relabel = o->relabel < 0 ? (A->n_rows == A->n_cols) : (o->relabel != 0);
   h->max_act_warp = o->max_act_warp > 0 ? o->max_act_warp : 8192;
+  h->xcd_groups = o->xcd_groups;
   h->alloc = o->alloc;
   h->dfree = o->free;
   h->alloc_ctx = o->alloc_ctx;

@@ -126,6 +126,13 @@ struct tc_handle {
   unsigned long long* d_counters = nullptr;  // per-tile work counters of the persistent pass
   int32_t* d_empty = nullptr;       // internal rows without any entry (zeroed by every product)
   int64_t n_empty = 0;
+  // XCD schedule: tile 0 on every XCD, tiles 1..xcd_groups at once, tile g
+  // pinned to the workgroups that land on XCD g-1, each writing its own y copy
+  int32_t xcd_groups = 0;
+  float* d_ypriv = nullptr;         // xcd_groups x n_rows, rows a tile never writes stay 0
+  int32_t* d_zero0 = nullptr;       // rows tile 0 does not write (zeroed before the combine)
+  int64_t* d_tile_wl_begin = nullptr;  // device copy of tile_wl_begin
+  int64_t n_zero0 = 0;
   int n_cu = 256;                   // compute units of the device
   int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
 

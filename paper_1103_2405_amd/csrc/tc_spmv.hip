@@ -282,6 +282,14 @@ struct StagedX {
   __device__ void addy(float* y, int32_t row, double s) const { addy_policy<true>(y, row, s); }
 };
 
+// ... or writing a private copy of y: every row of a tile is written once,
+// so the copy is stored whatever the first-writer flag says.
+struct PrivX {
+  const float* __restrict__ x;
+  __device__ float operator()(int32_t i) const { return x[i]; }
+  __device__ void addy(float* y, int32_t rid, double s) const { y[rid & ~kAddFlag] = (float)s; }
+};
+
 template <class G>
 __device__ inline void run_workload(const Wl& d, int lane, const int32_t* __restrict__ idx,
                                     const float* __restrict__ val, const int32_t* __restrict__ rowid, const G& x,
@@ -318,6 +326,34 @@ __global__ void __launch_bounds__(kB) k_tile_spmv(const Wl* __restrict__ wl, int
   run_workload(d, lane, idx, val, rowid, GlobalX<YNT>{x}, y, partial);
 }
 
+// Concurrent pass over tiles 1..G of the XCD schedule.  Workgroups are
+// dispatched round-robin over the 8 XCDs, so block b runs on XCD b % 8: tile
+// 1 + (b % G) takes blocks b with that residue, and its x range stays in one
+// XCD's L2.  Each tile writes its own copy of y (ypriv + g * n_rows).
+__global__ void __launch_bounds__(kB) k_tile_xcd(const Wl* __restrict__ wl, const int64_t* __restrict__ wl_begin,
+                                                 int32_t G, const int32_t* __restrict__ idx,
+                                                 const float* __restrict__ val, const int32_t* __restrict__ rowid,
+                                                 const float* __restrict__ x, float* __restrict__ ypriv, int64_t n_rows,
+                                                 double* __restrict__ partial) {
+  const int lane = lane_id();
+  const int32_t g = blockIdx.x % G;
+  const int64_t jb = blockIdx.x / G;
+  const int64_t b = wl_begin[g], e = wl_begin[g + 1];
+  const int64_t j = b + jb * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (j >= e) return;
+  const Wl d = wl[j];
+  run_workload(d, lane, idx, val, rowid, PrivX{x}, ypriv + (int64_t)g * n_rows, partial);
+}
+
+// y[r] += sum over g of ypriv[g][r], in g order (rows tile 0 did not write were zeroed).
+__global__ void k_combine_priv(float* __restrict__ y, const float* __restrict__ ypriv, int64_t n, int32_t G) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = (double)y[r];
+  for (int32_t g = 0; g < G; ++g) s += (double)ypriv[(int64_t)g * n + r];
+  y[r] = (float)s;
+}
+
 // Persistent tile pass: a few workgroups per CU stage the tile's hot x head
 // [cb, cb + lw) in LDS, then every wavefront takes workloads from the tile's
 // counter until none is left (each wavefront leaves once the counter passes
@@ -346,13 +382,13 @@ __global__ void __launch_bounds__(kPB) k_tile_persist(const Wl* __restrict__ wl,
 // Sum of every split row's chunks in (tile, chunk) order, added to y (or
 // stored when no tile wrote the row).
 __global__ void k_split_combine(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
-                                float* __restrict__ y) {
+                                float* __restrict__ y, int force_add) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const SplitRow s = sr[i];
   double acc = 0.0;
   for (int32_t q = 0; q < s.n_slots; ++q) acc += partial[s.slot_begin + q];
-  if (s.store)
+  if (s.store && !force_add)
     y[s.row] = (float)acc;
   else
     add_to_y(y, s.row, acc);
@@ -530,14 +566,23 @@ __global__ void k_finish(const double* __restrict__ parts, int nparts, int nv, d
 // PageRank update (Eq. 6 with uniform dangling mass), fused with the L1
 // change and the dangling mass of the new iterate:
 //   p'_i = c (y_i + d/n) + (1-c)/n
-__global__ void __launch_bounds__(kB) k_pr_update(const float* __restrict__ y, float* __restrict__ p, int64_t n,
-                                                  int64_t dang_begin, double c, const double* __restrict__ dmass,
+// (ypriv, G): private copies of y of the XCD schedule still to be added, in
+// g order, to y (G = 0 when there are none).
+__global__ void __launch_bounds__(kB) k_pr_update(const float* __restrict__ y, const float* __restrict__ ypriv,
+                                                  int32_t G, float* __restrict__ p, int64_t n, int64_t dang_begin,
+                                                  double c, const double* __restrict__ dmass,
                                                   double* __restrict__ parts) {
   const double dn = *dmass / (double)n;
   const double tele = (1.0 - c) / (double)n;
   double v[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
-    const float pn = (float)(c * ((double)y[i] + dn) + tele);
+    float yi = y[i];
+    if (G > 0) {
+      double s = (double)yi;
+      for (int32_t g = 0; g < G; ++g) s += (double)ypriv[(int64_t)g * n + i];
+      yi = (float)s;
+    }
+    const float pn = (float)(c * ((double)yi + dn) + tele);
     v[0] += fabs((double)pn - (double)p[i]);
     if (i >= dang_begin) v[1] += (double)pn;
     p[i] = pn;
@@ -714,15 +759,19 @@ TileConfig tile_config() {
 }
 
 // y := A x in internal ids (x: n_cols, y: n_rows)
-void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st) {
+// fuse_combine: in the XCD schedule, leave y without the private copies (the
+// caller adds them in its own pass); split rows are then added to y first.
+void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine = false) {
   const TileConfig cfg = tile_config();
-  const int64_t nz = std::max<int64_t>(h->n_empty, h->n_tiles);
+  const bool xcd = h->xcd_groups > 0 && h->n_tiles > 1;
+  const int64_t nzero = xcd ? h->n_zero0 : h->n_empty;
+  const int64_t nz = std::max<int64_t>(nzero, h->n_tiles);
   if (nz > 0) {
-    hipLaunchKernelGGL(k_begin_spmv, dim3(nblk(nz, kB)), dim3(kB), 0, st, y, (const int32_t*)h->d_empty, h->n_empty,
-                       h->d_counters, (int32_t)h->n_tiles);
+    hipLaunchKernelGGL(k_begin_spmv, dim3(nblk(nz, kB)), dim3(kB), 0, st, y,
+                       (const int32_t*)(xcd ? h->d_zero0 : h->d_empty), nzero, h->d_counters, (int32_t)h->n_tiles);
     HIPC(hipGetLastError());
   }
-  for (int t = 0; t < h->n_tiles; ++t) {
+  for (int t = 0; t < (xcd ? 1 : h->n_tiles); ++t) {
     const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];
     if (e == b) continue;
     if (cfg.persist) {
@@ -741,9 +790,24 @@ void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st) {
                   (const int32_t*)h->d_rowid, x, y, h->d_partial);
     }
   }
+  if (xcd) {
+    const int32_t G = h->n_tiles - 1;
+    int64_t maxb = 0;
+    for (int g = 1; g <= G; ++g)
+      maxb = std::max<int64_t>(maxb, (h->tile_wl_begin[g + 1] - h->tile_wl_begin[g] + kWpb - 1) / kWpb);
+    if (maxb > 0)
+      launch_tile(h, k_tile_xcd, dim3((unsigned)(maxb * G)), dim3(kB), 0, st, (const Wl*)h->d_wl,
+                  (const int64_t*)(h->d_tile_wl_begin + 1), G, (const int32_t*)h->d_idx, (const float*)h->d_val,
+                  (const int32_t*)h->d_rowid, x, h->d_ypriv, h->n_rows, h->d_partial);
+    if (h->n_rows > 0 && !fuse_combine) {
+      hipLaunchKernelGGL(k_combine_priv, dim3(nblk(h->n_rows, kB)), dim3(kB), 0, st, y, (const float*)h->d_ypriv,
+                         h->n_rows, G);
+      HIPC(hipGetLastError());
+    }
+  }
   if (h->n_split_rows > 0) {
     hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
-                       h->n_split_rows, h->d_partial, y);
+                       h->n_split_rows, h->d_partial, y, xcd ? 1 : 0);
     HIPC(hipGetLastError());
   }
   h->spmv_calls++;
@@ -897,10 +961,12 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
       hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)(parts + kRedBlocks), kRedBlocks, 1,
                          res + 1);
       HIPC(hipGetLastError());
+      const bool xcd = h->xcd_groups > 0 && h->n_tiles > 1;
+      const int32_t G = xcd ? h->n_tiles - 1 : 0;
       for (it = 0; it < max_iter;) {
-        spmv_internal(h, p, y, st);
-        hipLaunchKernelGGL(k_pr_update, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)y, p, n,
-                           n - h->n_dangling, (double)c, (const double*)(res + 1), parts);
+        spmv_internal(h, p, y, st, xcd);
+        hipLaunchKernelGGL(k_pr_update, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)y, (const float*)h->d_ypriv,
+                           G, p, n, n - h->n_dangling, (double)c, (const double*)(res + 1), parts);
         HIPC(hipGetLastError());
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)parts, kRedBlocks, 2, res);
         HIPC(hipGetLastError());

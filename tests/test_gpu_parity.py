@@ -49,14 +49,16 @@ def assert_same_format(g, r):
 
 
 def build_both(csr, W, wl=None, S=64, split_len=-1, n_tiles=-1, camping_pad=False, table_path=None,
-               max_act_warp=8192):
+               max_act_warp=8192, xcd_groups=0):
     say("build", csr[0], csr[1], len(csr[3]), "W", W, "wl", wl if not isinstance(wl, list) else wl[:3], "S", S,
         "split", split_len)
     wl_list = wl if wl is None or isinstance(wl, list) else [wl] * 4096
     ref = rf.build(csr, W=W, n_tiles=n_tiles, wl=wl_list, S=S, split_len=split_len, camping_pad=camping_pad,
-                   table=PerfTable.load(table_path) if table_path else None, max_act_warp=max_act_warp)
+                   table=PerfTable.load(table_path) if table_path else None, max_act_warp=max_act_warp,
+                   xcd_groups=xcd_groups)
     gm = TiledMatrix(csr, tile_width=W, n_tiles=n_tiles, wl=wl, wave=S, split_len=split_len,
-                     camping_pad=camping_pad, perf_table=table_path, max_act_warp=max_act_warp)
+                     camping_pad=camping_pad, perf_table=table_path, max_act_warp=max_act_warp,
+                     xcd_groups=xcd_groups)
     return gm, ref
 
 
@@ -137,6 +139,33 @@ def test_autotuned_workload_sizes_match_reference(tmp_path):
         assert len(set(ref["tile_wl"])) > 1
         assert_same_format(fmt, ref)
         check_spmv(gm, csr, gg.uniform_f32(g.n, 5))
+
+
+@pytest.mark.parametrize("W,groups,split", [(1024, 8, -1), (256, 3, 64), (4096, 8, 0)])
+def test_xcd_schedule_format_and_products(W, groups, split):
+    """XCD schedule: head tile plus column ranges of equal entries, bit-exact
+    format; products, SpMM and PageRank through the concurrent pinned pass."""
+    g = gg.rmat(14, 16, seed=14)
+    csr = gg.pagerank_matrix(g)
+    gm, ref = build_both(csr, W=W, wl=512, split_len=split, xcd_groups=groups)
+    fmt = gm.export_format()
+    assert fmt["xcd_groups"] == groups and fmt["n_tiles_total"] == groups + 1
+    assert_same_format(fmt, ref)
+    x = gg.uniform_f32(g.n, 7)
+    check_spmv(gm, csr, x)
+    X = np.stack([gg.uniform_f32(g.n, 20 + q) for q in range(4)], axis=1)
+    Y = gm.spmm(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Y - oracle.spmm(csr, X)) <= TOL * oracle.spmm(
+        (csr[0], csr[1], csr[2], csr[3], np.abs(csr[4])), np.abs(X)))
+    p, it, res = gm.pagerank(0.85, 0.0, 30)
+    pref, _, _ = oracle.pagerank(csr, 0.85, 0.0, 30)
+    assert np.abs(p.cpu().numpy().astype(np.float64) - pref).sum() <= 1e-6
+
+
+def test_xcd_schedule_dyadic_bit_exact():
+    csr = gg.random_csr(3000, 3000, 0.004, 5, values="dyadic", power=1.2)
+    x = ((np.arange(3000) * 5) % 7 - 3).astype(np.float32)
+    check_spmv(TiledMatrix(csr, tile_width=64, wl=300, split_len=16, xcd_groups=8), csr, x, exact=True)
 
 
 # ------------------------------------------------------------------- SpMV

@@ -77,9 +77,10 @@ def check_invariants(csr, fmt):
     b, e = fmt["tile_col_begin"], fmt["tile_col_end"]
     if len(b):
         assert b[0] == 0 and e[-1] == n_cols and np.all(b[1:] == e[:-1])
-    for t in range(fmt["T"]):
-        assert b[t] == t * fmt["W"]
-        assert cs[b[t]] >= 2 or fmt["T"] == 0
+    if not fmt.get("xcd_groups"):
+        for t in range(fmt["T"]):
+            assert b[t] == t * fmt["W"]
+            assert cs[b[t]] >= 2 or fmt["T"] == 0
     # per-tile rows sorted by decreasing length, ties by increasing row id
     for t in range(fmt["n_tiles_total"]):
         L = fmt["rows_len"][fmt["tile_row_off"][t]:fmt["tile_row_off"][t + 1]]
@@ -208,3 +209,24 @@ def test_partition_camping_pad():
     # every workload is 64 x 8 = 512 floats, so 64 pad floats follow each one
     assert np.all(np.diff(fmt["wl_data_off"]) == 512 + 64)
     check_invariants(csr, fmt)
+
+
+@pytest.mark.parametrize("seed,W,groups", [(0, 16, 8), (1, 1, 4), (2, 500, 8), (3, 40, 3)])
+def test_xcd_column_ranges(seed, W, groups):
+    """Head tile [0, W) then `groups` column ranges of (nearly) equal entries:
+    every range's entry count is within one column length of rest / groups."""
+    csr = gg.random_csr(400, 400, 0.02, seed, power=1.2)
+    fmt = rf.build(csr, W=W, wl=[64] * 20, S=64, split_len=-1, xcd_groups=groups)
+    check_invariants(csr, fmt)
+    b, e, nz = fmt["tile_col_begin"], fmt["tile_col_end"], fmt["tile_nnz"]
+    assert len(b) == groups + 1 and b[0] == 0 and e[0] == min(W, 400)
+    cs = fmt["clen"][fmt["cperm"].astype(np.int64)]
+    rest = int(cs[e[0]:].sum())
+    for g in range(1, groups + 1):
+        # prefix of the rest at the end of range g reaches ceil(g * rest / groups) at the first column
+        pre_end = int(cs[e[0]:e[g]].sum())
+        assert pre_end >= min(rest, -(-(g * rest) // groups)) or e[g] == 400
+        if e[g] > e[0]:
+            assert int(cs[e[0]:e[g] - 1].sum()) < -(-(g * rest) // groups) or g == groups
+    x = gg.uniform_f32(400, seed)
+    assert np.allclose(rf.spmv_format(fmt, x), oracle.spmv(csr, x), rtol=1e-12, atol=1e-14)
