@@ -223,8 +223,16 @@ tc_status tc_set_timing(tc_handle* h, int32_t enable);
 /* Read the totals (synchronises the handle's pending events). */
 tc_status tc_get_timing(tc_handle* h, tc_timing* t);
 
-/* Release the handle and all its device memory (waits for the device). */
+/* Release the handle and all its device memory (waits for the device).  The
+ * memory goes back to the library's device pool, where later builds on the
+ * same device reuse it. */
 void tc_destroy(tc_handle* h);
+
+/* Return every block cached in the library's device pool to HIP (all
+ * devices; synchronous).  Handles still alive keep their memory.  Returns the
+ * number of bytes released.  Setting TC_POOL=0 in the environment before the
+ * first call disables the pool (every release then goes straight to hipFree). */
+size_t tc_release_cached_memory(void);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* tc_last_error(void);

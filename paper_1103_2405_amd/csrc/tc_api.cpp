@@ -150,9 +150,11 @@ extern "C" void tc_destroy(tc_handle* h) {
     if (h->dfree)
       h->dfree(p, h->alloc_ctx);
     else
-      (void)hipFree(p);
+      tc::pool_free(p, nullptr, true);
   }
-  if (h->d_ws) (void)hipFree(h->d_ws);
+  if (h->d_ws) tc::pool_free(h->d_ws, nullptr, true);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
 }
+
+extern "C" size_t tc_release_cached_memory(void) { return tc::pool_release_cached(); }

@@ -14,6 +14,8 @@
 // pure function of the input and the options.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -50,29 +52,30 @@ struct Fail {
   } while (0)
 
 // Temporary device buffers of one build, freed when the build ends.
+// Temporary device arrays of one build, taken from the library's pool on the
+// build stream and handed back (stream-ordered) when released or at the end.
 struct Tmp {
+  hipStream_t st;
   std::vector<void*> bufs;
+  explicit Tmp(hipStream_t s) : st(s) {}
   template <class T>
   T* get(int64_t n) {
-    void* p = nullptr;
     size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      throw Fail{TC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
-    }
+    void* p = pool_alloc(bytes, st);
+    if (!p) throw Fail{TC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
     bufs.push_back(p);
     return (T*)p;
   }
   void release(void* p) {
     for (auto& b : bufs)
       if (b == p) {
-        (void)hipFree(b);
+        pool_free(b, st, false);
         b = nullptr;
       }
   }
   ~Tmp() {
     for (void* p : bufs)
-      if (p) (void)hipFree(p);
+      if (p) pool_free(p, st, false);
   }
 };
 
@@ -83,8 +86,7 @@ T* hold(tc_handle* h, int64_t n) {
   if (h->alloc) {
     p = h->alloc(bytes, h->alloc_ctx);
     if (!p) throw Fail{TC_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
-  } else if (hipMalloc(&p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
+  } else if (!(p = pool_alloc(bytes, h->stream))) {
     throw Fail{TC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
   }
   h->owned.push_back(p);
@@ -128,15 +130,27 @@ __global__ void k_col_sample(const int32_t* __restrict__ col, int64_t nnz, int32
   if (k < nnz) atomicAdd(&samp[col[k]], 1);
 }
 
-// number of columns whose sampled count is >= 2^b, for b = 0..31
-__global__ void k_sample_hist(const int32_t* __restrict__ samp, int64_t n, unsigned long long* __restrict__ ge) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t v = i < n ? samp[i] : 0;
-  for (int b = 0; b < 31; ++b) {
-    const uint64_t m = __ballot(v >= (1 << b));
-    if (lane_id() == 0 && m) atomicAdd(&ge[b], (unsigned long long)__popcll(m));
-    if (!m) break;
+// number of columns whose sampled count is >= 2^b, for b = 0..31:
+// grid-stride, per-wave ballot counts summed in LDS, one atomic per block and b
+__global__ void __launch_bounds__(256) k_sample_hist(const int32_t* __restrict__ samp, int64_t n,
+                                                     unsigned long long* __restrict__ ge) {
+  __shared__ unsigned int bc[32];
+  if (threadIdx.x < 32) bc[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned int acc[31];
+#pragma unroll
+  for (int b = 0; b < 31; ++b) acc[b] = 0;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const int32_t v = i < n ? samp[i] : 0;
+#pragma unroll
+    for (int b = 0; b < 31; ++b) acc[b] += (unsigned int)__popcll(__ballot(v >= (1 << b)));
   }
+  if (lane_id() == 0)
+    for (int b = 0; b < 31; ++b)
+      if (acc[b]) atomicAdd(&bc[b], acc[b]);
+  __syncthreads();
+  if (threadIdx.x < 31 && bc[threadIdx.x]) atomicAdd(&ge[threadIdx.x], (unsigned long long)bc[threadIdx.x]);
 }
 
 __global__ void k_ge_flags(const int32_t* __restrict__ samp, int64_t n, int32_t thr, int32_t* __restrict__ flags) {
@@ -178,6 +192,62 @@ __global__ void __launch_bounds__(256) k_col_count_hot(const int32_t* __restrict
   __syncthreads();
   for (int i = threadIdx.x; i < kHotSlots; i += blockDim.x)
     if (key[i] != -1 && cnt[i]) atomicAdd(&clen[key[i]], cnt[i]);
+}
+
+// a1, bucketed: a counting-sort pass groups the column ids by their high
+// bits, then each block counts one window of kCntWin columns of one bucket
+// (a slice of its ids) in LDS and writes the window's lengths: plain stores
+// when the bucket is one slice, atomics on the few buckets that need several.
+constexpr int kCntWin = 32768;  // 128 KB of LDS counters
+constexpr int kCntBlock = 1024;
+constexpr int64_t kCntSlice = 1 << 20;
+
+struct ColBucketOp {
+  const int32_t* cin;
+  int32_t* cout;
+  int shift;
+  __device__ uint32_t bucket(int64_t k) const { return (uint32_t)cin[k] >> shift; }
+  __device__ void move(int64_t k, int64_t p) const { cout[p] = cin[k]; }
+};
+
+struct CntTask {
+  int64_t begin, end;  // slice of the bucketed ids
+  int32_t base;        // first column of the window
+  int32_t atomic;      // several slices share the window
+};
+
+__global__ void __launch_bounds__(kCntBlock) k_col_count_lds(const int32_t* __restrict__ bcol,
+                                                             const CntTask* __restrict__ tasks, int64_t n_cols,
+                                                             int32_t* __restrict__ clen) {
+  extern __shared__ int32_t cnt_lds[];
+  const CntTask t = tasks[blockIdx.x];
+  for (int i = threadIdx.x; i < kCntWin; i += kCntBlock) cnt_lds[i] = 0;
+  __syncthreads();
+  int64_t k = t.begin + threadIdx.x;
+  for (; k + 7 * kCntBlock < t.end; k += 8 * kCntBlock) {  // eight loads in flight
+    int32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = bcol[k + u * kCntBlock];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t c = (uint32_t)(v[u] - t.base);
+      if (c < (uint32_t)kCntWin) atomicAdd(&cnt_lds[c], 1);
+    }
+  }
+  for (; k < t.end; k += kCntBlock) {
+    const uint32_t c = (uint32_t)(bcol[k] - t.base);
+    if (c < (uint32_t)kCntWin) atomicAdd(&cnt_lds[c], 1);
+  }
+  __syncthreads();
+  const int64_t lim = min<int64_t>(kCntWin, n_cols - t.base);
+  for (int i = threadIdx.x; i < lim; i += kCntBlock) {
+    const int32_t v = cnt_lds[i];
+    if (t.atomic) {
+      if (v) atomicAdd(&clen[t.base + i], v);
+    } else {
+      clen[t.base + i] = v;
+    }
+  }
 }
 
 // maximum of a non-negative array: grid-stride, one atomic per block
@@ -253,6 +323,12 @@ __global__ void k_strided(const int32_t* __restrict__ a, int64_t stride, int64_t
 
 // Row id of every entry: lanes write their own short rows, the whole
 // wavefront writes each long row.
+// out[i] = a[i * stride] for i < n
+__global__ void k_strided64(const int64_t* __restrict__ a, int64_t stride, int64_t n, int64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i * stride];
+}
+
 __global__ void k_expand_rows(const int64_t* __restrict__ rp, int64_t n_rows, int32_t* __restrict__ row_of) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = lane_id();
@@ -336,6 +412,29 @@ __global__ void k_seg_emit(const int32_t* __restrict__ flags, const int32_t* __r
   seg_start[s] = (int32_t)k;
   seg_row[s] = rowmap[b_row[k]];
   seg_tile[s] = tm(b_icol[k]);
+}
+
+// a5 with one tile: internal row i is a segment if its original row is non-empty
+__global__ void k_rowseg_flags(const int64_t* __restrict__ rp, const int32_t* __restrict__ rowinv, int64_t n_rows,
+                               int32_t* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  const int32_t o = rowinv[i];
+  flags[i] = rp[o + 1] > rp[o];
+}
+
+__global__ void k_rowseg_emit(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos,
+                              const int64_t* __restrict__ rp, const int32_t* __restrict__ rowinv, int64_t n_rows,
+                              int32_t* __restrict__ seg_start, int32_t* __restrict__ seg_row,
+                              int32_t* __restrict__ seg_tile, int32_t* __restrict__ seg_len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows || !flags[i]) return;
+  const int32_t s = pos[i], o = rowinv[i];
+  const int64_t a = rp[o];
+  seg_start[s] = (int32_t)a;
+  seg_row[s] = (int32_t)i;
+  seg_tile[s] = 0;
+  seg_len[s] = (int32_t)(rp[o + 1] - a);
 }
 
 __global__ void k_seg_len(const int32_t* __restrict__ seg_start, int64_t nseg, int64_t nnz, int32_t* __restrict__ seg_len) {
@@ -595,9 +694,117 @@ int32_t dev_max(const int32_t* a, int64_t n, Tmp& tmp, hipStream_t st) {
 
 int64_t ceil_to(int64_t v, int64_t s) { return (v + s - 1) / s * s; }
 
+// a1 for small inputs and very wide matrices: global atomics, with the
+// hottest columns (found from a 1/64 sample) counted in a per-block LDS table.
+void col_count_atomic(const int32_t* col_idx, int64_t nnz, int64_t n_cols, int32_t* clen, Tmp& tmp, hipStream_t st) {
+  int32_t n_hot = 0;
+  int32_t* hot = nullptr;
+  if (nnz >= (int64_t)kSampleStep * 1024) {
+    int32_t* samp = tmp.get<int32_t>(n_cols);
+    unsigned long long* ge = tmp.get<unsigned long long>(32);
+    HIPX(hipMemsetAsync(samp, 0, sizeof(int32_t) * n_cols, st));
+    HIPX(hipMemsetAsync(ge, 0, sizeof(unsigned long long) * 32, st));
+    const int64_t ns = (nnz + kSampleStep - 1) / kSampleStep;
+    hipLaunchKernelGGL(k_col_sample, dim3(nblk(ns, kB)), dim3(kB), 0, st, col_idx, nnz, samp);
+    hipLaunchKernelGGL(k_sample_hist, dim3((unsigned)std::min<int64_t>(1024, nblk(n_cols, 256))), dim3(256), 0, st,
+                       (const int32_t*)samp, n_cols, ge);
+    HIPX(hipGetLastError());
+    unsigned long long hge[32];
+    HIPX(hipMemcpyAsync(hge, ge, sizeof(hge), hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    int b = 2;  // at least 4 sampled hits (about 256 entries) to be worth a slot
+    while (b < 31 && hge[b] > (unsigned long long)kHotCap) ++b;
+    if (b < 31 && hge[b] > 0) {
+      int32_t* fl = tmp.get<int32_t>(n_cols);
+      int32_t* ps = tmp.get<int32_t>(n_cols);
+      hipLaunchKernelGGL(k_ge_flags, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, (const int32_t*)samp, n_cols,
+                         (int32_t)1 << b, fl);
+      HIPX(hipGetLastError());
+      n_hot = (int32_t)excl_scan<int32_t, int32_t>(fl, n_cols, ps, tmp, st);
+      hot = tmp.get<int32_t>(n_hot);
+      hipLaunchKernelGGL(k_compact_idx, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, (const int32_t*)fl,
+                         (const int32_t*)ps, n_cols, hot);
+      HIPX(hipGetLastError());
+    }
+  }
+  if (nnz > 0) {
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, nblk(nnz, kB));
+    hipLaunchKernelGGL(k_col_count_hot, dim3(grid), dim3(256), 0, st, col_idx, nnz, (const int32_t*)hot, n_hot, clen);
+    HIPX(hipGetLastError());
+  }
+}
+
+// a1 for everything else: see k_col_count_lds
+void col_count_bucketed(const int32_t* col, int64_t nnz, int64_t n_cols, int cshift, int64_t windows, int32_t* clen,
+                        Tmp& tmp, hipStream_t st) {
+  const int nbits = 8, nb = 1 << nbits;
+  const int64_t chunk = 4096;
+  const int64_t nchunks = (nnz + chunk - 1) / chunk;
+  const unsigned grid = (unsigned)((nchunks + kCsWaves - 1) / kCsWaves);
+  int32_t* bcol = tmp.get<int32_t>(nnz);
+  int32_t* hist = tmp.get<int32_t>((int64_t)nb * nchunks);
+  int64_t* offs = tmp.get<int64_t>((int64_t)nb * nchunks + 1);
+  const ColBucketOp op{col, bcol, cshift};
+  hipLaunchKernelGGL((k_cs_hist<ColBucketOp>), dim3(grid), dim3(kCsBlock), kCsWaves * nb * sizeof(int32_t), st, op, nnz,
+                     nb, chunk, nchunks, hist);
+  HIPX(hipGetLastError());
+  excl_scan<int32_t, int64_t>(hist, (int64_t)nb * nchunks, offs, tmp, st);
+  hipLaunchKernelGGL((k_cs_scatter<ColBucketOp>), dim3(grid), dim3(kCsBlock), kCsWaves * nb * sizeof(int64_t), st, op,
+                     nnz, nb, nbits, chunk, nchunks, (const int64_t*)offs);
+  HIPX(hipGetLastError());
+  // bucket starts: offs[b * nchunks]
+  int64_t* d_bs = tmp.get<int64_t>(nb);
+  hipLaunchKernelGGL(k_strided64, dim3(1), dim3(nb), 0, st, (const int64_t*)offs, nchunks, (int64_t)nb, d_bs);
+  HIPX(hipGetLastError());
+  std::vector<int64_t> bs(nb + 1);
+  HIPX(hipMemcpyAsync(bs.data(), d_bs, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, st));
+  HIPX(hipStreamSynchronize(st));
+  bs[nb] = nnz;
+  std::vector<CntTask> tasks;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t len = bs[b + 1] - bs[b];
+    if (len == 0) continue;
+    const int64_t ns = (len + kCntSlice - 1) / kCntSlice;
+    for (int64_t w = 0; w < windows; ++w) {
+      const int64_t base = ((int64_t)b << cshift) + w * kCntWin;
+      if (base >= n_cols) break;
+      for (int64_t j = 0; j < ns; ++j)
+        tasks.push_back(CntTask{bs[b] + len * j / ns, bs[b] + len * (j + 1) / ns, (int32_t)base, ns > 1 ? 1 : 0});
+    }
+  }
+  if (tasks.empty()) return;
+  CntTask* d_tasks = tmp.get<CntTask>((int64_t)tasks.size());
+  HIPX(hipMemcpyAsync(d_tasks, tasks.data(), sizeof(CntTask) * tasks.size(), hipMemcpyHostToDevice, st));
+  HIPX(hipFuncSetAttribute((const void*)k_col_count_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           kCntWin * (int)sizeof(int32_t)));
+  hipLaunchKernelGGL(k_col_count_lds, dim3((unsigned)tasks.size()), dim3(kCntBlock), kCntWin * sizeof(int32_t), st,
+                     (const int32_t*)bcol, (const CntTask*)d_tasks, n_cols, clen);
+  HIPX(hipGetLastError());
+  // the task list is host memory: finish before it goes out of scope
+  HIPX(hipStreamSynchronize(st));
+}
+
+// TC_BUILD_TRACE=1: synchronise after every phase and print its wall time
+struct PhaseClock {
+  hipStream_t st;
+  bool on;
+  std::chrono::steady_clock::time_point t;
+  explicit PhaseClock(hipStream_t s)
+      : st(s), on(std::getenv("TC_BUILD_TRACE") != nullptr), t(std::chrono::steady_clock::now()) {}
+  void mark(const char* what) {
+    if (!on) return;
+    (void)hipStreamSynchronize(st);
+    const auto n = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "tc build: %-24s %9.3f ms\n", what, std::chrono::duration<double, std::milli>(n - t).count());
+    t = n;
+  }
+};
+
 void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h) {
+  PhaseClock clk(st);
   const int64_t n_rows = A->n_rows, n_cols = A->n_cols, nnz = A->nnz;
-  Tmp tmp;
+  Tmp tmp(st);
+  h->stream = st;
 
   // ---- validation
   {
@@ -614,49 +821,22 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     if (f & 2) throw Fail{TC_EINVAL, "invalid CSR: a column id is outside [0, n_cols)"};
   }
 
+  clk.mark("validation");
   // ---- a1: column lengths
   int32_t* clen = hold<int32_t>(h, n_cols);
   h->d_clen = clen;
-  if (n_cols > 0) {
-    HIPX(hipMemsetAsync(clen, 0, sizeof(int32_t) * n_cols, st));
-    int32_t n_hot = 0;
-    int32_t* hot = nullptr;
-    if (nnz >= (int64_t)kSampleStep * 1024) {
-      int32_t* samp = tmp.get<int32_t>(n_cols);
-      unsigned long long* ge = tmp.get<unsigned long long>(32);
-      HIPX(hipMemsetAsync(samp, 0, sizeof(int32_t) * n_cols, st));
-      HIPX(hipMemsetAsync(ge, 0, sizeof(unsigned long long) * 32, st));
-      const int64_t ns = (nnz + kSampleStep - 1) / kSampleStep;
-      hipLaunchKernelGGL(k_col_sample, dim3(nblk(ns, kB)), dim3(kB), 0, st, A->col_idx, nnz, samp);
-      hipLaunchKernelGGL(k_sample_hist, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, (const int32_t*)samp, n_cols, ge);
-      HIPX(hipGetLastError());
-      unsigned long long hge[32];
-      HIPX(hipMemcpyAsync(hge, ge, sizeof(hge), hipMemcpyDeviceToHost, st));
-      HIPX(hipStreamSynchronize(st));
-      int b = 2;  // at least 4 sampled hits (about 256 entries) to be worth a slot
-      while (b < 31 && hge[b] > (unsigned long long)kHotCap) ++b;
-      if (b < 31 && hge[b] > 0) {
-        int32_t* fl = tmp.get<int32_t>(n_cols);
-        int32_t* ps = tmp.get<int32_t>(n_cols);
-        hipLaunchKernelGGL(k_ge_flags, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, (const int32_t*)samp, n_cols,
-                           (int32_t)1 << b, fl);
-        HIPX(hipGetLastError());
-        n_hot = (int32_t)excl_scan<int32_t, int32_t>(fl, n_cols, ps, tmp, st);
-        hot = tmp.get<int32_t>(n_hot);
-        hipLaunchKernelGGL(k_compact_idx, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, (const int32_t*)fl,
-                           (const int32_t*)ps, n_cols, hot);
-        HIPX(hipGetLastError());
-      }
-    }
-    if (nnz > 0) {
-      const unsigned grid = (unsigned)std::min<int64_t>(2048, nblk(nnz, kB));
-      hipLaunchKernelGGL(k_col_count_hot, dim3(grid), dim3(256), 0, st, A->col_idx, nnz, (const int32_t*)hot, n_hot,
-                         clen);
-      HIPX(hipGetLastError());
-    }
+  if (n_cols > 0) HIPX(hipMemsetAsync(clen, 0, sizeof(int32_t) * n_cols, st));
+  const int cbits = bits_for((uint64_t)(n_cols > 1 ? n_cols - 1 : 0));
+  const int cshift = std::max(15, cbits - 8);  // bucket = column >> cshift (at most 256 buckets)
+  const int64_t windows = (int64_t)1 << (cshift - 15);
+  if (nnz >= 4096 && windows <= 4) {
+    col_count_bucketed(A->col_idx, nnz, n_cols, cshift, windows, clen, tmp, st);
+  } else if (n_cols > 0) {
+    col_count_atomic(A->col_idx, nnz, n_cols, clen, tmp, st);
   }
   const int32_t maxclen = dev_max(clen, n_cols, tmp, st);
 
+  clk.mark("a1 column lengths");
   // ---- a2: stable sort of columns by decreasing length
   int32_t* cperm = hold<int32_t>(h, n_cols);
   int32_t* cpos = hold<int32_t>(h, n_cols);
@@ -698,6 +878,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipGetLastError());
   }
 
+  clk.mark("a2 column sort");
   // ---- a3: Algorithm 1 (or the XCD schedule's column ranges)
   const int32_t W = h->W;
   const int64_t NT = (n_cols + W - 1) / W;
@@ -756,24 +937,26 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     tmap = TileMap{W, T, d_starts, ntiles - 1};
   }
 
+  clk.mark("a3 tiles");
   // ---- a4: bucket entries by tile (stable)
+  // One tile: the entries stay in CSR order, so the caller's values are read
+  // in place and no per-entry row ids are needed (a5 works per row).
+  const bool one_tile = ntiles <= 1;
   int32_t *b_icol = nullptr, *b_row = nullptr;
-  float* b_val = nullptr;
+  const float* b_val = nullptr;
   std::vector<int64_t> tstart(ntiles + 1, 0);
   if (nnz > 0) {
-    int32_t* row_of = tmp.get<int32_t>(nnz);
-    hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, row_of);
-    HIPX(hipGetLastError());
     int32_t* icol = tmp.get<int32_t>(nnz);
     hipLaunchKernelGGL(k_icol, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, cpos, nnz, icol);
     HIPX(hipGetLastError());
     const int tb = bits_for((uint64_t)(ntiles > 1 ? ntiles - 1 : 0));
-    if (tb == 0) {
+    if (one_tile) {
       b_icol = icol;
-      b_row = row_of;
-      b_val = tmp.get<float>(nnz);
-      HIPX(hipMemcpyAsync(b_val, A->val, sizeof(float) * nnz, hipMemcpyDeviceToDevice, st));
+      b_val = A->val;
     } else {
+      int32_t* row_of = tmp.get<int32_t>(nnz);
+      hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, row_of);
+      HIPX(hipGetLastError());
       // LSD passes over 8-bit digits of the tile id; buffers alternate between
       // two sets (the caller's values are only read)
       int32_t* bi[2] = {tmp.get<int32_t>(nnz), icol};
@@ -794,7 +977,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       }
       b_icol = (int32_t*)ci;
       b_row = (int32_t*)cr;
-      b_val = (float*)cv;
+      b_val = cv;
     }
     int64_t* d_ts = tmp.get<int64_t>(ntiles + 1);
     hipLaunchKernelGGL(k_tile_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, b_icol, nnz, tmap, ntiles, d_ts);
@@ -817,6 +1000,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipGetLastError());
   }
 
+  clk.mark("a4 tile buckets");
   // ---- a5: segments (tile, row) and their sort by decreasing length
   int64_t nseg = 0;
   int32_t *rows_sorted = nullptr, *rows_len = nullptr, *srt_start = nullptr;
@@ -824,22 +1008,41 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   std::vector<int64_t> run_pos;
   std::vector<int32_t> run_len;
   if (nnz > 0) {
-    int32_t* flags = tmp.get<int32_t>(nnz);
-    int32_t* pos = tmp.get<int32_t>(nnz);
-    hipLaunchKernelGGL(k_seg_flags, dim3(nblk(nnz, kB)), dim3(kB), 0, st, b_icol, b_row, nnz, tmap, flags);
-    HIPX(hipGetLastError());
-    nseg = excl_scan<int32_t, int32_t>(flags, nnz, pos, tmp, st);
-    int32_t* seg_start = tmp.get<int32_t>(nseg);
-    int32_t* seg_row = tmp.get<int32_t>(nseg);
-    int32_t* seg_tile = tmp.get<int32_t>(nseg);
-    int32_t* seg_len = tmp.get<int32_t>(nseg);
-    hipLaunchKernelGGL(k_seg_emit, dim3(nblk(nnz, kB)), dim3(kB), 0, st, flags, pos, b_icol, b_row, rowmap, nnz, tmap,
-                       seg_start, seg_row, seg_tile);
-    HIPX(hipGetLastError());
-    hipLaunchKernelGGL(k_seg_len, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_start, nseg, nnz, seg_len);
-    HIPX(hipGetLastError());
-    tmp.release(flags);
-    tmp.release(pos);
+    int32_t *seg_start, *seg_row, *seg_tile, *seg_len;
+    if (one_tile) {
+      // one segment per non-empty row, emitted in increasing internal row
+      int32_t* flags = tmp.get<int32_t>(n_rows);
+      int32_t* pos = tmp.get<int32_t>(n_rows);
+      hipLaunchKernelGGL(k_rowseg_flags, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, rowinv, n_rows, flags);
+      HIPX(hipGetLastError());
+      nseg = excl_scan<int32_t, int32_t>(flags, n_rows, pos, tmp, st);
+      seg_start = tmp.get<int32_t>(nseg);
+      seg_row = tmp.get<int32_t>(nseg);
+      seg_tile = tmp.get<int32_t>(nseg);
+      seg_len = tmp.get<int32_t>(nseg);
+      hipLaunchKernelGGL(k_rowseg_emit, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, flags, pos, A->row_ptr, rowinv,
+                         n_rows, seg_start, seg_row, seg_tile, seg_len);
+      HIPX(hipGetLastError());
+      tmp.release(flags);
+      tmp.release(pos);
+    } else {
+      int32_t* flags = tmp.get<int32_t>(nnz);
+      int32_t* pos = tmp.get<int32_t>(nnz);
+      hipLaunchKernelGGL(k_seg_flags, dim3(nblk(nnz, kB)), dim3(kB), 0, st, b_icol, b_row, nnz, tmap, flags);
+      HIPX(hipGetLastError());
+      nseg = excl_scan<int32_t, int32_t>(flags, nnz, pos, tmp, st);
+      seg_start = tmp.get<int32_t>(nseg);
+      seg_row = tmp.get<int32_t>(nseg);
+      seg_tile = tmp.get<int32_t>(nseg);
+      seg_len = tmp.get<int32_t>(nseg);
+      hipLaunchKernelGGL(k_seg_emit, dim3(nblk(nnz, kB)), dim3(kB), 0, st, flags, pos, b_icol, b_row, rowmap, nnz,
+                         tmap, seg_start, seg_row, seg_tile);
+      HIPX(hipGetLastError());
+      hipLaunchKernelGGL(k_seg_len, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_start, nseg, nnz, seg_len);
+      HIPX(hipGetLastError());
+      tmp.release(flags);
+      tmp.release(pos);
+    }
     hipLaunchKernelGGL(k_first_touch, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg,
                        (const int64_t*)d_split_t, first, touched);
     HIPX(hipGetLastError());
@@ -855,7 +1058,9 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     hipLaunchKernelGGL(k_seg_keys, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg, maxlen, lb,
                        rb, k0, v0);
     HIPX(hipGetLastError());
-    for (int sh = 0; sh < lb + rb + tb; sh += 8) {
+    // one tile: the segments already come in increasing row (the key's low
+    // rb bits), so the stable passes over the length bits finish the order
+    for (int sh = one_tile ? rb : 0; sh < lb + rb + tb; sh += 8) {
       cs_pass(RadixU64Op{k0, v0, k1, v1, sh}, nseg, 8, tmp, st);
       std::swap(k0, k1);
       std::swap(v0, v1);
@@ -891,6 +1096,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->n_rows_sorted = nseg;
   h->tile_row_off = trow;
 
+  clk.mark("a5 segments");
   // ---- a6: workload sizes (Algorithm 2) and partition
   PerfTable table;
   if (o->perf_table) {
@@ -1002,6 +1208,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->n_rowid = roff;
   if (doff >= ((int64_t)1 << 40)) throw Fail{TC_EUNSUPPORTED, "padded format too large"};
 
+  clk.mark("a6 partition");
   // ---- a7: pack
   h->d_idx = hold<int32_t>(h, doff);
   h->d_val = hold<float>(h, doff);
@@ -1056,6 +1263,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     h->n_cu = cus > 0 ? cus : 256;
   }
   HIPX(hipStreamSynchronize(st));
+  clk.mark("a7 pack + metadata");
 }
 
 }  // namespace

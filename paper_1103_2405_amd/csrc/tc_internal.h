@@ -89,6 +89,12 @@ void partition_tile(const std::vector<LenRun>& runs, int64_t wl, int32_t tile, i
 // thread-local error message
 void set_error(const std::string& msg);
 
+// device memory pool (tc_mem.cpp): stream-ordered reuse of freed blocks
+void* pool_alloc(size_t bytes, hipStream_t st);           // nullptr when out of memory
+void pool_free(void* p, hipStream_t st, bool idle);       // idle: no queued work uses p
+size_t pool_release_cached();
+size_t pool_cached_bytes();
+
 }  // namespace tc
 
 // The handle: every device buffer of one built matrix.
@@ -141,6 +147,7 @@ struct tc_handle {
   void (*dfree)(void*, void*) = nullptr;
   void* alloc_ctx = nullptr;
   std::vector<void*> owned;
+  hipStream_t stream = nullptr;     // stream the handle was built on
 
   // growable workspace for SpMM and the drivers (device)
   void* d_ws = nullptr;

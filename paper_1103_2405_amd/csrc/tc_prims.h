@@ -124,7 +124,16 @@ __global__ void __launch_bounds__(kCsBlock) k_cs_hist(Op op, int64_t n, int32_t 
   __syncthreads();
   if (c < nchunks) {
     const int64_t end = min(n, (c + 1) * chunk);
-    for (int64_t k = c * chunk + lane; k < end; k += kWave) atomicAdd(&cnt[op.bucket(k)], 1);
+    int64_t k = c * chunk + lane;
+    for (; k + 3 * kWave < end; k += 4 * kWave) {  // four loads in flight
+      const uint32_t b0 = op.bucket(k), b1 = op.bucket(k + kWave), b2 = op.bucket(k + 2 * kWave),
+                     b3 = op.bucket(k + 3 * kWave);
+      atomicAdd(&cnt[b0], 1);
+      atomicAdd(&cnt[b1], 1);
+      atomicAdd(&cnt[b2], 1);
+      atomicAdd(&cnt[b3], 1);
+    }
+    for (; k < end; k += kWave) atomicAdd(&cnt[op.bucket(k)], 1);
   }
   __syncthreads();
   if (c < nchunks)
@@ -145,23 +154,32 @@ __global__ void __launch_bounds__(kCsBlock) k_cs_scatter(Op op, int64_t n, int32
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const int64_t end = min(n, (c + 1) * chunk);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t base = c * chunk; base < end; base += kWave) {
-    const int64_t k = base + lane;
-    const bool valid = k < end;
-    const uint32_t b = valid ? op.bucket(k) : 0u;
-    uint64_t peers = __ballot(valid);
-    for (int bit = 0; bit < nbits; ++bit) {
-      const bool set = (b >> bit) & 1u;
-      const uint64_t bal = __ballot(set);
-      peers &= set ? bal : ~bal;
+  for (int64_t base0 = c * chunk; base0 < end; base0 += 4 * kWave) {
+    uint32_t bs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // four loads in flight, then the steps in order
+      const int64_t k = base0 + u * kWave + lane;
+      bs[u] = k < end ? op.bucket(k) : 0u;
     }
-    const int64_t pos = valid ? run[b] + (int64_t)__popcll(peers & lt) : 0;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (valid) op.move(k, pos);
-    if (valid && (peers >> lane) == 1ull) run[b] += (int64_t)__popcll(peers);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = base0 + u * kWave + lane;
+      const bool valid = k < end;
+      const uint32_t b = bs[u];
+      uint64_t peers = __ballot(valid);
+      for (int bit = 0; bit < nbits; ++bit) {
+        const bool set = (b >> bit) & 1u;
+        const uint64_t bal = __ballot(set);
+        peers &= set ? bal : ~bal;
+      }
+      const int64_t pos = valid ? run[b] + (int64_t)__popcll(peers & lt) : 0;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (valid) op.move(k, pos);
+      if (valid && (peers >> lane) == 1ull) run[b] += (int64_t)__popcll(peers);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
   }
 }
 

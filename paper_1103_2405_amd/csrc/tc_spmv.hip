@@ -693,15 +693,11 @@ struct Err {
 
 void* workspace(tc_handle* h, size_t bytes, hipStream_t st) {
   if (bytes <= h->ws_bytes) return h->d_ws;
-  HIPC(hipStreamSynchronize(st));
-  if (h->d_ws) HIPC(hipFree(h->d_ws));
+  if (h->d_ws) pool_free(h->d_ws, st, false);
   h->d_ws = nullptr;
   h->ws_bytes = 0;
-  if (hipMalloc(&h->d_ws, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    h->d_ws = nullptr;
+  if (!(h->d_ws = pool_alloc(bytes, st)))
     throw Err{TC_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed"};
-  }
   h->ws_bytes = bytes;
   return h->d_ws;
 }

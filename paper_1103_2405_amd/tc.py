@@ -81,7 +81,7 @@ class CTiming(ctypes.Structure):
 
 EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_internal", "tc_spmm",
             "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
-            "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error"]
+            "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory"]
 
 _lib = None
 
@@ -112,10 +112,12 @@ def load_library(path: str = LIB_PATH):
     lib.tc_get_timing.argtypes = [vp, P(CTiming)]
     lib.tc_destroy.argtypes = [vp]
     lib.tc_destroy.restype = None
+    lib.tc_release_cached_memory.argtypes = []
+    lib.tc_release_cached_memory.restype = ctypes.c_size_t
     lib.tc_last_error.argtypes = []
     lib.tc_last_error.restype = ctypes.c_char_p
     for f in EXPORTED:
-        if f not in ("tc_build_opts_default", "tc_destroy", "tc_last_error"):
+        if f not in ("tc_build_opts_default", "tc_destroy", "tc_last_error", "tc_release_cached_memory"):
             getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -315,6 +317,11 @@ class TiledMatrix:
         t = CTiming()
         _check(load_library().tc_get_timing(self.handle, ctypes.byref(t)), "tc_get_timing")
         return {"tile_kernel_ms": t.tile_kernel_ms, "tile_launches": t.tile_launches, "spmv_calls": t.spmv_calls}
+
+
+def release_cached_memory() -> int:
+    """Return the library's cached device blocks to HIP; bytes released."""
+    return int(load_library().tc_release_cached_memory())
 
 
 def build_tiled(csr, **opts) -> TiledMatrix:
