@@ -80,11 +80,11 @@ def cpu_baseline(csr, budget_s: float):
 def rwr_batched(c: float = 0.85, tol: float = 1e-6, ks=(1, 8, 32, 64)):
     """Batched RWR (multi-RHS SpMM) on the symmetrised R-MAT scale-20 graph:
     queries/s for k one-hot restart vectors solved together to an L1 change of
-    tol, against k sequential single-query solves with (a) the plain CSR SpMV
-    kernel and (b) the tiled single-vector SpMV."""
+    tol, against k = 32 sequential single-query solves with (a) PyTorch's
+    sparse CSR matrix-vector product and (b) the tiled single-vector SpMV."""
     import torch
     import graphgen as gg
-    from paper_1103_2405_amd import DeviceCsr, TiledMatrix, csr_spmv
+    from paper_1103_2405_amd import DeviceCsr, TiledMatrix
     g = gg.rmat(20, 16, seed=20)
     W = gg.rwr_matrix(g)
     seeds = gg.rwr_seeds(g, max(ks), 40)
@@ -107,28 +107,43 @@ def rwr_batched(c: float = 0.85, tol: float = 1e-6, ks=(1, 8, 32, 64)):
         tm.rwr(seeds[q:q + 1], c, tol, 500, 10)
     torch.cuda.synchronize()
     tiled_seq = k / (time.perf_counter() - t0)
-    # (a) k sequential solves with the plain CSR kernel (vector update by torch)
     n = A.n_rows
-    r = torch.empty(n, device="cuda")
-    y = torch.empty(n, device="cuda")
-    t0 = time.perf_counter()
-    for q in range(k):
-        s = int(seeds[q])
-        r.zero_()
-        r[s] = 1.0
-        for it in range(500):
-            csr_spmv(A, r, y)
-            y.mul_(c)
-            y[s] += 1.0 - c
-            d = float((y - r).abs().sum()) if (it + 1) % 10 == 0 else 1.0
-            r, y = y, r
-            if d <= tol:
-                break
-    torch.cuda.synchronize()
-    csr_seq = k / (time.perf_counter() - t0)
+
+    def plain_loop(spmv):
+        """k = 32 sequential single-query solves: y = A r by `spmv`, the RWR
+        update and the residual (checked every 10 iterations) by torch."""
+        r = torch.empty(n, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in range(k):
+            s = int(seeds[q])
+            r.zero_()
+            r[s] = 1.0
+            for it in range(500):
+                y = spmv(r)
+                y.mul_(c)
+                y[s] += 1.0 - c
+                d = float((y - r).abs().sum()) if (it + 1) % 10 == 0 else 1.0
+                r = y
+                if d <= tol:
+                    break
+        torch.cuda.synchronize()
+        return k / (time.perf_counter() - t0)
+
+    # (a) PyTorch's sparse CSR matrix-vector product (the ROCm sparse library)
+    try:
+        Wt = torch.sparse_csr_tensor(torch.from_numpy(W[2].astype(np.int32)).cuda(),
+                                     torch.from_numpy(W[3]).cuda(), torch.from_numpy(W[4]).cuda(), size=(n, n))
+        torch_seq = plain_loop(lambda r: torch.mv(Wt, r))
+        del Wt
+    except Exception as e:  # report, do not fail the benchmark
+        log("torch sparse CSR baseline unavailable:", repr(e))
+        torch_seq = None
     b = out["k32"]["queries_per_s"]
-    out.update(csr_loop_queries_per_s=round(csr_seq, 2), tiled_loop_queries_per_s=round(tiled_seq, 2),
-               speedup_k32_vs_csr_loop=round(b / csr_seq, 2), speedup_k32_vs_tiled_loop=round(b / tiled_seq, 2))
+    out.update(tiled_loop_queries_per_s=round(tiled_seq, 2),
+               torch_csr_loop_queries_per_s=None if torch_seq is None else round(torch_seq, 2),
+               speedup_k32_vs_tiled_loop=round(b / tiled_seq, 2),
+               speedup_k32_vs_torch_csr_loop=None if torch_seq is None else round(b / torch_seq, 2))
     tm.close()
     return out
 
@@ -204,8 +219,10 @@ def main():
         per_launch_bytes = spmv_bytes * calls / max(launches, 1)
         avg_ms = tot_ms / max(launches, 1)
         achieved = per_launch_bytes / (avg_ms / 1e3) / 1e9
+        from paper_1103_2405_amd.profsum import read_traffic
+        traffic = read_traffic(os.path.join(ROOT, "profiles", "k_tile_spmv_%s_pagerank_counters.txt" % args.workload))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "k_tile_spmv", "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches_per_spmv": round(launches / max(calls, 1), 2),
                     "bytes_per_launch": int(per_launch_bytes)}

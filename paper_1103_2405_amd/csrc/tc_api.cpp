@@ -153,6 +153,7 @@ extern "C" void tc_destroy(tc_handle* h) {
       tc::pool_free(p, nullptr, true);
   }
   if (h->d_ws) tc::pool_free(h->d_ws, nullptr, true);
+  if (h->d_mm_partial) tc::pool_free(h->d_mm_partial, nullptr, true);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
 }

@@ -141,6 +141,12 @@ struct tc_handle {
   int64_t n_zero0 = 0;
   int n_cu = 256;                   // compute units of the device
   int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
+  // SpMM plan (lazily built): leading chunk workloads per tile, pieces per chunk
+  bool mm_planned = false;
+  std::vector<int64_t> mm_lead;
+  int32_t mm_pieces = 1;
+  double* d_mm_partial = nullptr;   // n_slots x pieces x k partial sums
+  size_t mm_partial_bytes = 0;
 
   // allocator
   void* (*alloc)(size_t, void*) = nullptr;

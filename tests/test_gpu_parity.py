@@ -207,6 +207,50 @@ def test_spmm_matches_oracle():
         assert np.all(np.abs(Y - ref) <= bound), k
 
 
+def _heavy_rows_csr(n, heavy, heavy_len, light_len, seed, dyadic):
+    """n x n CSR whose first `heavy` rows hold heavy_len distinct columns and
+    every other row light_len; dyadic values when asked."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        m = heavy_len if i < heavy else int(rng.integers(0, light_len + 1))
+        rows.append(np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32))
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.concatenate(rows).astype(np.int32)
+    if dyadic:
+        val = rng.choice(np.array([1, -1, 0.5, -0.5, 0.25, -0.25], np.float32), size=col.size)
+    else:
+        val = rng.random(col.size, dtype=np.float32)
+    return (n, n, rp, col, val.astype(np.float32))
+
+
+@pytest.mark.parametrize("W,split", [(4096, 1280), (1024, 256), (4096, 0)])
+def test_spmm_heavy_rows_in_pieces(W, split):
+    # rows of 2500 entries: with split 1280 every chunk is summed in three
+    # 512-entry pieces; with 0 the rows stay whole (row-major, all groups)
+    csr = _heavy_rows_csr(3000, 5, 2500, 6, 17, dyadic=False)
+    gm = TiledMatrix(csr, tile_width=W, split_len=split)
+    for k in (1, 2, 7, 32, 64, 65, 130):
+        X = np.stack([gg.uniform_f32(csr[1], 40 + q) for q in range(k)], axis=1)
+        Y = gm.spmm(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+        ref = oracle.spmm(csr, X)
+        bound = TOL * oracle.spmm((csr[0], csr[1], csr[2], csr[3], np.abs(csr[4])), np.abs(X))
+        assert np.all(np.abs(Y - ref) <= bound), (W, split, k)
+
+
+def test_spmm_dyadic_bit_exact():
+    # dyadic values and small-integer X: every summation order is exact, so
+    # each column of Y must equal the oracle bit for bit
+    csr = _heavy_rows_csr(3000, 4, 2200, 9, 23, dyadic=True)
+    gm = TiledMatrix(csr, tile_width=1024, split_len=1024)
+    rng = np.random.default_rng(5)
+    for k in (1, 9, 64, 70):
+        X = rng.integers(-8, 9, size=(csr[1], k)).astype(np.float32)
+        Y = gm.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+        assert np.array_equal(Y.astype(np.float64), oracle.spmm(csr, X)), k
+
+
 def test_csr_baseline_matches_oracle():
     g = gg.rmat(14, 16, seed=14)
     csr = gg.pagerank_matrix(g)
