@@ -148,6 +148,50 @@ def rwr_batched(c: float = 0.85, tol: float = 1e-6, ks=(1, 8, 32, 64)):
     return out
 
 
+def rwr_multi_graph(c: float = 0.85, iters: int = 30, n_graphs: int = 32):
+    """RWR with one query on each of 32 independent R-MAT graphs (graph g:
+    seed 4000 + g, scale uniform in 10..16, edge factor uniform in 8..32),
+    30 iterations each: all graphs per launch (captured once in a HIP graph,
+    and eagerly) against the graphs one after another with the single-graph
+    driver."""
+    import torch
+    import graphgen as gg
+    from paper_1103_2405_amd import DeviceCsr, TiledMatrix, rwr_multi
+    scales = 10 + gg.uniform_int(n_graphs, 7, 4000)
+    efs = 8 + gg.uniform_int(n_graphs, 25, 4001)
+    mats, seeds, nodes, nnz = [], [], 0, 0
+    for g in range(n_graphs):
+        G = gg.rmat(int(scales[g]), int(efs[g]), seed=4000 + g)
+        W = gg.rwr_matrix(G)
+        mats.append(TiledMatrix(DeviceCsr(W)))
+        seeds.append(int(gg.rwr_seeds(G, 1, 4100 + g)[0]))
+        nodes += G.n
+        nnz += int(W[3].size)
+    out = {"graphs": n_graphs, "nodes": nodes, "nnz": nnz, "iters": iters, "c": c}
+
+    def timed(f, reps=3):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    out["multi_graph_ms"] = round(timed(lambda: rwr_multi(mats, seeds, c, 0.0, iters, iters, graph=True)), 3)
+    out["multi_eager_ms"] = round(timed(lambda: rwr_multi(mats, seeds, c, 0.0, iters, iters, graph=False)), 3)
+
+    def seq():
+        for m, s in zip(mats, seeds):
+            m.rwr([s], c, 0.0, iters, iters)
+
+    out["sequential_ms"] = round(timed(seq), 3)
+    out["speedup_vs_sequential"] = round(out["sequential_ms"] / min(out["multi_graph_ms"], out["multi_eager_ms"]), 2)
+    for m in mats:
+        m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +302,7 @@ def main():
         del A
         torch.cuda.empty_cache()
         rwr = rwr_batched()
+        rwr["multi_graph"] = rwr_multi_graph()
         log("batched rwr:", json.dumps(rwr))
 
     cpu = None

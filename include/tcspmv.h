@@ -207,6 +207,21 @@ tc_status tc_rwr(const tc_handle* W, const int32_t* seeds, int32_t k, float c, f
                  int32_t max_iter, int32_t check_every, float* d_R, int32_t* iters, double* resid,
                  tc_stream_t stream);
 
+/* RWR (Appendix F, Eq. 9) on many graphs at once, one query per graph.
+ * handles[g] is built from graph g's matrix as for tc_rwr; seeds[g] is its
+ * restart node (original id, host array); d_R[g] (host array of device
+ * pointers) receives its n_g scores in original ids.  Every launch covers all
+ * graphs: tile t of each, the split rows of each, then the update of each, so
+ * small graphs share the GPU.  Stopping as in tc_rwr with the largest per-graph
+ * L1 change; resid (host array of n_graphs, may be NULL) gets each graph's last
+ * change.  flags bit 0: capture the iterations between checks in a HIP graph
+ * once and replay it (kernels only; results are identical to eager launches).
+ * Handles built with the XCD schedule are rejected (TC_EUNSUPPORTED).  The
+ * call synchronises `stream`. */
+tc_status tc_rwr_multi(tc_handle* const* handles, int32_t n_graphs, const int32_t* seeds, float c, float tol,
+                       int32_t max_iter, int32_t check_every, int32_t flags, float* const* d_R, int32_t* iters,
+                       double* resid, tc_stream_t stream);
+
 /* Plain CSR SpMV (one thread per row, Appendix B's CSR kernel), the baseline
  * the tiled kernels are compared with: y := A x, caller's ids, no handle. */
 tc_status tc_csr_spmv(const tc_csr* A, const float* d_x, float* d_y, tc_stream_t stream);

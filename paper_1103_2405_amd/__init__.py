@@ -5,4 +5,4 @@ The compute path is the HIP library libtcspmv.so (C ABI in include/tcspmv.h);
 the first call does, and raises if it is not built.
 """
 from .tc import (DeviceCsr, NotConverged, TcError, TiledMatrix, build_tiled, csr_spmv,  # noqa: F401
-                 load_library, release_cached_memory)
+                 load_library, release_cached_memory, rwr_multi)

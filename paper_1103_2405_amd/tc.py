@@ -81,7 +81,8 @@ class CTiming(ctypes.Structure):
 
 EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_internal", "tc_spmm",
             "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
-            "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory"]
+            "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory",
+            "tc_rwr_multi"]
 
 _lib = None
 
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.tc_rwr.argtypes = [vp, vp, i32, ctypes.c_float, ctypes.c_float, i32, i32, vp, P(i32),
                            P(ctypes.c_double), vp]
     lib.tc_csr_spmv.argtypes = [P(CCsr), vp, vp, vp]
+    lib.tc_rwr_multi.argtypes = [vp, i32, vp, ctypes.c_float, ctypes.c_float, i32, i32, i32, vp, P(i32), vp, vp]
     lib.tc_handle_info.argtypes = [vp, P(CInfo)]
     lib.tc_export_format.argtypes = [vp, P(CFormatView)]
     lib.tc_set_timing.argtypes = [vp, i32]
@@ -317,6 +319,26 @@ class TiledMatrix:
         t = CTiming()
         _check(load_library().tc_get_timing(self.handle, ctypes.byref(t)), "tc_get_timing")
         return {"tile_kernel_ms": t.tile_kernel_ms, "tile_launches": t.tile_launches, "spmv_calls": t.spmv_calls}
+
+
+def rwr_multi(mats, seeds, c: float = 0.85, tol: float = 0.0, max_iter: int = 30, check_every: int = 1,
+              graph: bool = True, stream=None):
+    """RWR on several graphs at once (one query each): returns (list of score
+    vectors, iterations, per-graph last L1 change)."""
+    n = len(mats)
+    hs = (vp * max(n, 1))(*[m.handle for m in mats])
+    s = np.ascontiguousarray(seeds, np.int32)
+    if s.size != n:
+        raise ValueError("one seed per graph")
+    outs = [torch.empty(m.n_rows, dtype=torch.float32, device="cuda") for m in mats]
+    ptrs = (vp * max(n, 1))(*[o.data_ptr() for o in outs])
+    res = (ctypes.c_double * max(n, 1))()
+    it = i32(0)
+    _check(load_library().tc_rwr_multi(ctypes.cast(hs, vp), n, s.ctypes.data_as(vp), c, tol, max_iter, check_every,
+                                       1 if graph else 0, ctypes.cast(ptrs, vp), ctypes.byref(it),
+                                       ctypes.cast(res, vp), _stream(stream)),
+           "tc_rwr_multi")
+    return outs, it.value, np.array(res[:n])
 
 
 def release_cached_memory() -> int:

@@ -350,3 +350,55 @@ def test_rwr_matches_oracle():
         d = np.abs(R.cpu().numpy() - Rref).sum(axis=0)
         say("rwr L1 diff per column", d)
         assert np.all(d <= 1e-6)
+
+
+# ------------------------------------------------------------ several graphs per launch
+def _multi_set():
+    mats, csrs, seeds = [], [], []
+    for gi in range(6):
+        g = gg.rmat(8 + gi % 4, 4 + 3 * gi, seed=700 + gi)
+        csr = gg.rwr_matrix(g)
+        # mixed formats: several tiles, split rows, one tile
+        W = 128 if gi % 2 else 0
+        split = 64 if gi % 3 == 0 else -1
+        mats.append(TiledMatrix(csr, tile_width=W, split_len=split))
+        csrs.append(csr)
+        seeds.append(int(gg.rwr_seeds(g, 1, 50 + gi)[0]))
+    return mats, csrs, seeds
+
+
+def test_rwr_multi_matches_oracle_and_single_graph_driver():
+    from paper_1103_2405_amd import rwr_multi
+    mats, csrs, seeds = _multi_set()
+    eager, it, res = rwr_multi(mats, seeds, 0.85, 0.0, 30, 1, graph=False)
+    assert it == 30
+    for m, csr, s, r in zip(mats, csrs, seeds, eager):
+        ref, _, _ = oracle.rwr(csr, [s], 0.85, 0.0, 30)
+        d = np.abs(r.cpu().numpy() - ref[:, 0]).sum()
+        say("multi rwr L1 diff", d)
+        assert d <= 1e-6
+        # the same kernels as the single-graph driver: identical iterates
+        one, _, _ = m.rwr([s], 0.85, 0.0, 30)
+        assert torch.equal(one[:, 0], r)
+    # the HIP graph replays give the eager result, call after call
+    for rep in range(3):
+        got, it2, _ = rwr_multi(mats, seeds, 0.85, 0.0, 30, 10, graph=True)
+        assert it2 == 30
+        for a, b in zip(got, eager):
+            assert torch.equal(a, b), rep
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+
+
+def test_rwr_multi_tolerance_and_empty():
+    from paper_1103_2405_amd import rwr_multi
+    mats, csrs, seeds = _multi_set()
+    out, it, res = rwr_multi(mats, seeds, 0.85, 1e-6, 500, 5, graph=True)
+    assert it % 5 == 0 and res.max() <= 1e-6
+    for csr, s, r in zip(csrs, seeds, out):
+        ref, _, _ = oracle.rwr(csr, [s], 0.85, 0.0, it)
+        assert np.abs(r.cpu().numpy() - ref[:, 0]).sum() <= 1e-6
+    out, it, res = rwr_multi([], [], 0.85, 0.0, 30, 1)
+    assert out == [] and it == 0
+    with pytest.raises(TcError):
+        rwr_multi(mats[:2], [seeds[0], -1], 0.85, 0.0, 5, 1)
