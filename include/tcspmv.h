@@ -110,6 +110,8 @@ typedef struct {
   int64_t n_dangling;         /* empty columns; internal ids n_cols - n_dangling .. n_cols-1 */
   int64_t device_bytes;       /* device memory held by the handle */
   double build_us;            /* wall time of tc_build_tiled */
+  double model_us;            /* Eq. 1-5 prediction for one product with the built workload sizes, summed
+                                 over tiles (microseconds; the throughput table is in entries per us) */
 } tc_info;
 
 /* Host copies of the whole format, for checking it entry by entry.  The caller

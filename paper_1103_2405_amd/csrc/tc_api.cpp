@@ -40,6 +40,7 @@ extern "C" tc_status tc_handle_info(const tc_handle* h, tc_info* info) {
                   h->n_split_rows * (int64_t)sizeof(SplitRow) + (int64_t)h->ws_bytes;
   info->device_bytes = bytes;
   info->build_us = h->build_us;
+  info->model_us = h->model_us;
   return TC_OK;
 }
 

@@ -1131,6 +1131,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     }
     if (WLt < 1) throw Fail{TC_EINVAL, "workload size must be >= 1"};
     h->tile_wl[t] = WLt;
+    if (!runs.empty()) h->model_us += model_time(runs, WLt, table, t >= T, pp);
     h->tile_wl_begin[t] = (int64_t)wls.size();
     partition_tile(runs, WLt, t, trow[t], pp, &wls);
   }

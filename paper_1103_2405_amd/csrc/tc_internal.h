@@ -106,6 +106,7 @@ struct tc_handle {
   int64_t nnz_pad = 0, n_rowid = 0, n_rows_sorted = 0, n_dangling = 0;
   int64_t n_wl = 0, n_slots = 0, n_split_rows = 0;
   double build_us = 0.0;
+  double model_us = 0.0;            // Eq. 1-5 time of the built partition, all tiles
 
   // host copies of small metadata
   std::vector<int64_t> tile_col_begin, tile_col_end, tile_nnz, tile_wl, tile_split, tile_row_off;

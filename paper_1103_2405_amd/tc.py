@@ -53,7 +53,7 @@ class CInfo(ctypes.Structure):
                 ("xcd_groups", i32), ("pad_", i32), ("n_dense_tiles", i32), ("n_tiles", i32),
                 ("n_workloads", i64), ("nnz_pad", i64), ("n_rowid", i64), ("n_rows_sorted", i64),
                 ("n_split_rows", i64), ("n_partials", i64), ("n_dangling", i64), ("device_bytes", i64),
-                ("build_us", ctypes.c_double)]
+                ("build_us", ctypes.c_double), ("model_us", ctypes.c_double)]
 
 
 _VIEW_FIELDS = [("cperm", np.int32, "n_cols"), ("rowmap", np.int32, "n_rows"),

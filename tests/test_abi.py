@@ -46,3 +46,28 @@ def test_null_arguments_rejected_without_gpu_work():
     assert lib.tc_handle_info(None, None) == tc.TC_EINVAL
     assert lib.tc_spmv(None, None, None, None) == tc.TC_EINVAL
     lib.tc_destroy(None)
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    # compile a probe against the header and compare every field offset and
+    # struct size with the ctypes mirrors in the binding
+    import subprocess
+    from paper_1103_2405_amd import tc
+    structs = {"tc_csr": tc.CCsr, "tc_build_opts": tc.CBuildOpts, "tc_info": tc.CInfo,
+               "tc_format_view": tc.CFormatView, "tc_timing": tc.CTiming}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tcspmv.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                               text=True).stdout.split("\n") if line)
+    for cname, py in structs.items():
+        assert int(got["%s size" % cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
