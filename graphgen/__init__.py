@@ -155,6 +155,15 @@ def uniform_f32(n: int, seed: int) -> np.ndarray:
     return out
 
 
+def normal_f32(n: int, seed: int) -> np.ndarray:
+    """n standard normal floats (Box-Muller on two uniform streams, FP64, then
+    rounded to FP32); the edge features of the differentiable RWR."""
+    u1 = uniform_f32(n, seed).astype(np.float64)
+    u2 = uniform_f32(n, seed ^ 0x5DEECE66D).astype(np.float64)
+    u1 = 1.0 - u1  # (0, 1]
+    return (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).astype(np.float32)
+
+
 def uniform_int(n: int, bound: int, seed: int) -> np.ndarray:
     out = np.empty(n, np.int64)
     _load().gg_uniform_int(n, seed, bound, _p(out))

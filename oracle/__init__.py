@@ -8,6 +8,8 @@ imports the library.
                   power iterations (ctypes, built here with gcc)
   ref_format.py   reference builder of the tiled composite format (numpy)
   autotune.py     Algorithms 1-3 and the performance model (Eq. 1-5)
+  rwr_grad.py     RWR with learned, column-normalised edge weights and the
+                  gradient of a loss on its iterate (FP64 adjoint pass)
 """
 from __future__ import annotations
 
