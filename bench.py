@@ -192,6 +192,44 @@ def rwr_multi_graph(c: float = 0.85, iters: int = 30, n_graphs: int = 32):
     return out
 
 
+def diff_rwr(K: int = 30, every: int = 6, reps: int = 3):
+    """Differentiable RWR on the symmetrised R-MAT scale-20 graph: edge weights
+    softplus(theta . f_e) with 4 features per entry, column-normalised; loss
+    = -sum of log scores of 16 target nodes after K iterations from one seed.
+    Times the forward (weights, both builds, K iterations with checkpoints)
+    and the backward (adjoint pass and the chain to theta)."""
+    import torch
+    import graphgen as gg
+    from paper_1103_2405_amd.rwr_grad import EdgeWeightedRWR
+    g = gg.rmat(20, 16, seed=20)
+    n, _, rp, col, _ = gg.rwr_matrix(g)
+    feats = gg.normal_f32(len(col) * 4, 21).reshape(len(col), 4)
+    seed = int(gg.rwr_seeds(g, 1, 22)[0])
+    targets = torch.as_tensor(gg.rwr_seeds(g, 16, 23).astype(np.int64)).cuda()
+    model = EdgeWeightedRWR((n, n, rp, col), feats, seed, 0.85, K, every=every)
+    theta = torch.tensor([0.4, -0.3, 0.2, 0.1], dtype=torch.float64, requires_grad=True)
+    fw, bw = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        scores = model.scores(theta)
+        loss = -torch.log(scores[targets].double()).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        theta.grad = None
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    model.close()
+    return {"graph": "symmetrised rmat-20", "nnz": int(len(col)), "features": 4, "iters": K,
+            "checkpoint_every": every, "targets": 16, "loss": round(loss.item(), 6),
+            "grad": [round(float(v), 6) for v in theta.grad], "forward_ms": round(min(fw) * 1e3, 2),
+            "backward_ms": round(min(bw) * 1e3, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +341,7 @@ def main():
         torch.cuda.empty_cache()
         rwr = rwr_batched()
         rwr["multi_graph"] = rwr_multi_graph()
+        rwr["differentiable"] = diff_rwr()
         log("batched rwr:", json.dumps(rwr))
 
     cpu = None

@@ -224,6 +224,53 @@ tc_status tc_rwr_multi(tc_handle* const* handles, int32_t n_graphs, const int32_
                        int32_t max_iter, int32_t check_every, int32_t flags, float* const* d_R, int32_t* iters,
                        double* resid, tc_stream_t stream);
 
+/* ---- Differentiable RWR: learned edge weights (Appendix F, Eq. 9) ----------
+ * For a square pattern A (n x n, entries e = (i, j), CSR rp/col on the device)
+ * with nf features per entry (d_feats, nnz x nf row-major):
+ *   z_e = theta . f_e,  w_e = softplus(z_e),  W_e = w_e / S_j  (S_j: sum of w over column j),
+ *   r^0 = e_s,  r^{k+1} = c W r^k + (1 - c) e_s.
+ * The gradient of a loss on r^K runs back through the iteration:
+ *   g^k = c W^T g^{k+1}   (tiled SpMV on a build of W^T),
+ *   dL/dW_e = c sum_k g^{k+1}_i r^k_j,
+ * then through the normalisation and the softplus to theta.  Vectors are in
+ * the caller's ids; every FP64 sum below has a fixed order. */
+
+/* CSR of A^T (n_cols x n_rows): d_rpT (n_cols + 1), d_colT and d_valT (nnz)
+ * and d_permT (nnz; entry e' of A^T is entry d_permT[e'] of A).  Each row of
+ * A^T lists its entries by increasing row of A.  d_colT, d_valT and d_permT
+ * may be NULL.  Validates A like tc_build_tiled.  Synchronous. */
+tc_status tc_csr_transpose(const tc_csr* A, int64_t* d_rpT, int32_t* d_colT, float* d_valT, int32_t* d_permT,
+                           tc_stream_t stream);
+
+/* z, w (FP64, nnz), S (FP64, n_cols) and the FP32 values of W in A's order
+ * (d_val) and in A^T's order (d_valT) for theta (host, nf <= 16).  d_col is
+ * A's column array; d_rpT/d_permT come from tc_csr_transpose.  Synchronous. */
+tc_status tc_rwr_edge_weights(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT,
+                              const int32_t* d_permT, int32_t nf, const float* d_feats, const double* theta,
+                              double* d_z, double* d_w, double* d_S, float* d_val, float* d_valT,
+                              tc_stream_t stream);
+
+/* K RWR iterations on the handle of W from e_seed; d_rK receives r^K and
+ * d_ckpt (ceil(K / every) x n) the checkpoints r^0, r^every, ...  Each step
+ * rounds like tc_rwr, so r^K equals tc_rwr's with k = 1. */
+tc_status tc_rwr_iterates(const tc_handle* W, int32_t seed, float c, int32_t K, int32_t every, float* d_ckpt,
+                          float* d_rK, tc_stream_t stream);
+
+/* Adjoint pass from d_gK = dL/dr^K: recomputes the iterates between
+ * checkpoints (every x n scratch), and returns d_G[e] = sum_k g^{k+1}_i r^k_j
+ * (FP64, nnz, A's order; dL/dW = c G) and, if d_g0 is not NULL, g^0.  Wt is
+ * the handle built from A^T with W's values (tc_csr_transpose + d_valT). */
+tc_status tc_rwr_adjoint(const tc_handle* W, const tc_handle* Wt, const int64_t* d_rp, const int32_t* d_col,
+                         int32_t seed, float c, int32_t K, int32_t every, const float* d_ckpt, const float* d_gK,
+                         double* d_G, float* d_g0, tc_stream_t stream);
+
+/* dL/dtheta (host, nf doubles) from d_G of tc_rwr_adjoint and z, w, S of
+ * tc_rwr_edge_weights.  Synchronous. */
+tc_status tc_rwr_theta_grad(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT,
+                            const int32_t* d_permT, int32_t nf, const float* d_feats, const double* d_z,
+                            const double* d_w, const double* d_S, const double* d_G, float c, double* dtheta,
+                            tc_stream_t stream);
+
 /* Plain CSR SpMV (one thread per row, Appendix B's CSR kernel), the baseline
  * the tiled kernels are compared with: y := A x, caller's ids, no handle. */
 tc_status tc_csr_spmv(const tc_csr* A, const float* d_x, float* d_y, tc_stream_t stream);

@@ -784,6 +784,69 @@ void col_count_bucketed(const int32_t* col, int64_t nnz, int64_t n_cols, int csh
   HIPX(hipStreamSynchronize(st));
 }
 
+// transpose: entry e' of A^T is entry v[e'] of A
+__global__ void k_transpose_gather(const int32_t* __restrict__ v, const int32_t* __restrict__ row_of,
+                                   const float* __restrict__ val, int64_t n, int32_t* __restrict__ colT,
+                                   float* __restrict__ valT, int32_t* __restrict__ permT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t e = v[i];
+  if (colT) colT[i] = row_of[e];
+  if (valT) valT[i] = val[e];
+  if (permT) permT[i] = e;
+}
+
+// CSR of A^T: column counts, their scan, and a stable sort of the entries by
+// column (LSD counting-sort passes that carry the entry index), so each row of
+// A^T lists its entries by increasing row of A.
+void transpose(const tc_csr* A, int64_t* rpT, int32_t* colT, float* valT, int32_t* permT, hipStream_t st) {
+  const int64_t n_rows = A->n_rows, n_cols = A->n_cols, nnz = A->nnz;
+  Tmp tmp(st);
+  {
+    int* flag = tmp.get<int>(1);
+    HIPX(hipMemsetAsync(flag, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_validate_rows, dim3(nblk(n_rows + 1, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, nnz, flag);
+    if (nnz > 0) hipLaunchKernelGGL(k_validate_cols, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, nnz, n_cols, flag);
+    HIPX(hipGetLastError());
+    int f = 0;
+    HIPX(hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    if (f & 1) throw Fail{TC_EINVAL, "invalid CSR: row_ptr must start at 0, not decrease and end at nnz"};
+    if (f & 2) throw Fail{TC_EINVAL, "invalid CSR: a column id is outside [0, n_cols)"};
+  }
+  int32_t* clen = tmp.get<int32_t>(n_cols);
+  if (n_cols > 0) HIPX(hipMemsetAsync(clen, 0, sizeof(int32_t) * n_cols, st));
+  const int cbits = bits_for((uint64_t)(n_cols > 1 ? n_cols - 1 : 0));
+  const int cshift = std::max(15, cbits - 8);
+  const int64_t windows = (int64_t)1 << (cshift - 15);
+  if (nnz >= 4096 && windows <= 4)
+    col_count_bucketed(A->col_idx, nnz, n_cols, cshift, windows, clen, tmp, st);
+  else if (n_cols > 0 && nnz > 0)
+    col_count_atomic(A->col_idx, nnz, n_cols, clen, tmp, st);
+  const int64_t total = n_cols > 0 ? excl_scan<int32_t, int64_t>(clen, n_cols, rpT, tmp, st) : 0;
+  HIPX(hipMemcpyAsync(rpT + n_cols, &total, sizeof(int64_t), hipMemcpyHostToDevice, st));
+  if (nnz > 0) {
+    int32_t* row_of = tmp.get<int32_t>(nnz);
+    hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, row_of);
+    uint32_t* k0 = tmp.get<uint32_t>(nnz);
+    uint32_t* k1 = tmp.get<uint32_t>(nnz);
+    int32_t* v0 = tmp.get<int32_t>(nnz);
+    int32_t* v1 = tmp.get<int32_t>(nnz);
+    HIPX(hipMemcpyAsync(k0, A->col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_iota, dim3(nblk(nnz, kB)), dim3(kB), 0, st, v0, nnz);
+    HIPX(hipGetLastError());
+    for (int sh = 0; sh < cbits; sh += 8) {
+      cs_pass(RadixU32Op{k0, v0, k1, v1, sh}, nnz, 8, tmp, st);
+      std::swap(k0, k1);
+      std::swap(v0, v1);
+    }
+    hipLaunchKernelGGL(k_transpose_gather, dim3(nblk(nnz, kB)), dim3(kB), 0, st, (const int32_t*)v0,
+                       (const int32_t*)row_of, A->val, nnz, colT, valT, permT);
+    HIPX(hipGetLastError());
+  }
+  HIPX(hipStreamSynchronize(st));  // the host total above is read by the copy
+}
+
 // TC_BUILD_TRACE=1: synchronise after every phase and print its wall time
 struct PhaseClock {
   hipStream_t st;
@@ -1343,5 +1406,31 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   }
   h->build_us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   *out = h;
+  return TC_OK;
+}
+
+extern "C" tc_status tc_csr_transpose(const tc_csr* A, int64_t* d_rpT, int32_t* d_colT, float* d_valT,
+                                      int32_t* d_permT, tc_stream_t stream) {
+  if (!A || !d_rpT || (A && A->nnz > 0 && (!A->row_ptr || !A->col_idx || (d_valT && !A->val)))) {
+    set_error("tc_csr_transpose: NULL argument");
+    return TC_EINVAL;
+  }
+  if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0 || !A->row_ptr) {
+    set_error("tc_csr_transpose: invalid sizes");
+    return TC_EINVAL;
+  }
+  if (A->nnz >= ((int64_t)1 << 31) || A->n_rows >= ((int64_t)1 << 31) - 1 || A->n_cols >= ((int64_t)1 << 31) - 1) {
+    set_error("tc_csr_transpose: sizes must fit 32-bit ids");
+    return TC_EUNSUPPORTED;
+  }
+  try {
+    transpose(A, d_rpT, d_colT, d_valT, d_permT, (hipStream_t)stream);
+  } catch (const Fail& f) {
+    set_error(std::string("tc_csr_transpose: ") + f.msg);
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    set_error("tc_csr_transpose: host allocation failed");
+    return TC_ENOMEM;
+  }
   return TC_OK;
 }

@@ -933,6 +933,147 @@ __global__ void k_map_ids_multi(const int32_t* const* __restrict__ maps, const i
   for (int32_t g = threadIdx.x; g < n; g += blockDim.x) out[g] = maps[g][ids[g]];
 }
 
+// ---- differentiable RWR: learned edge weights (Appendix F, Eq. 9)
+//
+// z_e = theta . f_e, w_e = softplus(z_e), W_e = w_e / S_j with S_j the sum of
+// w over column j.  Column quantities run one wavefront per column over the
+// CSR of the transpose (rows of A^T = columns of A; permT maps its entries
+// back to A's), so every sum has a fixed order.
+__device__ inline double softplus_d(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
+
+__global__ void k_edge_softplus(const float* __restrict__ feats, int64_t nnz, int32_t nf,
+                                const double* __restrict__ theta, double* __restrict__ z, double* __restrict__ w) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  double a = 0.0;
+  for (int32_t d = 0; d < nf; ++d) a = fma((double)feats[e * nf + d], theta[d], a);
+  z[e] = a;
+  w[e] = softplus_d(a);
+}
+
+// S_j = sum over column j of w (wave per column), and the FP32 values of the
+// transpose's entries, W^T[j][i] = fl32(w_e / S_j)
+__global__ void __launch_bounds__(kB) k_col_norm(const int64_t* __restrict__ rpT, const int32_t* __restrict__ permT,
+                                                 int64_t n_cols, const double* __restrict__ w,
+                                                 double* __restrict__ S, float* __restrict__ valT) {
+  const int lane = lane_id();
+  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (j >= n_cols) return;
+  const int64_t a = rpT[j], b = rpT[j + 1];
+  double s = 0.0;
+  for (int64_t q = a + lane; q < b; q += kWave) s += w[permT[q]];
+  s = wave_sum(s);
+  if (lane == 0) S[j] = s;
+  for (int64_t q = a + lane; q < b; q += kWave) valT[q] = (float)(w[permT[q]] / s);
+}
+
+__global__ void k_edge_values(const int32_t* __restrict__ col, int64_t nnz, const double* __restrict__ w,
+                              const double* __restrict__ S, float* __restrict__ val) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) val[e] = (float)(w[e] / S[col[e]]);
+}
+
+// r_next = fl32(c y + (1 - c) [i == seed]) (the same rounding as k_rwr_update)
+__global__ void k_rwr_step(const float* __restrict__ y, float* __restrict__ r, int64_t n, int32_t seed, double c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = (float)(c * (double)y[i] + (i == seed ? 1.0 - c : 0.0));
+}
+
+__global__ void k_scale(const float* __restrict__ y, float* __restrict__ g, int64_t n, double c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = (float)(c * (double)y[i]);
+}
+
+// G_e += g_{row(e)} r_{col(e)}  (one adjoint step of dL/dW, before the factor c)
+__global__ void k_edge_accum(const int32_t* __restrict__ row_of, const int32_t* __restrict__ col, int64_t nnz,
+                             const float* __restrict__ g, const float* __restrict__ r, double* __restrict__ G) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) G[e] = fma((double)g[row_of[e]], (double)r[col[e]], G[e]);
+}
+
+// row index of every entry: short rows by their thread, long rows (> 64
+// entries) by the whole wavefront in turn
+__global__ void k_rows_of(const int64_t* __restrict__ rp, int64_t n_rows, int32_t* __restrict__ row_of) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = lane_id();
+  int64_t a = 0, b = 0;
+  if (i < n_rows) {
+    a = rp[i];
+    b = rp[i + 1];
+  }
+  const bool longrow = (b - a) > kWave;
+  if (!longrow)
+    for (int64_t e = a; e < b; ++e) row_of[e] = (int32_t)i;
+  uint64_t m = __ballot(longrow);
+  while (m) {
+    const int src = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int64_t aa = __shfl(a, src, kWave), bb = __shfl(b, src, kWave);
+    const int32_t r = (int32_t)__shfl((int64_t)i, src, kWave);
+    for (int64_t e = aa + lane; e < bb; e += kWave) row_of[e] = r;
+  }
+}
+
+__global__ void k_onehot(float* __restrict__ r, int64_t n, int32_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = i == seed ? 1.0f : 0.0f;
+}
+
+// per column j: cs_j = sum over its entries of dL/dW_e W_e, with dL/dW = c G
+// and W_e = w_e / S_j (wave per column, over the transpose)
+__global__ void __launch_bounds__(kB) k_col_dot(const int64_t* __restrict__ rpT, const int32_t* __restrict__ permT,
+                                                int64_t n_cols, const double* __restrict__ G,
+                                                const double* __restrict__ w, const double* __restrict__ S,
+                                                double c, double* __restrict__ cs) {
+  const int lane = lane_id();
+  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (j >= n_cols) return;
+  const int64_t a = rpT[j], b = rpT[j + 1];
+  const double sj = S[j];
+  double s = 0.0;
+  for (int64_t q = a + lane; q < b; q += kWave) {
+    const int32_t e = permT[q];
+    s += (c * G[e]) * (w[e] / sj);
+  }
+  s = wave_sum(s);
+  if (lane == 0) cs[j] = s;
+}
+
+// dL/dz_e = (dL/dW_e - cs_j) / S_j * sigmoid(z_e); per-block partial sums of
+// dL/dz_e f_e (nf of them), combined afterwards in block order
+constexpr int kGradBlocks = 1024;
+constexpr int kMaxFeat = 16;
+__global__ void __launch_bounds__(kB) k_theta_grad(const int32_t* __restrict__ col, int64_t nnz, int32_t nf,
+                                                   const float* __restrict__ feats, const double* __restrict__ z,
+                                                   const double* __restrict__ S, const double* __restrict__ G,
+                                                   const double* __restrict__ cs, double c,
+                                                   double* __restrict__ parts) {
+  double acc[kMaxFeat];
+#pragma unroll
+  for (int d = 0; d < kMaxFeat; ++d) acc[d] = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kB + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kB) {
+    const int32_t j = col[e];
+    const double dw = (c * G[e] - cs[j]) / S[j];
+    const double dz = dw / (1.0 + exp(-z[e]));
+#pragma unroll
+    for (int d = 0; d < kMaxFeat; ++d)
+      if (d < nf) acc[d] = fma(dz, (double)feats[e * nf + d], acc[d]);
+  }
+  __shared__ double sm[kMaxFeat][kB / kWave];
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int d = 0; d < kMaxFeat; ++d) {
+    const double t = wave_sum(acc[d]);
+    if (lane == 0) sm[d][wv] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < nf) {
+    double t = 0.0;
+    for (int q = 0; q < kB / kWave; ++q) t += sm[threadIdx.x][q];
+    parts[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 // ------------------------------------------------------------ host side
 struct Err {
   tc_status st;
@@ -1626,6 +1767,177 @@ extern "C" tc_status tc_rwr_multi(tc_handle* const* hs, int32_t n_graphs, const 
       set_error("tc_rwr_multi: tolerance not reached in max_iter iterations");
       return TC_ENOTCONV;
     }
+    return TC_OK;
+  });
+}
+
+// ---- differentiable RWR (host)
+namespace tc {
+namespace {
+// y := A x in the caller's ids (as tc_spmv)
+void spmv_user(tc_handle* h, const float* x, float* y, hipStream_t st) {
+  gather_rows(x, h->d_cperm, h->n_cols, 1, h->d_xbuf, st);
+  if (h->relabel) {
+    spmv_internal(h, h->d_xbuf, h->d_ybuf, st);
+    gather_rows(h->d_ybuf, h->d_rowmap, h->n_rows, 1, y, st);
+  } else {
+    spmv_internal(h, h->d_xbuf, y, st);
+  }
+}
+
+struct PoolBuf {
+  void* p = nullptr;
+  hipStream_t st;
+  PoolBuf(size_t bytes, hipStream_t s) : st(s) {
+    p = pool_alloc(bytes ? bytes : 1, s);
+    if (!p) throw Err{TC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  }
+  ~PoolBuf() { pool_free(p, st, false); }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
+int32_t n_checkpoints(int32_t K, int32_t every) { return K <= 0 ? 0 : (K + every - 1) / every; }
+}  // namespace
+}  // namespace tc
+
+extern "C" tc_status tc_rwr_edge_weights(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT,
+                                         const int32_t* d_permT, int32_t nf, const float* d_feats,
+                                         const double* theta, double* d_z, double* d_w, double* d_S, float* d_val,
+                                         float* d_valT, tc_stream_t stream) {
+  return guarded("tc_rwr_edge_weights", [&]() -> tc_status {
+    if (n_cols < 0 || nnz < 0 || nf < 1 || nf > kMaxFeat) throw Err{TC_EINVAL, "need sizes >= 0 and 1 <= nf <= 16"};
+    if (!theta || !d_rpT || !d_S || (nnz > 0 && (!d_col || !d_permT || !d_feats || !d_z || !d_w || !d_val || !d_valT)))
+      throw Err{TC_EINVAL, "NULL argument"};
+    hipStream_t st = (hipStream_t)stream;
+    PoolBuf th(sizeof(double) * nf, st);
+    HIPC(hipMemcpyAsync(th.p, theta, sizeof(double) * nf, hipMemcpyHostToDevice, st));
+    if (nnz > 0) {
+      hipLaunchKernelGGL(k_edge_softplus, dim3(nblk(nnz, kB)), dim3(kB), 0, st, d_feats, nnz, nf,
+                         th.as<const double>(), d_z, d_w);
+      HIPC(hipGetLastError());
+    }
+    if (n_cols > 0) {
+      hipLaunchKernelGGL(k_col_norm, dim3(nblk(n_cols, kWpb)), dim3(kB), 0, st, d_rpT, d_permT, n_cols,
+                         (const double*)d_w, d_S, d_valT);
+      HIPC(hipGetLastError());
+    }
+    if (nnz > 0) {
+      hipLaunchKernelGGL(k_edge_values, dim3(nblk(nnz, kB)), dim3(kB), 0, st, d_col, nnz, (const double*)d_w,
+                         (const double*)d_S, d_val);
+      HIPC(hipGetLastError());
+    }
+    HIPC(hipStreamSynchronize(st));  // theta's staging copy is released below
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_rwr_iterates(const tc_handle* hc, int32_t seed, float c, int32_t K, int32_t every,
+                                     float* d_ckpt, float* d_rK, tc_stream_t stream) {
+  return guarded("tc_rwr_iterates", [&]() -> tc_status {
+    if (!hc || (!d_rK && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    need_square(hc, "tc_rwr_iterates");
+    if (K < 0 || every < 1 || !(c >= 0.0f && c <= 1.0f)) throw Err{TC_EINVAL, "need K >= 0, every >= 1, 0 <= c <= 1"};
+    if (seed < 0 || seed >= hc->n_rows) throw Err{TC_EINVAL, "seed out of range"};
+    if (K > 0 && !d_ckpt) throw Err{TC_EINVAL, "NULL checkpoint array"};
+    tc_handle* h = const_cast<tc_handle*>(hc);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = h->n_rows;
+    PoolBuf y(sizeof(float) * n, st);
+    hipLaunchKernelGGL(k_onehot, dim3(nblk(n, kB)), dim3(kB), 0, st, d_rK, n, seed);
+    HIPC(hipGetLastError());
+    for (int32_t k = 0; k < K; ++k) {
+      if (k % every == 0)
+        HIPC(hipMemcpyAsync(d_ckpt + (int64_t)(k / every) * n, d_rK, sizeof(float) * n, hipMemcpyDeviceToDevice,
+                            st));
+      spmv_user(h, d_rK, y.as<float>(), st);
+      hipLaunchKernelGGL(k_rwr_step, dim3(nblk(n, kB)), dim3(kB), 0, st, y.as<const float>(), d_rK, n, seed,
+                         (double)c);
+      HIPC(hipGetLastError());
+    }
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_rwr_adjoint(const tc_handle* hc, const tc_handle* htc, const int64_t* d_rp,
+                                    const int32_t* d_col, int32_t seed, float c, int32_t K, int32_t every,
+                                    const float* d_ckpt, const float* d_gK, double* d_G, float* d_g0,
+                                    tc_stream_t stream) {
+  return guarded("tc_rwr_adjoint", [&]() -> tc_status {
+    if (!hc || !htc || !d_rp || (hc->n_rows > 0 && !d_gK)) throw Err{TC_EINVAL, "NULL argument"};
+    need_square(hc, "tc_rwr_adjoint");
+    need_square(htc, "tc_rwr_adjoint");
+    if (htc->n_rows != hc->n_rows || htc->nnz != hc->nnz) throw Err{TC_EINVAL, "the second handle must hold A^T"};
+    if (K < 0 || every < 1 || !(c >= 0.0f && c <= 1.0f)) throw Err{TC_EINVAL, "need K >= 0, every >= 1, 0 <= c <= 1"};
+    if (seed < 0 || seed >= hc->n_rows) throw Err{TC_EINVAL, "seed out of range"};
+    const int64_t n = hc->n_rows, nnz = hc->nnz;
+    if (nnz > 0 && (!d_col || !d_G)) throw Err{TC_EINVAL, "NULL argument"};
+    if (K > 0 && !d_ckpt) throw Err{TC_EINVAL, "NULL checkpoint array"};
+    tc_handle* h = const_cast<tc_handle*>(hc);
+    tc_handle* ht = const_cast<tc_handle*>(htc);
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t seglen = std::min(every, std::max(K, 1));
+    PoolBuf seg(sizeof(float) * (size_t)n * seglen, st), g(sizeof(float) * n, st), tmp(sizeof(float) * n, st),
+        rows(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), st);
+    if (nnz > 0) {
+      HIPC(hipMemsetAsync(d_G, 0, sizeof(double) * nnz, st));
+      hipLaunchKernelGGL(k_rows_of, dim3(nblk(n, kB)), dim3(kB), 0, st, d_rp, n, rows.as<int32_t>());
+      HIPC(hipGetLastError());
+    }
+    if (n > 0) HIPC(hipMemcpyAsync(g.p, d_gK, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    float* S = seg.as<float>();
+    for (int32_t q = n_checkpoints(K, every) - 1; q >= 0; --q) {
+      const int32_t k0 = q * every, k1 = std::min(K, k0 + every);
+      // recompute r^{k0} .. r^{k1-1} from the checkpoint
+      HIPC(hipMemcpyAsync(S, d_ckpt + (int64_t)q * n, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+      for (int32_t t = 1; t < k1 - k0; ++t) {
+        spmv_user(h, S + (int64_t)(t - 1) * n, tmp.as<float>(), st);
+        hipLaunchKernelGGL(k_rwr_step, dim3(nblk(n, kB)), dim3(kB), 0, st, tmp.as<const float>(), S + (int64_t)t * n,
+                           n, seed, (double)c);
+        HIPC(hipGetLastError());
+      }
+      for (int32_t k = k1 - 1; k >= k0; --k) {
+        if (nnz > 0) {
+          hipLaunchKernelGGL(k_edge_accum, dim3(nblk(nnz, kB)), dim3(kB), 0, st, rows.as<const int32_t>(), d_col,
+                             nnz, g.as<const float>(), (const float*)(S + (int64_t)(k - k0) * n), d_G);
+          HIPC(hipGetLastError());
+        }
+        spmv_user(ht, g.as<const float>(), tmp.as<float>(), st);
+        hipLaunchKernelGGL(k_scale, dim3(nblk(n, kB)), dim3(kB), 0, st, tmp.as<const float>(), g.as<float>(), n,
+                           (double)c);
+        HIPC(hipGetLastError());
+      }
+    }
+    if (d_g0 && n > 0) HIPC(hipMemcpyAsync(d_g0, g.p, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_rwr_theta_grad(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT,
+                                       const int32_t* d_permT, int32_t nf, const float* d_feats, const double* d_z,
+                                       const double* d_w, const double* d_S, const double* d_G, float c,
+                                       double* dtheta, tc_stream_t stream) {
+  return guarded("tc_rwr_theta_grad", [&]() -> tc_status {
+    if (n_cols < 0 || nnz < 0 || nf < 1 || nf > kMaxFeat) throw Err{TC_EINVAL, "need sizes >= 0 and 1 <= nf <= 16"};
+    if (!dtheta || !d_rpT || !d_S ||
+        (nnz > 0 && (!d_col || !d_permT || !d_feats || !d_z || !d_w || !d_G)))
+      throw Err{TC_EINVAL, "NULL argument"};
+    hipStream_t st = (hipStream_t)stream;
+    PoolBuf cs(sizeof(double) * (size_t)std::max<int64_t>(n_cols, 1), st),
+        parts(sizeof(double) * (size_t)kGradBlocks * nf, st), out(sizeof(double) * nf, st);
+    if (n_cols > 0) {
+      hipLaunchKernelGGL(k_col_dot, dim3(nblk(n_cols, kWpb)), dim3(kB), 0, st, d_rpT, d_permT, n_cols, d_G, d_w, d_S,
+                         (double)c, cs.as<double>());
+      HIPC(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_theta_grad, dim3(kGradBlocks), dim3(kB), 0, st, d_col, nnz, nf, d_feats, d_z, d_S, d_G,
+                       cs.as<const double>(), (double)c, parts.as<double>());
+    HIPC(hipGetLastError());
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, parts.as<const double>(), kGradBlocks, nf,
+                       out.as<double>());
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(dtheta, out.p, sizeof(double) * nf, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
     return TC_OK;
   });
 }

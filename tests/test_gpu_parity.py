@@ -402,3 +402,60 @@ def test_rwr_multi_tolerance_and_empty():
     assert out == [] and it == 0
     with pytest.raises(TcError):
         rwr_multi(mats[:2], [seeds[0], -1], 0.85, 0.0, 5, 1)
+
+
+# ------------------------------------------------------------ differentiable RWR
+def test_csr_transpose_bit_exact():
+    g = gg.rmat(11, 8, seed=12)
+    n, _, rp, col, val = gg.pagerank_matrix(g)
+    A = DeviceCsr((n, n, rp, col, val))
+    rpT = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    colT = torch.empty(len(col), dtype=torch.int32, device="cuda")
+    valT = torch.empty(len(col), dtype=torch.float32, device="cuda")
+    permT = torch.empty(len(col), dtype=torch.int32, device="cuda")
+    import ctypes
+    lib = tcmod.load_library()
+    c = A.c()
+    assert lib.tc_csr_transpose(ctypes.byref(c), ctypes.c_void_p(rpT.data_ptr()), ctypes.c_void_p(colT.data_ptr()),
+                                ctypes.c_void_p(valT.data_ptr()), ctypes.c_void_p(permT.data_ptr()), None) == 0
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    order = np.lexsort((rows, col))  # by column, then row: a stable sort by column
+    assert np.array_equal(permT.cpu().numpy(), order)
+    assert np.array_equal(colT.cpu().numpy(), rows[order])
+    assert np.array_equal(valT.cpu().numpy(), val[order])
+    assert np.array_equal(rpT.cpu().numpy(), np.concatenate([[0], np.cumsum(np.bincount(col, minlength=n))]))
+
+
+@pytest.mark.parametrize("scale,ef,every", [(10, 8, 7), (9, 12, 1), (11, 6, 30)])
+def test_rwr_gradient_matches_fp64_reference(scale, ef, every):
+    from test_oracle_rwr_grad import problem
+    from oracle import rwr_grad as rg
+    from paper_1103_2405_amd.rwr_grad import EdgeWeightedRWR
+    n, rp, col, feats, theta, s, targets = problem(scale, ef, 31 + scale)
+    model = EdgeWeightedRWR((n, n, rp, col), feats, s, 0.85, 30, every=every)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    r = model.scores(th)
+    loss = -torch.log(r[torch.as_tensor(targets).cuda()].double()).sum()
+    loss.backward()
+    ref_loss, ref_grad, _ = rg.loss_and_grad(n, rp, col, feats, theta, s, targets, 0.85, 30)
+    say("loss", loss.item(), ref_loss, "grad", th.grad.numpy(), ref_grad)
+    assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
+    assert np.linalg.norm(th.grad.numpy() - ref_grad) <= 1e-4 * np.linalg.norm(ref_grad)
+    # the forward is the RWR driver's iteration on the same FP32 matrix
+    one, _, _ = model.W.rwr([s], 0.85, 0.0, 30)
+    assert torch.equal(one[:, 0], r.detach())
+    model.close()
+
+
+def test_rwr_gradient_does_not_depend_on_checkpoint_interval():
+    from test_oracle_rwr_grad import problem
+    from paper_1103_2405_amd.rwr_grad import EdgeWeightedRWR
+    n, rp, col, feats, theta, s, targets = problem(9, 8, 77)
+    grads = []
+    for every in (1, 4, 30):
+        model = EdgeWeightedRWR((n, n, rp, col), feats, s, 0.85, 30, every=every)
+        th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+        (-torch.log(model.scores(th)[torch.as_tensor(targets).cuda()].double()).sum()).backward()
+        grads.append(th.grad.numpy().copy())
+        model.close()
+    assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[0], grads[2])
