@@ -230,6 +230,47 @@ def diff_rwr(K: int = 30, every: int = 6, reps: int = 3):
             "backward_ms": round(min(bw) * 1e3, 2)}
 
 
+def kernel_compare(A_cl23=None, reps: int = 20):
+    """TILE-COMPOSITE against TILE-COO (the paper's two kernels, Section 4):
+    microseconds per product and effective GB/s (the metric's byte count) on
+    power-law and non-power-law matrices, including the dense 2000 x 2000
+    case of Section 4."""
+    import torch
+    import graphgen as gg
+    from paper_1103_2405_amd import DeviceCsr, TiledMatrix
+    mats = []
+    if A_cl23 is not None:
+        mats.append(("pagerank-chung-lu-2^23", A_cl23))
+    mats.append(("pagerank-rmat-20", DeviceCsr(gg.pagerank_matrix(gg.rmat(20, 16, seed=20)))))
+    n = 1 << 20  # uniform random rows of 16 entries (not power-law)
+    rp = np.arange(n + 1, dtype=np.int64) * 16
+    mats.append(("uniform-random-2^20x16", DeviceCsr((n, n, rp, gg.uniform_int(n * 16, n, 77).astype(np.int32),
+                                                      gg.uniform_f32(n * 16, 78)))))
+    d = 2000
+    mats.append(("dense-2000", DeviceCsr((d, d, np.arange(d + 1, dtype=np.int64) * d,
+                                          np.tile(np.arange(d, dtype=np.int32), d), gg.uniform_f32(d * d, 2000)))))
+    out = {}
+    for name, A in mats:
+        nbytes = 8 * A.nnz + 4 * (A.n_rows + A.n_cols)
+        row = {"nnz": int(A.nnz)}
+        for kernel in ("composite", "coo"):
+            tm = TiledMatrix(A, kernel=kernel)
+            x = torch.rand(A.n_cols, device="cuda")
+            y = torch.empty(A.n_rows, device="cuda")
+            for _ in range(3):
+                tm.spmv_internal(x, y)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                tm.spmv_internal(x, y)
+            torch.cuda.synchronize()
+            us = (time.perf_counter() - t0) / reps * 1e6
+            row[kernel] = {"us": round(us, 1), "gbps": round(nbytes / us / 1e3, 1)}
+            tm.close()
+        out[name] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +376,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    kernels = None if args.no_rwr else kernel_compare(A)
+    if kernels:
+        log("kernels:", json.dumps(kernels))
+
     rwr = None
     if not args.no_rwr:
         del A
@@ -363,6 +408,7 @@ def main():
         "csr_baseline_spmv_gbps": round(spmv_bytes / (csr_ms / 1e3) / 1e9, 1),
         "roofline": roofline,
         "rwr_batched": rwr,
+        "kernels": kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

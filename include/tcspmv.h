@@ -87,6 +87,11 @@ typedef struct {
                                  G > 0: MI355X schedule -- tile 0 = columns [0, W), then G
                                  column ranges holding equal numbers of entries, run together
                                  with range g pinned to XCD g-1 and summed afterwards */
+  int32_t kernel;             /* 0: TILE-COMPOSITE (padded row-major / column-major workloads,
+                                 Solution 3; default).  1: TILE-COO -- each tile's entries in
+                                 coordinate form, equal intervals per wavefront and a segmented
+                                 sum (Section 3.1, Observation 3); the composite workloads are
+                                 still built (SpMM and the metadata use them) */
   const char* perf_table;     /* path of a throughput table for the model; NULL = built-in */
   /* optional device allocator for the handle's buffers; NULL = hipMalloc / hipFree */
   void* (*alloc)(size_t bytes, void* ctx);
@@ -98,7 +103,7 @@ typedef struct {
 typedef struct {
   int64_t n_rows, n_cols, nnz;
   int32_t tile_width, wave, split_len, relabel;  /* split_len as given (-1 = automatic) */
-  int32_t xcd_groups, pad_;
+  int32_t xcd_groups, kernel;
   int32_t n_dense_tiles;      /* T of Algorithm 1 */
   int32_t n_tiles;            /* T plus one if a sparse tile exists */
   int64_t n_workloads;
@@ -141,6 +146,10 @@ typedef struct {
   int32_t* idx;               /* [nnz_pad] internal column id; pads: the tile's first column */
   float* val;                 /* [nnz_pad] value; pads: +0.0 */
   int32_t* rowid;             /* [n_rowid] internal row id; pad rows: -1 */
+  /* TILE-COO handles only ([nnz], tile t at offset sum of tile_nnz before t): */
+  int32_t* coo_row;           /* internal row id, bit 30 set when an earlier tile holds the row */
+  int32_t* coo_col;           /* internal column id */
+  float* coo_val;             /* value */
 } tc_format_view;
 
 /* Accumulated time of the tile kernels when timing is enabled (tc_set_timing). */

@@ -50,7 +50,8 @@ def xcd_boundaries(clen_sorted: np.ndarray, W: int, groups: int) -> list:
 
 def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S: int = 64,
           split_len: int = -1, camping_pad: bool = False, relabel: Optional[bool] = None,
-          table: Optional[PerfTable] = None, max_act_warp: int = 8192, xcd_groups: int = 0) -> dict:
+          table: Optional[PerfTable] = None, max_act_warp: int = 8192, xcd_groups: int = 0,
+          coo: bool = False) -> dict:
     n_rows, n_cols, rp, col, val = csr
     rp = np.asarray(rp, np.int64)
     col = np.asarray(col, np.int32)
@@ -180,7 +181,21 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
         idx_out[dest] = cpos[col[src]]
         val_out[dest] = val[src]
 
+    extra = {}
+    if coo:
+        # TILE-COO (Section 3.1, Observation 3): each tile's entries in
+        # coordinate form, in the bucketed order (tiles ascending, rows ascending
+        # inside a tile, input order inside a row).  A row whose first tile is
+        # an earlier one carries bit 30 (the kernel adds to y instead of storing).
+        rows_b = row_of[order]
+        tile_b = tile_of[order]
+        first_tile = np.full(n_rows, np.iinfo(np.int64).max, np.int64)
+        np.minimum.at(first_tile, rows_b, tile_b)
+        flag = np.where(first_tile[rows_b] < tile_b, 1 << 30, 0)
+        extra = dict(coo_row=(rmap[rows_b] | flag).astype(np.int32), coo_col=icol[order].astype(np.int32),
+                     coo_val=val[order].astype(np.float32))
     return dict(
+        **extra,
         n_rows=n_rows, n_cols=n_cols, nnz=nnz, W=W, S=S, split_len=split_len, T=T, xcd_groups=xcd_groups,
         tile_split=np.asarray(split_used, np.int64),
         n_tiles_total=ntiles, relabel=bool(relabel),

@@ -25,6 +25,7 @@ extern "C" tc_status tc_handle_info(const tc_handle* h, tc_info* info) {
   info->split_len = h->split_len;
   info->relabel = h->relabel ? 1 : 0;
   info->xcd_groups = h->xcd_groups;
+  info->kernel = h->kernel;
   info->n_dense_tiles = h->T;
   info->n_tiles = h->n_tiles;
   info->n_workloads = h->n_wl;
@@ -72,6 +73,11 @@ extern "C" tc_status tc_export_format(const tc_handle* h, tc_format_view* v) {
   chk(d2h(v->idx, h->d_idx, h->nnz_pad));
   chk(d2h(v->val, h->d_val, h->nnz_pad));
   chk(d2h(v->rowid, h->d_rowid, h->n_rowid));
+  if (h->kernel == 1) {
+    chk(d2h(v->coo_row, h->d_coo_row, h->nnz));
+    chk(d2h(v->coo_col, h->d_coo_col, h->nnz));
+    chk(d2h(v->coo_val, h->d_coo_val, h->nnz));
+  }
   if (v->rowid)  // the first-writer flag is an implementation detail of the kernels
     for (int64_t k = 0; k < h->n_rowid; ++k)
       if (v->rowid[k] >= 0) v->rowid[k] &= ~kAddFlag;
@@ -155,6 +161,7 @@ extern "C" void tc_destroy(tc_handle* h) {
   }
   if (h->d_ws) tc::pool_free(h->d_ws, nullptr, true);
   if (h->d_mm_partial) tc::pool_free(h->d_mm_partial, nullptr, true);
+  if (h->d_coo_carry) tc::pool_free(h->d_coo_carry, nullptr, true);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
 }

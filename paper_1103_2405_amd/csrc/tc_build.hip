@@ -847,6 +847,36 @@ void transpose(const tc_csr* A, int64_t* rpT, int32_t* colT, float* valT, int32_
   HIPX(hipStreamSynchronize(st));  // the host total above is read by the copy
 }
 
+// TILE-COO: first tile holding each row (tiles ascend in the bucketed order)
+__global__ void k_coo_first(const int32_t* __restrict__ rows, const int64_t* __restrict__ tstart, int32_t ntiles,
+                            const int32_t* __restrict__ rowmap, int64_t nnz, int32_t* __restrict__ first) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  int32_t lo = 0, hi = ntiles - 1;  // tile of entry e: last t with tstart[t] <= e
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (tstart[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  atomicMin(&first[rowmap[rows[e]]], lo);
+}
+
+__global__ void k_coo_pack(const int32_t* __restrict__ rows, const int32_t* __restrict__ icol,
+                           const float* __restrict__ val, const int64_t* __restrict__ tstart, int32_t ntiles,
+                           const int32_t* __restrict__ rowmap, const int32_t* __restrict__ first, int64_t nnz,
+                           int32_t* __restrict__ crow, int32_t* __restrict__ ccol, float* __restrict__ cval) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  int32_t lo = 0, hi = ntiles - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (tstart[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  const int32_t r = rowmap[rows[e]];
+  crow[e] = r | (first ? (first[r] == lo ? 0 : kAddFlag) : 0);
+  ccol[e] = icol[e];
+  cval[e] = val[e];
+}
+
 // TC_BUILD_TRACE=1: synchronise after every phase and print its wall time
 struct PhaseClock {
   hipStream_t st;
@@ -1286,6 +1316,35 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
                        rows_sorted, b_icol, b_val, (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid);
     HIPX(hipGetLastError());
   }
+  // TILE-COO: the bucketed entries themselves, with internal rows and the
+  // first-touch flag of the coordinate kernel (a row's first tile stores)
+  h->tile_coo_off = tstart;
+  if (h->kernel == 1 && nnz > 0) {
+    const int32_t* rows = b_row;
+    if (!rows) {  // one tile: entries in CSR order
+      int32_t* r = tmp.get<int32_t>(nnz);
+      hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, r);
+      HIPX(hipGetLastError());
+      rows = r;
+    }
+    int64_t* d_ts = tmp.get<int64_t>(ntiles + 1);
+    HIPX(hipMemcpyAsync(d_ts, tstart.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, st));
+    int32_t* cfirst = nullptr;
+    if (ntiles > 1) {
+      cfirst = tmp.get<int32_t>(n_rows);
+      hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, cfirst, n_rows, (int32_t)0x7fffffff);
+      hipLaunchKernelGGL(k_coo_first, dim3(nblk(nnz, kB)), dim3(kB), 0, st, rows, (const int64_t*)d_ts, ntiles,
+                         (const int32_t*)rowmap, nnz, cfirst);
+      HIPX(hipGetLastError());
+    }
+    h->d_coo_row = hold<int32_t>(h, nnz);
+    h->d_coo_col = hold<int32_t>(h, nnz);
+    h->d_coo_val = hold<float>(h, nnz);
+    hipLaunchKernelGGL(k_coo_pack, dim3(nblk(nnz, kB)), dim3(kB), 0, st, rows, (const int32_t*)b_icol, b_val,
+                       (const int64_t*)d_ts, ntiles, (const int32_t*)rowmap, (const int32_t*)cfirst, nnz,
+                       h->d_coo_row, h->d_coo_col, h->d_coo_val);
+    HIPX(hipGetLastError());
+  }
   // rows without any entry: every product writes their zero
   if (n_rows > 0) {
     int32_t* ef = tmp.get<int32_t>(n_rows);
@@ -1368,7 +1427,7 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
     set_error("tc_build_tiled: NULL CSR array");
     return TC_EINVAL;
   }
-  if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->xcd_groups < 0 || o->xcd_groups > 64 || o->max_act_warp < 0 || o->wl_policy < 0 ||
+  if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->xcd_groups < 0 || o->xcd_groups > 64 || o->kernel < 0 || o->kernel > 1 || (o->kernel == 1 && o->xcd_groups > 0) || o->max_act_warp < 0 || o->wl_policy < 0 ||
       o->wl_policy > 2 || (o->wl_policy == 1 && !o->wl_per_tile) || (o->relabel > 0 && A->n_rows != A->n_cols)) {
     set_error("tc_build_tiled: invalid option");
     return TC_EINVAL;
@@ -1388,6 +1447,7 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   h->relabel = o->relabel < 0 ? (A->n_rows == A->n_cols) : (o->relabel != 0);
   h->max_act_warp = o->max_act_warp > 0 ? o->max_act_warp : 8192;
   h->xcd_groups = o->xcd_groups;
+  h->kernel = o->kernel;
   h->alloc = o->alloc;
   h->dfree = o->free;
   h->alloc_ctx = o->alloc_ctx;

@@ -142,6 +142,14 @@ struct tc_handle {
   int64_t n_zero0 = 0;
   int n_cu = 256;                   // compute units of the device
   int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
+  // TILE-COO (kernel == 1): every tile's entries in coordinate form
+  int32_t kernel = 0;
+  int32_t* d_coo_row = nullptr;     // internal row | kAddFlag when an earlier tile holds the row
+  int32_t* d_coo_col = nullptr;     // internal column
+  float* d_coo_val = nullptr;
+  std::vector<int64_t> tile_coo_off;  // [n_tiles + 1]
+  void* d_coo_carry = nullptr;      // per-wavefront partial sums of rows crossing intervals
+  int64_t coo_carry_n = 0;
   // SpMM plan (lazily built): leading chunk workloads per tile, pieces per chunk
   bool mm_planned = false;
   std::vector<int64_t> mm_lead;

@@ -810,6 +810,142 @@ __global__ void k_max_of(const double* __restrict__ v, int n, double* out) {
   }
 }
 
+// ---- TILE-COO (Section 3.1, Observation 3)
+//
+// A tile's entries, sorted by row, are cut into intervals of kCooIv entries,
+// one per wavefront, whatever the row lengths.  Lane l takes kCooPer
+// consecutive entries and sums them row by row: rows that start and end in
+// its run are written at once; its first and last row go to a segmented scan
+// across the lanes (pairs (a, g): out_l = a_l + g_l out_{l-1}, g = 1 when the
+// lane holds a single row continuing the previous lane's last one).  A row
+// that crosses an interval boundary leaves partial sums in a per-wavefront
+// record; a fix-up pass adds them in interval order.  All sums are FP64 in a
+// fixed order; y gets fl32 once per row and tile (store, or add when an
+// earlier tile holds the row).
+constexpr int kCooPer = 8;
+constexpr int kCooIv = kWave * kCooPer;
+
+struct CooCarry {
+  int32_t row0, row1;  // first and last row of the interval (flagged ids)
+  int32_t flags;       // 1: row0 started before the interval, 2: row1 continues after it, 4: single row
+  int32_t pad;
+  double p0, p1;       // this interval's partial sums of row0 and row1
+};
+
+__device__ inline void coo_write(float* __restrict__ y, int32_t rf, double s) {
+  const int32_t r = rf & ~kAddFlag;
+  if (rf & kAddFlag)
+    y[r] = (float)((double)y[r] + s);
+  else
+    y[r] = (float)s;
+}
+
+__global__ void __launch_bounds__(kB) k_tile_coo(const int32_t* __restrict__ crow, const int32_t* __restrict__ ccol,
+                                                 const float* __restrict__ cval, int64_t n,
+                                                 const float* __restrict__ x, float* __restrict__ y,
+                                                 CooCarry* __restrict__ carry) {
+  const int lane = lane_id();
+  const int64_t w = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t b = w * kCooIv;
+  if (b >= n) return;
+  const int64_t e = min(n, b + (int64_t)kCooIv);
+  const int last = (int)((e - b - 1) / kCooPer);  // last lane holding entries
+  const int64_t s0 = b + (int64_t)lane * kCooPer;
+  const int cnt = lane <= last ? (int)min<int64_t>(kCooPer, e - s0) : 0;
+  int32_t rr[kCooPer];
+  double pp[kCooPer];
+#pragma unroll
+  for (int j = 0; j < kCooPer; ++j) {
+    rr[j] = j < cnt ? crow[s0 + j] : 0;
+    pp[j] = j < cnt ? (double)cval[s0 + j] * (double)x[ccol[s0 + j]] : 0.0;
+  }
+  // lane pass
+  const int32_t first = rr[0];
+  int32_t cur = first;
+  double acc = 0.0, head = 0.0;
+  bool multi = false;
+#pragma unroll
+  for (int j = 0; j < kCooPer; ++j) {
+    if (j < cnt) {
+      if (rr[j] != cur) {
+        if (!multi) {
+          head = acc;
+          multi = true;
+        } else {
+          coo_write(y, cur, acc);  // a row inside this lane's run
+        }
+        cur = rr[j];
+        acc = 0.0;
+      }
+      acc += pp[j];
+    }
+  }
+  const int32_t tail_row = cur;
+  // scan over lanes
+  const int32_t prev_tail = __shfl_up(tail_row, 1, kWave);
+  const bool cont = lane > 0 && lane <= last && first == prev_tail;  // first row continues lane l-1's last
+  double a = lane <= last ? acc : 0.0;
+  int g = (lane <= last && !multi && cont) ? 1 : 0;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double au = __shfl_up(a, o, kWave);
+    const int gu = __shfl_up(g, o, kWave);
+    if (lane >= o) {
+      if (g) a += au;
+      g = g & gu;
+    }
+  }
+  const double out_prev = __shfl_up(a, 1, kWave);
+  const double c_in = cont ? out_prev : 0.0;
+  // interval boundary rows
+  const int32_t R0 = __shfl(first, 0, kWave), R1 = __shfl(tail_row, last, kWave);
+  const bool cont_in = b > 0 && crow[b - 1] == R0;
+  const bool cont_out = e < n && crow[e] == R1;
+  const bool single = R0 == R1;
+  // completion of the lane's first row (multi-row lanes)
+  if (lane <= last && multi) {
+    const double t = head + c_in;
+    if (first == R0 && cont_in)
+      carry[w].p0 = t;
+    else
+      coo_write(y, first, t);
+  }
+  // completion of the lane's last row
+  const int32_t next_first = __shfl_down(first, 1, kWave);
+  if (lane <= last) {
+    const bool ends_here = lane < last ? next_first != tail_row : !cont_out;
+    if (lane == last && cont_out) {
+      carry[w].p1 = a;
+      if (single) carry[w].p0 = a;
+    } else if (ends_here) {
+      if (tail_row == R0 && cont_in)
+        carry[w].p0 = a;
+      else
+        coo_write(y, tail_row, a);
+    }
+  }
+  if (lane == 0) {
+    carry[w].row0 = R0;
+    carry[w].row1 = R1;
+    carry[w].flags = (cont_in ? 1 : 0) | (cont_out ? 2 : 0) | (single ? 4 : 0);
+  }
+}
+
+// rows crossing interval boundaries: the interval where such a row starts
+// adds the partial sums of the following intervals, in order, and writes it
+__global__ void k_coo_fixup(const CooCarry* __restrict__ carry, int64_t nw, float* __restrict__ y) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  const CooCarry c = carry[w];
+  if (!(c.flags & 2) || ((c.flags & 4) && (c.flags & 1))) return;
+  double t = c.p1;
+  for (int64_t v = w + 1; v < nw; ++v) {
+    const CooCarry d = carry[v];
+    t += d.p0;
+    if (!((d.flags & 4) && (d.flags & 2))) break;
+  }
+  coo_write(y, c.row1, t);
+}
+
 // ---- several graphs per launch (batched RWR over many small graphs)
 //
 // One launch runs tile t of every graph.  A segment is one graph's tile t:
@@ -1161,6 +1297,29 @@ void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool 
     hipLaunchKernelGGL(k_begin_spmv, dim3(nblk(nz, kB)), dim3(kB), 0, st, y,
                        (const int32_t*)(xcd ? h->d_zero0 : h->d_empty), nzero, h->d_counters, (int32_t)h->n_tiles);
     HIPC(hipGetLastError());
+  }
+  if (h->kernel == 1) {  // TILE-COO: tiles in order, each an interval pass and its fix-up
+    int64_t maxw = 0;
+    for (int t = 0; t < h->n_tiles; ++t)
+      maxw = std::max<int64_t>(maxw, (h->tile_coo_off[t + 1] - h->tile_coo_off[t] + kCooIv - 1) / kCooIv);
+    if (maxw > h->coo_carry_n) {
+      if (h->d_coo_carry) pool_free(h->d_coo_carry, st, false);
+      h->d_coo_carry = pool_alloc(sizeof(CooCarry) * maxw, st);
+      h->coo_carry_n = h->d_coo_carry ? maxw : 0;
+      if (!h->d_coo_carry) throw Err{TC_ENOMEM, "TILE-COO carry records: allocation failed"};
+    }
+    for (int t = 0; t < h->n_tiles; ++t) {
+      const int64_t o = h->tile_coo_off[t], nt = h->tile_coo_off[t + 1] - o;
+      if (nt == 0) continue;
+      const int64_t nw = (nt + kCooIv - 1) / kCooIv;
+      launch_tile(h, k_tile_coo, dim3(nblk(nw, kWpb)), dim3(kB), 0, st, (const int32_t*)(h->d_coo_row + o),
+                  (const int32_t*)(h->d_coo_col + o), (const float*)(h->d_coo_val + o), nt, x, y,
+                  (CooCarry*)h->d_coo_carry);
+      hipLaunchKernelGGL(k_coo_fixup, dim3(nblk(nw, kB)), dim3(kB), 0, st, (const CooCarry*)h->d_coo_carry, nw, y);
+      HIPC(hipGetLastError());
+    }
+    h->spmv_calls++;
+    return;
   }
   for (int t = 0; t < (xcd ? 1 : h->n_tiles); ++t) {
     const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];

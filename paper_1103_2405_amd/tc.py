@@ -43,14 +43,14 @@ class CCsr(ctypes.Structure):
 class CBuildOpts(ctypes.Structure):
     _fields_ = [("tile_width", i32), ("n_tiles", i32), ("wl_policy", i32), ("wl_all", i32),
                 ("wl_per_tile", vp), ("n_wl_per_tile", i32), ("wave", i32), ("split_len", i32),
-                ("camping_pad", i32), ("relabel", i32), ("max_act_warp", i32), ("xcd_groups", i32),
+                ("camping_pad", i32), ("relabel", i32), ("max_act_warp", i32), ("xcd_groups", i32), ("kernel", i32),
                 ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
 
 
 class CInfo(ctypes.Structure):
     _fields_ = [("n_rows", i64), ("n_cols", i64), ("nnz", i64),
                 ("tile_width", i32), ("wave", i32), ("split_len", i32), ("relabel", i32),
-                ("xcd_groups", i32), ("pad_", i32), ("n_dense_tiles", i32), ("n_tiles", i32),
+                ("xcd_groups", i32), ("kernel", i32), ("n_dense_tiles", i32), ("n_tiles", i32),
                 ("n_workloads", i64), ("nnz_pad", i64), ("n_rowid", i64), ("n_rows_sorted", i64),
                 ("n_split_rows", i64), ("n_partials", i64), ("n_dangling", i64), ("device_bytes", i64),
                 ("build_us", ctypes.c_double), ("model_us", ctypes.c_double)]
@@ -68,7 +68,9 @@ _VIEW_FIELDS = [("cperm", np.int32, "n_cols"), ("rowmap", np.int32, "n_rows"),
                 ("wl_n_rows", np.int32, "n_workloads"), ("wl_chunk", np.int32, "n_workloads"),
                 ("wl_n_chunks", np.int32, "n_workloads"), ("wl_data_off", np.int64, "n_workloads"),
                 ("wl_rowid_off", np.int64, "n_workloads"), ("idx", np.int32, "nnz_pad"),
-                ("val", np.float32, "nnz_pad"), ("rowid", np.int32, "n_rowid")]
+                ("val", np.float32, "nnz_pad"), ("rowid", np.int32, "n_rowid"),
+                ("coo_row", np.int32, "nnz_coo"), ("coo_col", np.int32, "nnz_coo"),
+                ("coo_val", np.float32, "nnz_coo")]
 
 
 class CFormatView(ctypes.Structure):
@@ -188,7 +190,7 @@ class TiledMatrix:
     def __init__(self, csr, tile_width: int = 0, n_tiles: int = -1, wl: Optional[Sequence[int] | int] = None,
                  wave: int = 64, split_len: int = -1, camping_pad: bool = False, relabel: int = -1,
                  max_act_warp: int = 0, perf_table: Optional[str] = "default", xcd_groups: int = -1,
-                 stream=None):
+                 kernel: str = "composite", stream=None):
         lib = load_library()
         A = csr if isinstance(csr, DeviceCsr) else DeviceCsr(csr)
         self.n_rows, self.n_cols, self.nnz = A.n_rows, A.n_cols, A.nnz
@@ -198,6 +200,9 @@ class TiledMatrix:
         o.camping_pad, o.relabel, o.max_act_warp = int(camping_pad), relabel, max_act_warp
         if xcd_groups >= 0:
             o.xcd_groups = xcd_groups
+        if kernel not in ("composite", "coo"):
+            raise ValueError("kernel must be 'composite' or 'coo'")
+        o.kernel = 1 if kernel == "coo" else 0
         keep = None
         if wl is None:
             o.wl_policy = 0
@@ -253,16 +258,19 @@ class TiledMatrix:
         inf = self.info()
         sizes = dict(inf)
         sizes["n_tiles+1"] = inf["n_tiles"] + 1
+        sizes["nnz_coo"] = inf["nnz"] if inf["kernel"] == 1 else 0
         arrays, view = {}, CFormatView()
         for name, dt, sz in _VIEW_FIELDS:
-            if metadata_only and sz in ("nnz_pad", "n_rowid", "n_rows_sorted", "n_rows", "n_cols"):
+            if metadata_only and sz in ("nnz_pad", "n_rowid", "n_rows_sorted", "n_rows", "n_cols", "nnz_coo"):
+                continue
+            if sz == "nnz_coo" and inf["kernel"] != 1:
                 continue
             a = np.zeros(max(int(sizes[sz]), 0), dt)
             arrays[name] = a
             setattr(view, name, a.ctypes.data_as(vp) if a.size else None)
         _check(load_library().tc_export_format(self.handle, ctypes.byref(view)), "tc_export_format")
         arrays.update(T=inf["n_dense_tiles"], n_tiles_total=inf["n_tiles"], nnz_pad=inf["nnz_pad"],
-                      xcd_groups=inf["xcd_groups"],
+                      xcd_groups=inf["xcd_groups"], kernel=inf["kernel"],
                       W=inf["tile_width"], S=inf["wave"], split_len=inf["split_len"],
                       relabel=bool(inf["relabel"]), n_rows=inf["n_rows"], n_cols=inf["n_cols"])
         return arrays

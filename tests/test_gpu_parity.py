@@ -49,16 +49,16 @@ def assert_same_format(g, r):
 
 
 def build_both(csr, W, wl=None, S=64, split_len=-1, n_tiles=-1, camping_pad=False, table_path=None,
-               max_act_warp=8192, xcd_groups=0):
+               max_act_warp=8192, xcd_groups=0, kernel="composite"):
     say("build", csr[0], csr[1], len(csr[3]), "W", W, "wl", wl if not isinstance(wl, list) else wl[:3], "S", S,
         "split", split_len)
     wl_list = wl if wl is None or isinstance(wl, list) else [wl] * 4096
     ref = rf.build(csr, W=W, n_tiles=n_tiles, wl=wl_list, S=S, split_len=split_len, camping_pad=camping_pad,
                    table=PerfTable.load(table_path) if table_path else None, max_act_warp=max_act_warp,
-                   xcd_groups=xcd_groups)
+                   xcd_groups=xcd_groups, coo=kernel == "coo")
     gm = TiledMatrix(csr, tile_width=W, n_tiles=n_tiles, wl=wl, wave=S, split_len=split_len,
                      camping_pad=camping_pad, perf_table=table_path, max_act_warp=max_act_warp,
-                     xcd_groups=xcd_groups)
+                     xcd_groups=xcd_groups, kernel=kernel)
     return gm, ref
 
 
@@ -459,3 +459,52 @@ def test_rwr_gradient_does_not_depend_on_checkpoint_interval():
         grads.append(th.grad.numpy().copy())
         model.close()
     assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[0], grads[2])
+
+
+# ------------------------------------------------------------ TILE-COO
+@pytest.mark.parametrize("W,split", [(64, -1), (512, 256), (1 << 20, 0)])
+def test_tile_coo_format_and_products(W, split):
+    g = gg.rmat(12, 16, seed=3)
+    csr = gg.pagerank_matrix(g)
+    gm, ref = build_both(csr, W, wl=1024, split_len=split, kernel="coo")
+    fmt = gm.export_format()
+    assert_same_format(fmt, ref)
+    assert np.array_equal(fmt["coo_row"], ref["coo_row"]) and np.array_equal(fmt["coo_col"], ref["coo_col"])
+    assert np.array_equal(fmt["coo_val"].view(np.uint32), ref["coo_val"].view(np.uint32))
+    check_spmv(gm, csr, gg.uniform_f32(g.n, 9))
+
+
+def test_tile_coo_dyadic_bit_exact_long_rows():
+    # rows of 2500 entries cross several 512-entry intervals; every summation
+    # order is exact on dyadic inputs, so the result must be bit-exact
+    csr = _heavy_rows_csr(3000, 5, 2500, 6, 17, dyadic=True)
+    rng = np.random.default_rng(3)
+    x = rng.integers(-8, 9, size=csr[1]).astype(np.float32)
+    for W in (1 << 20, 700):
+        gm = TiledMatrix(csr, tile_width=W, kernel="coo")
+        check_spmv(gm, csr, x, exact=True)
+        assert gm.info()["kernel"] == 1
+
+
+def test_tile_coo_pagerank_and_empty_rows():
+    g = gg.rmat(14, 16, seed=14)
+    csr = gg.pagerank_matrix(g)
+    gm = TiledMatrix(csr, tile_width=4096, kernel="coo")
+    p, it, res = gm.pagerank(0.85, 0.0, 50)
+    ref, _, _ = oracle.pagerank(csr, 0.85, 0.0, 50)
+    assert np.abs(p.cpu().numpy() - ref).sum() <= 1e-6
+    # the same iterates as the composite kernel to FP32 rounding
+    pc, _, _ = TiledMatrix(csr, tile_width=4096).pagerank(0.85, 0.0, 50)
+    assert np.abs(p.cpu().numpy() - pc.cpu().numpy()).sum() <= 1e-6
+
+
+def test_dense_2000_matrix_both_kernels():
+    # the paper's dense 2000 x 2000 sanity case (Section 4)
+    n = 2000
+    rp = np.arange(n + 1, dtype=np.int64) * n
+    col = np.tile(np.arange(n, dtype=np.int32), n)
+    val = gg.uniform_f32(n * n, 2000)
+    csr = (n, n, rp, col, val)
+    x = gg.uniform_f32(n, 2001)
+    for kernel in ("composite", "coo"):
+        check_spmv(TiledMatrix(csr, kernel=kernel), csr, x)

@@ -230,3 +230,26 @@ def test_xcd_column_ranges(seed, W, groups):
             assert int(cs[e[0]:e[g] - 1].sum()) < -(-(g * rest) // groups) or g == groups
     x = gg.uniform_f32(400, seed)
     assert np.allclose(rf.spmv_format(fmt, x), oracle.spmv(csr, x), rtol=1e-12, atol=1e-14)
+
+
+def test_coo_arrays_follow_the_bucketed_order():
+    # the coordinate arrays of TILE-COO: every entry once, tiles ascending,
+    # rows ascending in a tile, and the add flag exactly on rows an earlier
+    # tile already holds
+    csr = gg.random_csr(40, 50, 0.2, 3, power=1.2)
+    f = rf.build(csr, W=8, wl=[64] * 100, S=4, coo=True)
+    assert len(f["coo_row"]) == f["nnz"]
+    flag = (f["coo_row"] >> 30) & 1
+    row = f["coo_row"] & ((1 << 30) - 1)
+    tile = np.repeat(np.arange(f["n_tiles_total"]), f["tile_nnz"])
+    assert np.all(np.diff(tile * (1 << 31) + row.astype(np.int64)) >= 0)
+    seen = set()
+    for t, r, fl in zip(tile, row, flag):
+        assert fl == (1 if any(s[1] == r and s[0] < t for s in seen) else 0)
+        seen.add((t, r))
+    # same multiset of (internal row, internal column, value) as the matrix
+    n, _, rp, col, val = csr
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    want = sorted(zip(f["rowmap"][rows].tolist(), f["cpos"][col].tolist(), val.view(np.uint32).tolist()))
+    got = sorted(zip(row.tolist(), f["coo_col"].tolist(), f["coo_val"].view(np.uint32).tolist()))
+    assert want == got
