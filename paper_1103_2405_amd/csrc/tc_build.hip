@@ -527,6 +527,7 @@ struct PackWl {
 };
 
 // a7: one wavefront per workload writes its rectangle, its pads and row ids.
+constexpr int kPackSlices = 4;
 __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int64_t n_wl,
                                              const int32_t* __restrict__ srt_start,
                                              const int32_t* __restrict__ rows_len,
@@ -534,23 +535,27 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
                                              const int32_t* __restrict__ b_icol, const float* __restrict__ b_val,
                                              const int32_t* __restrict__ first, int32_t* __restrict__ idx,
                                              float* __restrict__ val, int32_t* __restrict__ rowid) {
+  // kPackSlices wavefronts per workload, slice sl taking every kPackSlices-th
+  // row (RM), row block of 64 (CM) or 64-entry block (chunk)
   const int lane = lane_id();
-  const int64_t j = (int64_t)blockIdx.x * (kB / kWave) + threadIdx.x / kWave;
-  if (j >= n_wl) return;
+  const int64_t w = (int64_t)blockIdx.x * (kB / kWave) + threadIdx.x / kWave;
+  if (w >= n_wl * kPackSlices) return;
+  const int64_t j = w / kPackSlices;
+  const int sl = (int)(w % kPackSlices);
   const PackWl d = wls[j];
   const int64_t off = d.data_off;
   if (d.chunk_off >= 0) {
     const int32_t s = d.row_begin;
     const int64_t st = (int64_t)srt_start[s] + d.chunk_off;
     const int64_t L = d.chunk_len;
-    for (int64_t c = lane; c < d.w_pad; c += kWave) {
+    for (int64_t c = lane + (int64_t)sl * kWave; c < d.w_pad; c += (int64_t)kWave * kPackSlices) {
       const bool real = c < L;
       idx[off + c] = real ? b_icol[st + c] : d.tile_first;
       val[off + c] = real ? b_val[st + c] : 0.0f;
     }
-    if (lane == 0) rowid[d.rowid_off] = rows_sorted[s];
+    if (lane == 0 && sl == 0) rowid[d.rowid_off] = rows_sorted[s];
   } else if (d.layout == kRM) {
-    for (int32_t r = 0; r < d.n_rows; ++r) {
+    for (int32_t r = sl; r < d.n_rows; r += kPackSlices) {
       const int32_t s = d.row_begin + r;
       const int64_t st = srt_start[s];
       const int32_t L = rows_len[s];
@@ -566,7 +571,7 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
       }
     }
   } else {
-    for (int32_t r = lane; r < d.h_pad; r += kWave) {
+    for (int32_t r = lane + sl * kWave; r < d.h_pad; r += kWave * kPackSlices) {
       int64_t st = 0;
       int32_t L = 0, row = -1;
       if (r < d.n_rows) {
@@ -585,10 +590,11 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
     }
   }
   const int64_t end = off + (int64_t)d.w_pad * d.h_pad;
-  for (int32_t c = lane; c < d.extra; c += kWave) {
-    idx[end + c] = d.tile_first;
-    val[end + c] = 0.0f;
-  }
+  if (sl == 0)
+    for (int32_t c = lane; c < d.extra; c += kWave) {
+      idx[end + c] = d.tile_first;
+      val[end + c] = 0.0f;
+    }
 }
 
 // ------------------------------------------------------ counting-sort ops
@@ -1312,7 +1318,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     PackWl* d_pwl = tmp.get<PackWl>(nwl);
     HIPX(hipMemcpyAsync(d_pwl, pwl.data(), sizeof(PackWl) * nwl, hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(h->d_wl, dwl.data(), sizeof(Wl) * nwl, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_pack, dim3(nblk(nwl, kB / kWave)), dim3(kB), 0, st, d_pwl, nwl, srt_start, rows_len,
+    hipLaunchKernelGGL(k_pack, dim3(nblk(nwl * kPackSlices, kB / kWave)), dim3(kB), 0, st, d_pwl, nwl, srt_start, rows_len,
                        rows_sorted, b_icol, b_val, (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid);
     HIPX(hipGetLastError());
   }

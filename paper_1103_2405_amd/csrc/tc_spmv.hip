@@ -515,7 +515,7 @@ __device__ inline Vec<V> rm_range(const int32_t* __restrict__ idx, const float* 
 // shows up here: it is then done whole, as one piece).
 // SUB: rows summed per lane group in one column step (accumulators per lane).
 // `slices` wavefronts share a workload, slice s taking every slices-th step.
-template <int V, int SUB>
+template <int V, int SUB, int CU = 1>
 __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int64_t n_wl, int32_t slices,
                                                   const int32_t* __restrict__ idx,
                                                   const float* __restrict__ val, const int32_t* __restrict__ rowid,
@@ -543,7 +543,24 @@ __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int
       Vec<V> a[SUB];
 #pragma unroll
       for (int u = 0; u < SUB; ++u) a[u].zero();
-      for (int32_t c = 0; c < d.w_pad; ++c) {
+      int32_t c = 0;
+      if constexpr (CU == 2) {
+        // two columns per step: twice the X rows in flight, same accumulators
+        for (; c + 1 < d.w_pad; c += 2) {
+          const int64_t e = off + (int64_t)c * hp + r0 + lane;
+          const float vl0 = okl ? ld_nt(val + e) : 0.0f, vl1 = okl ? ld_nt(val + e + hp) : 0.0f;
+          const int32_t il0 = okl ? ld_nt(idx + e) : 0, il1 = okl ? ld_nt(idx + e + hp) : 0;
+          float v0[SUB], xv0[SUB][V], v1[SUB], xv1[SUB][V];
+          step_gather<V, SUB>(vl0, il0, subs, groups, g, X, k, col, act, v0, xv0);
+          step_gather<V, SUB>(vl1, il1, subs, groups, g, X, k, col, act, v1, xv1);
+#pragma unroll
+          for (int u = 0; u < SUB; ++u) {
+            if (v0[u] != 0.0f) fma_vec<V>(a[u], v0[u], xv0[u]);
+            if (v1[u] != 0.0f) fma_vec<V>(a[u], v1[u], xv1[u]);
+          }
+        }
+      }
+      for (; c < d.w_pad; ++c) {
         const int64_t e = off + (int64_t)c * hp + r0 + lane;
         const float vl = okl ? ld_nt(val + e) : 0.0f;
         const int32_t il = okl ? ld_nt(idx + e) : 0;
@@ -1288,12 +1305,16 @@ TileConfig tile_config() {
 // y := A x in internal ids (x: n_cols, y: n_rows)
 // fuse_combine: in the XCD schedule, leave y without the private copies (the
 // caller adds them in its own pass); split rows are then added to y first.
-void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine = false) {
+// skip_zero: y's empty rows are still zero from an earlier product into the
+// same y (nothing else writes them), so the zeroing launch can be left out
+// (one-tile-order schedule without the persistent variant only).
+void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine = false,
+                   bool skip_zero = false) {
   const TileConfig cfg = tile_config();
   const bool xcd = h->xcd_groups > 0 && h->n_tiles > 1;
   const int64_t nzero = xcd ? h->n_zero0 : h->n_empty;
   const int64_t nz = std::max<int64_t>(nzero, h->n_tiles);
-  if (nz > 0) {
+  if (nz > 0 && !(skip_zero && !xcd && !cfg.persist)) {
     hipLaunchKernelGGL(k_begin_spmv, dim3(nblk(nz, kB)), dim3(kB), 0, st, y,
                        (const int32_t*)(xcd ? h->d_zero0 : h->d_empty), nzero, h->d_counters, (int32_t)h->n_tiles);
     HIPC(hipGetLastError());
@@ -1395,8 +1416,9 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
   const int32_t pieces = h->mm_pieces;
   const int kchunks = (kq + kWave - 1) / kWave;
   // 4-wide lanes: four rows per sub-step group (fewer registers, more
-  // wavefronts resident) and each workload cut into four row slices
-  // (measured on a 31M-entry power-law matrix: 15% over one slice of eight)
+  // wavefronts resident), two columns per step, and each workload cut into
+  // four row slices (measured on a 31M-entry power-law matrix: 17% over one
+  // slice of eight rows and one column)
   const int32_t slices = v4 ? 4 : 1;
   double* partial = nullptr;
   if (h->n_slots > 0) {
@@ -1424,7 +1446,7 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
                   st, (const Wl*)(h->d_wl + b), lead, pieces, (const int32_t*)h->d_idx, (const float*)h->d_val, X, k,
                   kg, partial);
     if (e > b + lead)
-      launch_tile(h, v4 ? k_tile_spmm<4, 4> : k_tile_spmm<1, 8>, dim3(nblk((e - b - lead) * slices, kWpb), kchunks),
+      launch_tile(h, v4 ? k_tile_spmm<4, 4, 2> : k_tile_spmm<1, 8, 1>, dim3(nblk((e - b - lead) * slices, kWpb), kchunks),
                   dim3(kB), 0, st, (const Wl*)(h->d_wl + b + lead), (int64_t)(e - b - lead), slices,
                   (const int32_t*)h->d_idx,
                   (const float*)h->d_val, (const int32_t*)h->d_rowid, X, Y, k, kg, partial);
@@ -1565,7 +1587,7 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
       const bool xcd = h->xcd_groups > 0 && h->n_tiles > 1;
       const int32_t G = xcd ? h->n_tiles - 1 : 0;
       for (it = 0; it < max_iter;) {
-        spmv_internal(h, p, y, st, xcd);
+        spmv_internal(h, p, y, st, xcd, it > 0);
         hipLaunchKernelGGL(k_pr_update, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)y, (const float*)h->d_ypriv,
                            G, p, n, n - h->n_dangling, (double)c, (const double*)(res + 1), parts);
         HIPC(hipGetLastError());
