@@ -1114,10 +1114,30 @@ __global__ void __launch_bounds__(kB) k_col_norm(const int64_t* __restrict__ rpT
   if (j >= n_cols) return;
   const int64_t a = rpT[j], b = rpT[j + 1];
   double s = 0.0;
-  for (int64_t q = a + lane; q < b; q += kWave) s += w[permT[q]];
+  for (int64_t q0 = a; q0 < b; q0 += 8 * kWave) {  // eight gathers in flight (hub columns are long)
+    int32_t ee[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = q0 + u * kWave + lane;
+      ee[u] = q < b ? permT[q] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ee[u] >= 0) s += w[ee[u]];
+  }
   s = wave_sum(s);
   if (lane == 0) S[j] = s;
-  for (int64_t q = a + lane; q < b; q += kWave) valT[q] = (float)(w[permT[q]] / s);
+  for (int64_t q0 = a; q0 < b; q0 += 8 * kWave) {
+    int32_t ee[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = q0 + u * kWave + lane;
+      ee[u] = q < b ? permT[q] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ee[u] >= 0) valT[q0 + u * kWave + lane] = (float)(w[ee[u]] / s);
+  }
 }
 
 __global__ void k_edge_values(const int32_t* __restrict__ col, int64_t nnz, const double* __restrict__ w,
@@ -1137,12 +1157,20 @@ __global__ void k_scale(const float* __restrict__ y, float* __restrict__ g, int6
   if (i < n) g[i] = (float)(c * (double)y[i]);
 }
 
-// G_e += g_{row(e)} r_{col(e)}  (one adjoint step of dL/dW, before the factor c)
-__global__ void k_edge_accum(const int32_t* __restrict__ row_of, const int32_t* __restrict__ col, int64_t nnz,
-                             const float* __restrict__ g, const float* __restrict__ r, double* __restrict__ G) {
+// G_e += sum over the steps of one checkpoint segment, latest step first, of
+// g^{k+1}_{row(e)} r^k_{col(e)}: gs holds g^{k+1} and rs holds r^k for
+// k = k0 + m - 1 down to k0 (step t at offset t * n)
+__global__ void k_edge_accum_seg(const int32_t* __restrict__ row_of, const int32_t* __restrict__ col, int64_t nnz,
+                                 const float* __restrict__ gs, const float* __restrict__ rs, int32_t m, int64_t n,
+                                 double* __restrict__ G) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nnz) G[e] = fma((double)g[row_of[e]], (double)r[col[e]], G[e]);
+  if (e >= nnz) return;
+  const int32_t i = row_of[e], j = col[e];
+  double acc = G[e];
+  for (int32_t t = m - 1; t >= 0; --t) acc = fma((double)gs[(int64_t)t * n + i], (double)rs[(int64_t)t * n + j], acc);
+  G[e] = acc;
 }
+
 
 // row index of every entry: short rows by their thread, long rows (> 64
 // entries) by the whole wavefront in turn
@@ -1184,9 +1212,16 @@ __global__ void __launch_bounds__(kB) k_col_dot(const int64_t* __restrict__ rpT,
   const int64_t a = rpT[j], b = rpT[j + 1];
   const double sj = S[j];
   double s = 0.0;
-  for (int64_t q = a + lane; q < b; q += kWave) {
-    const int32_t e = permT[q];
-    s += (c * G[e]) * (w[e] / sj);
+  for (int64_t q0 = a; q0 < b; q0 += 8 * kWave) {
+    int32_t ee[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = q0 + u * kWave + lane;
+      ee[u] = q < b ? permT[q] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ee[u] >= 0) s += (c * G[ee[u]]) * (w[ee[u]] / sj);
   }
   s = wave_sum(s);
   if (lane == 0) cs[j] = s;
@@ -2058,7 +2093,8 @@ extern "C" tc_status tc_rwr_adjoint(const tc_handle* hc, const tc_handle* htc, c
     tc_handle* ht = const_cast<tc_handle*>(htc);
     hipStream_t st = (hipStream_t)stream;
     const int32_t seglen = std::min(every, std::max(K, 1));
-    PoolBuf seg(sizeof(float) * (size_t)n * seglen, st), g(sizeof(float) * n, st), tmp(sizeof(float) * n, st),
+    PoolBuf seg(sizeof(float) * (size_t)n * seglen, st), gseg(sizeof(float) * (size_t)n * seglen, st),
+        g(sizeof(float) * n, st), tmp(sizeof(float) * n, st),
         rows(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), st);
     if (nnz > 0) {
       HIPC(hipMemsetAsync(d_G, 0, sizeof(double) * nnz, st));
@@ -2077,15 +2113,20 @@ extern "C" tc_status tc_rwr_adjoint(const tc_handle* hc, const tc_handle* htc, c
                            n, seed, (double)c);
         HIPC(hipGetLastError());
       }
+      // adjoint vectors g^{k+1} of the segment, latest first, kept for one
+      // pass over the entries (which then reads them per step)
+      float* GS = gseg.as<float>();
       for (int32_t k = k1 - 1; k >= k0; --k) {
-        if (nnz > 0) {
-          hipLaunchKernelGGL(k_edge_accum, dim3(nblk(nnz, kB)), dim3(kB), 0, st, rows.as<const int32_t>(), d_col,
-                             nnz, g.as<const float>(), (const float*)(S + (int64_t)(k - k0) * n), d_G);
-          HIPC(hipGetLastError());
-        }
+        if (n > 0)
+          HIPC(hipMemcpyAsync(GS + (int64_t)(k - k0) * n, g.p, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
         spmv_user(ht, g.as<const float>(), tmp.as<float>(), st);
         hipLaunchKernelGGL(k_scale, dim3(nblk(n, kB)), dim3(kB), 0, st, tmp.as<const float>(), g.as<float>(), n,
                            (double)c);
+        HIPC(hipGetLastError());
+      }
+      if (nnz > 0) {
+        hipLaunchKernelGGL(k_edge_accum_seg, dim3(nblk(nnz, kB)), dim3(kB), 0, st, rows.as<const int32_t>(), d_col,
+                           nnz, (const float*)GS, (const float*)S, k1 - k0, n, d_G);
         HIPC(hipGetLastError());
       }
     }
