@@ -20,7 +20,7 @@ from oracle.autotune import PerfTable
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-if not torch.cuda.is_available():  # collected on a GPU machine only
+if not torch.cuda.is_available():  # these tests need a GPU
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_1103_2405_amd import TcError, TiledMatrix, DeviceCsr, csr_spmv  # noqa: E402
