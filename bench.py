@@ -71,10 +71,27 @@ def cpu_baseline(csr, budget_s: float):
     t0 = time.time()
     oracle.pagerank(csr, 0.85, 0.0, iters)
     dt = time.time() - t0
-    return {"value": round(iters * nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # one core, on a short sample of the same iteration
+    oracle.set_threads(1)
+    t0 = time.time()
+    oracle.pagerank(csr, 0.85, 0.0, 2)
+    one_core = 2 * nbytes / (time.time() - t0) / 1e9
+    oracle.set_threads(cores)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(iters * nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": cores,
             "kind": "oracle",
             "sample": "%d FP64 PageRank iterations of the same matrix (one CSR SpMV + update each), "
-                      "%.1f s; same byte formula" % (iters, dt)}
+                      "%.1f s; same byte formula" % (iters, dt),
+            "one_core_value": round(one_core, 3), "one_core_sample": "2 iterations (setup included)",
+            "cpu_model": model}
 
 
 def rwr_batched(c: float = 0.85, tol: float = 1e-6, ks=(1, 8, 32, 64)):
@@ -230,6 +247,47 @@ def diff_rwr(K: int = 30, every: int = 6, reps: int = 3):
             "backward_ms": round(min(bw) * 1e3, 2)}
 
 
+def rmat20_drivers(tol: float = 1e-6):
+    """R-MAT scale 20 (1,048,576 nodes, edge factor 16): one SpMV and PageRank,
+    HITS and one-query RWR run to an L1 change of tol (checked every 5
+    iterations), each on its own tiled build."""
+    import torch
+    import graphgen as gg
+    from paper_1103_2405_amd import DeviceCsr, TiledMatrix
+    g = gg.rmat(20, 16, seed=20)
+    out = {"graph": "rmat-20", "tol": tol}
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    A = DeviceCsr(gg.pagerank_matrix(g))
+    tm = TiledMatrix(A)
+    x = torch.rand(A.n_cols, device="cuda")
+    y = torch.empty(A.n_rows, device="cuda")
+    _, ms = timed(lambda: [tm.spmv_internal(x, y) for _ in range(20)])
+    nbytes = 8 * A.nnz + 4 * (A.n_rows + A.n_cols)
+    out["spmv"] = {"nnz": int(A.nnz), "us": round(ms * 1e3 / 20, 1), "gbps": round(nbytes / (ms / 20 * 1e6), 1),
+                   "n_tiles": tm.info()["n_tiles"], "wl": [int(v) for v in tm.export_format(True)["tile_wl"]]}
+    (p, it, res), ms = timed(lambda: tm.pagerank(0.85, tol, 1000, 5))
+    out["pagerank"] = {"iters": it, "resid": res, "ms": round(ms, 2)}
+    tm.close()
+    H = TiledMatrix(DeviceCsr(gg.hits_matrix(g)))
+    (a, h, it, res), ms = timed(lambda: H.hits(tol, 1000, 5))
+    out["hits"] = {"nnz": int(H.nnz), "iters": it, "resid": res, "ms": round(ms, 2)}
+    H.close()
+    R = TiledMatrix(DeviceCsr(gg.rwr_matrix(g)))
+    s = gg.rwr_seeds(g, 1, 40)
+    (r, it, res), ms = timed(lambda: R.rwr(s, 0.85, tol, 1000, 5))
+    out["rwr"] = {"nnz": int(R.nnz), "iters": it, "resid": res, "ms": round(ms, 2)}
+    R.close()
+    return out
+
+
 def kernel_compare(A_cl23=None, reps: int = 20):
     """TILE-COMPOSITE against TILE-COO (the paper's two kernels, Section 4):
     microseconds per product and effective GB/s (the metric's byte count) on
@@ -325,11 +383,13 @@ def main():
     # timed steps
     timing = not args.no_timing
     t0 = time.perf_counter()
-    infos = []
+    infos, marks = [], []
     for _ in range(args.steps):
         infos.append(step(timing))
+        marks.append(time.perf_counter())  # each step ends synchronised (PageRank reads its residual)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    per_step = np.diff(np.asarray([t0] + marks)) * 1e3
     ms_per_step = dt / args.steps * 1e3
     value = args.iters * spmv_bytes / (ms_per_step / 1e3) / 1e9
     info = infos[-1][0]
@@ -379,6 +439,9 @@ def main():
     kernels = None if args.no_rwr else kernel_compare(A)
     if kernels:
         log("kernels:", json.dumps(kernels))
+    drivers = None if args.no_rwr else rmat20_drivers()
+    if drivers:
+        log("rmat-20 drivers:", json.dumps(drivers))
 
     rwr = None
     if not args.no_rwr:
@@ -401,6 +464,8 @@ def main():
                        tile_width=info["tile_width"], n_tiles=info["n_tiles"],
                        n_workloads=info["n_workloads"], nnz_pad=info["nnz_pad"]),
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "step_ms": {"min": round(float(per_step.min()), 3), "median": round(float(np.median(per_step)), 3),
+                    "max": round(float(per_step.max()), 3)},
         "accumulate": "f64",
         "build_ms": round(info["build_us"] / 1e3, 3),
         "pagerank_ms": round(pr_ms, 3),
@@ -409,6 +474,7 @@ def main():
         "roofline": roofline,
         "rwr_batched": rwr,
         "kernels": kernels,
+        "rmat20_drivers": drivers,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

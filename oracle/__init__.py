@@ -73,6 +73,14 @@ def num_threads() -> int:
     return int(_load().or_num_threads())
 
 
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    lib = _load()
+    lib.or_set_threads.argtypes = [ctypes.c_int]
+    lib.or_set_threads.restype = None
+    lib.or_set_threads(int(n))
+
+
 def spmv(csr, x) -> np.ndarray:
     """y = A x in FP64 (x upcast from FP32 if it is FP32)."""
     n_rows, n_cols, rp, col, val = _csr(csr)

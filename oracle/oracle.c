@@ -198,3 +198,4 @@ int64_t or_rwr(int64_t n, const int64_t* row_ptr, const int32_t* col, const floa
 }
 
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int n) { omp_set_num_threads(n); }
