@@ -1,0 +1,66 @@
+"""The cache-size microbenchmark of Section 3.1 (Solution 1), on this GPU.
+
+The paper finds the tile width by taking the column indices modulo a width
+Wm, so that every x access falls in the first Wm entries, and sweeping Wm:
+the SpMV time stays flat while the segment fits the cache and rises beyond
+(the knee).  Here the matrix is the Chung-Lu PageRank matrix (or R-MAT 20),
+each modded matrix is built as one tile, and the tile-kernel time per product
+comes from HIP events around every launch.
+
+    python -m paper_1103_2405_amd.cache_sweep [--graph cl23|rmat20] [--reps 10]
+
+Prints one JSON line: the widths, the microseconds per product, and the
+knee (the largest width within 10% of the time at the smallest width).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+import torch
+
+from .tc import DeviceCsr, TiledMatrix
+
+WIDTHS = [1 << s for s in range(10, 24)]  # 1K .. 8M columns (4 KB .. 32 MB of x)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--graph", default="cl23")
+    ap.add_argument("--reps", type=int, default=10)
+    a = ap.parse_args(argv)
+    assert torch.cuda.is_available(), "runs on the GPU"
+    import graphgen as gg
+    if a.graph == "cl23":
+        csr = gg.pagerank_matrix(gg.chung_lu(23, 1 << 27, gamma=2.1, cap=float(1 << 20), seed=23))
+    else:
+        csr = gg.pagerank_matrix(gg.rmat(20, 16, seed=20))
+    n_rows, n_cols, rp, col, val = csr
+    A = DeviceCsr(csr)
+    col_d = A.col.clone()
+    res = []
+    for wm in [w for w in WIDTHS if w <= n_cols]:
+        A.col.copy_(torch.remainder(col_d, wm))
+        tm = TiledMatrix(A, tile_width=n_cols, n_tiles=1, relabel=0)
+        x = torch.rand(n_cols, device="cuda")
+        y = torch.empty(n_rows, device="cuda")
+        for _ in range(2):
+            tm.spmv_internal(x, y)
+        tm.set_timing(True)
+        for _ in range(a.reps):
+            tm.spmv_internal(x, y)
+        t = tm.get_timing()
+        tm.close()
+        res.append((wm, t["tile_kernel_ms"] * 1e3 / max(t["spmv_calls"], 1)))
+        print("width %8d (%8.1f KB of x): %8.1f us" % (wm, wm * 4 / 1024, res[-1][1]), file=sys.stderr, flush=True)
+    base = res[0][1]
+    knee = max(w for w, us in res if us <= 1.1 * base)
+    print(json.dumps({"graph": a.graph, "nnz": int(A.nnz), "widths": [w for w, _ in res],
+                      "us": [round(u, 1) for _, u in res], "knee_width": knee,
+                      "knee_kb": knee * 4 // 1024}), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
