@@ -251,13 +251,23 @@ tc_status tc_rwr_multi(tc_handle* const* handles, int32_t n_graphs, const int32_
 tc_status tc_csr_transpose(const tc_csr* A, int64_t* d_rpT, int32_t* d_colT, float* d_valT, int32_t* d_permT,
                            tc_stream_t stream);
 
-/* z, w (FP64, nnz), S (FP64, n_cols) and the FP32 values of W in A's order
- * (d_val) and in A^T's order (d_valT) for theta (host, nf <= 16).  d_col is
- * A's column array; d_rpT/d_permT come from tc_csr_transpose.  Synchronous. */
-tc_status tc_rwr_edge_weights(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT,
-                              const int32_t* d_permT, int32_t nf, const float* d_feats, const double* theta,
-                              double* d_z, double* d_w, double* d_S, float* d_val, float* d_valT,
-                              tc_stream_t stream);
+/* Row gather: row q of d_dst (n rows of `width` floats) is row d_idx[q] of
+ * d_src (n_src rows).  Puts the per-entry features of the learned weights
+ * into A^T's order (d_idx = d_permT of tc_csr_transpose).  Indices outside
+ * [0, n_src) give TC_EINVAL before anything is written.  Synchronous. */
+tc_status tc_gather_rows(const float* d_src, int64_t n_src, const int32_t* d_idx, int64_t n, int32_t width,
+                         float* d_dst, tc_stream_t stream);
+
+/* Learned edge weights (Appendix F, Eq. 9, with w = softplus(theta . f)):
+ * for theta (host, nf <= 16 doubles) computes z and w (FP64, nnz, in A^T's
+ * order), the column sums S (FP64, n_cols) and the FP32 values of W in A's
+ * order (d_val) and in A^T's order (d_valT), bit-identical entry by entry.
+ * d_feats holds nf floats per entry in A's order, d_featsT the same rows in
+ * A^T's order (tc_gather_rows); d_col is A's column array and d_rpT A^T's
+ * row pointers (tc_csr_transpose).  Synchronous. */
+tc_status tc_rwr_edge_weights(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT, int32_t nf,
+                              const float* d_feats, const float* d_featsT, const double* theta, double* d_zT,
+                              double* d_wT, double* d_S, float* d_val, float* d_valT, tc_stream_t stream);
 
 /* K RWR iterations on the handle of W from e_seed; d_rK receives r^K and
  * d_ckpt (ceil(K / every) x n) the checkpoints r^0, r^every, ...  Each step
@@ -266,19 +276,21 @@ tc_status tc_rwr_iterates(const tc_handle* W, int32_t seed, float c, int32_t K, 
                           float* d_rK, tc_stream_t stream);
 
 /* Adjoint pass from d_gK = dL/dr^K: recomputes the iterates between
- * checkpoints (every x n scratch), and returns d_G[e] = sum_k g^{k+1}_i r^k_j
- * (FP64, nnz, A's order; dL/dW = c G) and, if d_g0 is not NULL, g^0.  Wt is
- * the handle built from A^T with W's values (tc_csr_transpose + d_valT). */
-tc_status tc_rwr_adjoint(const tc_handle* W, const tc_handle* Wt, const int64_t* d_rp, const int32_t* d_col,
+ * checkpoints (every x n scratch), and returns, for every entry (i, j) of A in
+ * A^T's order, d_G = sum_k g^{k+1}_i r^k_j (FP64, nnz; dL/dW = c G) and, if
+ * d_g0 is not NULL, g^0.  Wt is the handle built from A^T with W's values
+ * (d_rpT, d_colT and d_valT); the sum of each entry runs latest step first,
+ * so the result does not depend on `every`. */
+tc_status tc_rwr_adjoint(const tc_handle* W, const tc_handle* Wt, const int64_t* d_rpT, const int32_t* d_colT,
                          int32_t seed, float c, int32_t K, int32_t every, const float* d_ckpt, const float* d_gK,
                          double* d_G, float* d_g0, tc_stream_t stream);
 
-/* dL/dtheta (host, nf doubles) from d_G of tc_rwr_adjoint and z, w, S of
- * tc_rwr_edge_weights.  Synchronous. */
-tc_status tc_rwr_theta_grad(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT,
-                            const int32_t* d_permT, int32_t nf, const float* d_feats, const double* d_z,
-                            const double* d_w, const double* d_S, const double* d_G, float c, double* dtheta,
-                            tc_stream_t stream);
+/* dL/dtheta (host, nf doubles) from d_G of tc_rwr_adjoint and the A^T-order
+ * d_featsT, z, w and S of tc_rwr_edge_weights: through the column
+ * normalisation and the softplus.  Synchronous. */
+tc_status tc_rwr_theta_grad(int64_t n_cols, int64_t nnz, const int64_t* d_rpT, int32_t nf, const float* d_featsT,
+                            const double* d_zT, const double* d_wT, const double* d_S, const double* d_G, float c,
+                            double* dtheta, tc_stream_t stream);
 
 /* Plain CSR SpMV (one thread per row, Appendix B's CSR kernel), the baseline
  * the tiled kernels are compared with: y := A x, caller's ids, no handle. */

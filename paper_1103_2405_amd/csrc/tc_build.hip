@@ -206,8 +206,10 @@ struct ColBucketOp {
   const int32_t* cin;
   int32_t* cout;
   int shift;
-  __device__ uint32_t bucket(int64_t k) const { return (uint32_t)cin[k] >> shift; }
-  __device__ void move(int64_t k, int64_t p) const { cout[p] = cin[k]; }
+  using Item = int32_t;
+  __device__ Item load(int64_t k) const { return cin[k]; }
+  __device__ uint32_t bucket_of(Item c) const { return (uint32_t)c >> shift; }
+  __device__ void store(int64_t p, Item c) const { cout[p] = c; }
 };
 
 struct CntTask {
@@ -536,7 +538,10 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
                                              const int32_t* __restrict__ first, int32_t* __restrict__ idx,
                                              float* __restrict__ val, int32_t* __restrict__ rowid) {
   // kPackSlices wavefronts per workload, slice sl taking every kPackSlices-th
-  // row (RM), row block of 64 (CM) or 64-entry block (chunk)
+  // row (RM), row block of 64 (CM) or 64-entry block (chunk).  Four positions'
+  // loads go out together, then their stores: a position past its row's L
+  // real entries reloads the row's last entry (entry 0 of the bucketed arrays
+  // for a row with none) and stores the pad.
   const int lane = lane_id();
   const int64_t w = (int64_t)blockIdx.x * (kB / kWave) + threadIdx.x / kWave;
   if (w >= n_wl * kPackSlices) return;
@@ -548,10 +553,24 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
     const int32_t s = d.row_begin;
     const int64_t st = (int64_t)srt_start[s] + d.chunk_off;
     const int64_t L = d.chunk_len;
-    for (int64_t c = lane + (int64_t)sl * kWave; c < d.w_pad; c += (int64_t)kWave * kPackSlices) {
-      const bool real = c < L;
-      idx[off + c] = real ? b_icol[st + c] : d.tile_first;
-      val[off + c] = real ? b_val[st + c] : 0.0f;
+    const int64_t step = (int64_t)kWave * kPackSlices;
+    for (int64_t c0 = lane + (int64_t)sl * kWave; c0 < d.w_pad; c0 += 4 * step) {
+      int32_t ti[4];
+      float tv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t q = L > 0 ? st + min(c0 + u * step, L - 1) : 0;
+        ti[u] = b_icol[q];
+        tv[u] = b_val[q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t c = c0 + u * step;
+        if (c < d.w_pad) {
+          idx[off + c] = c < L ? ti[u] : d.tile_first;
+          val[off + c] = c < L ? tv[u] : 0.0f;
+        }
+      }
     }
     if (lane == 0 && sl == 0) rowid[d.rowid_off] = rows_sorted[s];
   } else if (d.layout == kRM) {
@@ -560,10 +579,23 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
       const int64_t st = srt_start[s];
       const int32_t L = rows_len[s];
       const int64_t base = off + (int64_t)r * d.w_pad;
-      for (int64_t c = lane; c < d.w_pad; c += kWave) {
-        const bool real = c < L;
-        idx[base + c] = real ? b_icol[st + c] : d.tile_first;
-        val[base + c] = real ? b_val[st + c] : 0.0f;
+      for (int64_t c0 = lane; c0 < d.w_pad; c0 += 4 * kWave) {
+        int32_t ti[4];
+        float tv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t q = L > 0 ? st + min<int64_t>(c0 + u * kWave, L - 1) : 0;
+          ti[u] = b_icol[q];
+          tv[u] = b_val[q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t c = c0 + u * kWave;
+          if (c < d.w_pad) {
+            idx[base + c] = c < L ? ti[u] : d.tile_first;
+            val[base + c] = c < L ? tv[u] : 0.0f;
+          }
+        }
       }
       if (lane == 0) {
         const int32_t row = rows_sorted[s];
@@ -581,11 +613,24 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
         row = rows_sorted[s];
       }
       rowid[d.rowid_off + r] = row < 0 ? row : (row | (first[row] == d.tile ? 0 : kAddFlag));
-      for (int32_t c = 0; c < d.w_pad; ++c) {
-        const int64_t e = off + (int64_t)c * d.h_pad + r;
-        const bool real = c < L;
-        idx[e] = real ? b_icol[st + c] : d.tile_first;
-        val[e] = real ? b_val[st + c] : 0.0f;
+      for (int32_t c0 = 0; c0 < d.w_pad; c0 += 4) {
+        int32_t ti[4];
+        float tv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t q = L > 0 ? st + min(c0 + u, L - 1) : 0;
+          ti[u] = b_icol[q];
+          tv[u] = b_val[q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t c = c0 + u;
+          if (c < d.w_pad) {
+            const int64_t e = off + (int64_t)c * d.h_pad + r;
+            idx[e] = c < L ? ti[u] : d.tile_first;
+            val[e] = c < L ? tv[u] : 0.0f;
+          }
+        }
       }
     }
   }
@@ -598,30 +643,34 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
 }
 
 // ------------------------------------------------------ counting-sort ops
-struct RadixU32Op {
-  const uint32_t* kin;
-  const int32_t* vin;
-  uint32_t* kout;
-  int32_t* vout;
-  int shift;
-  __device__ uint32_t bucket(int64_t k) const { return (kin[k] >> shift) & 255u; }
-  __device__ void move(int64_t k, int64_t p) const {
-    kout[p] = kin[k];
-    vout[p] = vin[k];
-  }
+template <typename K>
+struct KeyVal {
+  K key;
+  int32_t v;
 };
 
-struct RadixU64Op {
-  const uint64_t* kin;
+template <typename K>
+struct RadixOp {
+  const K* kin;
   const int32_t* vin;
-  uint64_t* kout;
+  K* kout;
   int32_t* vout;
   int shift;
-  __device__ uint32_t bucket(int64_t k) const { return (uint32_t)(kin[k] >> shift) & 255u; }
-  __device__ void move(int64_t k, int64_t p) const {
-    kout[p] = kin[k];
-    vout[p] = vin[k];
+  using Item = KeyVal<K>;
+  __device__ Item load(int64_t k) const { return {kin[k], vin[k]}; }
+  __device__ uint32_t bucket_of(const Item& it) const { return (uint32_t)(it.key >> shift) & 255u; }
+  __device__ void store(int64_t p, const Item& it) const {
+    kout[p] = it.key;
+    vout[p] = it.v;
   }
+};
+using RadixU32Op = RadixOp<uint32_t>;
+using RadixU64Op = RadixOp<uint64_t>;
+
+struct TileItem {
+  int32_t icol;
+  float val;
+  int32_t row;
 };
 
 struct TileOp {
@@ -633,11 +682,13 @@ struct TileOp {
   int32_t* row_out;
   TileMap tm;
   int shift;
-  __device__ uint32_t bucket(int64_t k) const { return ((uint32_t)tm(icol_in[k]) >> shift) & 255u; }
-  __device__ void move(int64_t k, int64_t p) const {
-    icol_out[p] = icol_in[k];
-    val_out[p] = val_in[k];
-    row_out[p] = row_in[k];
+  using Item = TileItem;
+  __device__ Item load(int64_t k) const { return {icol_in[k], val_in[k], row_in[k]}; }
+  __device__ uint32_t bucket_of(const Item& it) const { return ((uint32_t)tm(it.icol) >> shift) & 255u; }
+  __device__ void store(int64_t p, const Item& it) const {
+    icol_out[p] = it.icol;
+    val_out[p] = it.val;
+    row_out[p] = it.row;
   }
 };
 

@@ -53,8 +53,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const In* __restrict
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
   int64_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanPer; ++i)
-    if (base + i < n) s += (int64_t)in[base + i];
+  for (int i = 0; i < kScanPer; ++i) {  // all loads issued together (past n: in[n - 1], not added)
+    const In t = in[min(base + i, n - 1)];
+    s += base + i < n ? (int64_t)t : 0;
+  }
   int64_t tot;
   block_excl_scan<int64_t>(s, &tot);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
@@ -88,7 +90,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_down(const In* __restrict__
   int64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    v[i] = (base + i < n) ? in[base + i] : (In)0;
+    const In t = in[min(base + i, n - 1)];
+    v[i] = base + i < n ? t : (In)0;
     s += (int64_t)v[i];
   }
   int64_t tot;
@@ -108,8 +111,13 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_down(const In* __restrict__
 // ranks equal buckets inside the step by lane order (ballots over the bucket's
 // bits), so equal keys keep their input order.
 //
-// Op provides:  __device__ uint32_t bucket(int64_t k) const;
-//               __device__ void move(int64_t k, int64_t pos) const;
+// Op provides:  struct Item;                                   (one element)
+//               __device__ Item load(int64_t k) const;
+//               __device__ uint32_t bucket_of(const Item&) const;
+//               __device__ void store(int64_t pos, const Item&) const;
+// Every lane loads (a lane past the chunk's end reloads the chunk's first
+// element) and only the stores are per lane: a load under a per-lane branch
+// would wait for its data inside the branch, one element at a time.
 constexpr int kCsBlock = 256;
 constexpr int kCsWaves = kCsBlock / kWave;
 
@@ -126,14 +134,14 @@ __global__ void __launch_bounds__(kCsBlock) k_cs_hist(Op op, int64_t n, int32_t 
     const int64_t end = min(n, (c + 1) * chunk);
     int64_t k = c * chunk + lane;
     for (; k + 3 * kWave < end; k += 4 * kWave) {  // four loads in flight
-      const uint32_t b0 = op.bucket(k), b1 = op.bucket(k + kWave), b2 = op.bucket(k + 2 * kWave),
-                     b3 = op.bucket(k + 3 * kWave);
+      const uint32_t b0 = op.bucket_of(op.load(k)), b1 = op.bucket_of(op.load(k + kWave)),
+                     b2 = op.bucket_of(op.load(k + 2 * kWave)), b3 = op.bucket_of(op.load(k + 3 * kWave));
       atomicAdd(&cnt[b0], 1);
       atomicAdd(&cnt[b1], 1);
       atomicAdd(&cnt[b2], 1);
       atomicAdd(&cnt[b3], 1);
     }
-    for (; k < end; k += kWave) atomicAdd(&cnt[op.bucket(k)], 1);
+    for (; k < end; k += kWave) atomicAdd(&cnt[op.bucket_of(op.load(k))], 1);
   }
   __syncthreads();
   if (c < nchunks)
@@ -152,20 +160,20 @@ __global__ void __launch_bounds__(kCsBlock) k_cs_scatter(Op op, int64_t n, int32
   for (int i = lane; i < nbuckets; i += kWave) run[i] = offs[(int64_t)i * nchunks + c];
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  const int64_t end = min(n, (c + 1) * chunk);
+  const int64_t first = c * chunk, end = min(n, (c + 1) * chunk);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t base0 = c * chunk; base0 < end; base0 += 4 * kWave) {
-    uint32_t bs[4];
+  for (int64_t base0 = first; base0 < end; base0 += 4 * kWave) {
+    typename Op::Item it[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {  // four loads in flight, then the steps in order
       const int64_t k = base0 + u * kWave + lane;
-      bs[u] = k < end ? op.bucket(k) : 0u;
+      it[u] = op.load(k < end ? k : first);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t k = base0 + u * kWave + lane;
       const bool valid = k < end;
-      const uint32_t b = bs[u];
+      const uint32_t b = op.bucket_of(it[u]);
       uint64_t peers = __ballot(valid);
       for (int bit = 0; bit < nbits; ++bit) {
         const bool set = (b >> bit) & 1u;
@@ -175,7 +183,7 @@ __global__ void __launch_bounds__(kCsBlock) k_cs_scatter(Op op, int64_t n, int32
       const int64_t pos = valid ? run[b] + (int64_t)__popcll(peers & lt) : 0;
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (valid) op.move(k, pos);
+      if (valid) op.store(pos, it[u]);
       if (valid && (peers >> lane) == 1ull) run[b] += (int64_t)__popcll(peers);
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "tc_internal.h"
 
@@ -160,7 +161,11 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
 }
 
 // Column-major rectangle: lane owns rows r = 64 u + lane; U row blocks and C
-// columns are in flight together (U * C independent gathers per lane).
+// columns are in flight together (U * C independent gathers per lane).  Every
+// load runs on every lane: a lane past the last row reads the workload's first
+// entry and takes index 0 and value 0 instead (its sum is never stored).  A
+// load under a per-lane branch would end its branch with a wait for it, so
+// the loads would go out one at a time.
 template <int U, int C, class G>
 __device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict__ idx,
                                const float* __restrict__ val, const int32_t* __restrict__ rowid,
@@ -178,29 +183,41 @@ __device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict_
     int32_t c = 0;
     for (; c + C <= w; c += C) {
       int32_t ii[U][C];
-      float vv[U][C];
+      float vv[U][C], xv[U][C];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int k = 0; k < C; ++k)
-          if (ok[u]) {
-            const int64_t e = off + (int64_t)(c + k) * hp + r0 + u * kWave + lane;
-            ii[u][k] = ld_nt(idx + e);
-            vv[u][k] = ld_nt(val + e);
-          }
+        for (int k = 0; k < C; ++k) {
+          const int64_t e = ok[u] ? off + (int64_t)(c + k) * hp + r0 + u * kWave + lane : off;
+          const int32_t ti = ld_nt(idx + e);
+          const float tv = ld_nt(val + e);
+          ii[u][k] = ok[u] ? ti : 0;
+          vv[u][k] = ok[u] ? tv : 0.0f;
+        }
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int k = 0; k < C; ++k)
-          if (ok[u]) acc[u] = fma((double)vv[u][k], (double)x(ii[u][k]), acc[u]);
+        for (int k = 0; k < C; ++k) xv[u][k] = x(ii[u][k]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc[u] = fma((double)vv[u][k], (double)xv[u][k], acc[u]);
     }
     for (; c < w; ++c) {
+      int32_t ii[U];
+      float vv[U], xv[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ok[u]) {
-          const int64_t e = off + (int64_t)c * hp + r0 + u * kWave + lane;
-          acc[u] = fma((double)ld_nt(val + e), (double)x(ld_nt(idx + e)), acc[u]);
-        }
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = ok[u] ? off + (int64_t)c * hp + r0 + u * kWave + lane : off;
+        const int32_t ti = ld_nt(idx + e);
+        const float tv = ld_nt(val + e);
+        ii[u] = ok[u] ? ti : 0;
+        vv[u] = ok[u] ? tv : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[u] = x(ii[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[u] = fma((double)vv[u], (double)xv[u], acc[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -291,7 +308,7 @@ struct PrivX {
 };
 
 template <class G>
-__device__ inline void run_workload(const Wl& d, int lane, const int32_t* __restrict__ idx,
+__device__ __attribute__((always_inline)) inline void run_workload(const Wl& d, int lane, const int32_t* __restrict__ idx,
                                     const float* __restrict__ val, const int32_t* __restrict__ rowid, const G& x,
                                     float* __restrict__ y, double* __restrict__ partial) {
   const int layout = d.info & 3;
@@ -412,20 +429,22 @@ struct Vec {
   }
 };
 
+// Branch-free: an inactive lane (pad entry, or right-hand sides past k) reads
+// X[0 .. V) and takes zeros.  A load under a branch would end its branch with
+// a wait for that load (the conversions to double sink into it), so a step's
+// gathers would go out one at a time instead of all together.
 template <int V>
 __device__ inline void load_x(const float* __restrict__ X, int64_t row, int32_t k, int32_t col, bool act, float* xv) {
+  const int64_t o = act ? row * k + col : 0;
   if constexpr (V == 4) {
-    if (act) {
-      const float4 t = *(const float4*)(X + row * k + col);
-      xv[0] = t.x;
-      xv[1] = t.y;
-      xv[2] = t.z;
-      xv[3] = t.w;
-    } else {
-      xv[0] = xv[1] = xv[2] = xv[3] = 0.0f;
-    }
+    const float4 t = *(const float4*)(X + o);
+    xv[0] = act ? t.x : 0.0f;
+    xv[1] = act ? t.y : 0.0f;
+    xv[2] = act ? t.z : 0.0f;
+    xv[3] = act ? t.w : 0.0f;
   } else {
-    xv[0] = act ? X[row * k + col] : 0.0f;
+    const float t = X[o];
+    xv[0] = act ? t : 0.0f;
   }
 }
 
@@ -515,7 +534,7 @@ __device__ inline Vec<V> rm_range(const int32_t* __restrict__ idx, const float* 
 // shows up here: it is then done whole, as one piece).
 // SUB: rows summed per lane group in one column step (accumulators per lane).
 // `slices` wavefronts share a workload, slice s taking every slices-th step.
-template <int V, int SUB, int CU = 1>
+template <int V, int SUB>
 __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int64_t n_wl, int32_t slices,
                                                   const int32_t* __restrict__ idx,
                                                   const float* __restrict__ val, const int32_t* __restrict__ rowid,
@@ -543,29 +562,20 @@ __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int
       Vec<V> a[SUB];
 #pragma unroll
       for (int u = 0; u < SUB; ++u) a[u].zero();
-      int32_t c = 0;
-      if constexpr (CU == 2) {
-        // two columns per step: twice the X rows in flight, same accumulators
-        for (; c + 1 < d.w_pad; c += 2) {
-          const int64_t e = off + (int64_t)c * hp + r0 + lane;
-          const float vl0 = okl ? ld_nt(val + e) : 0.0f, vl1 = okl ? ld_nt(val + e + hp) : 0.0f;
-          const int32_t il0 = okl ? ld_nt(idx + e) : 0, il1 = okl ? ld_nt(idx + e + hp) : 0;
-          float v0[SUB], xv0[SUB][V], v1[SUB], xv1[SUB][V];
-          step_gather<V, SUB>(vl0, il0, subs, groups, g, X, k, col, act, v0, xv0);
-          step_gather<V, SUB>(vl1, il1, subs, groups, g, X, k, col, act, v1, xv1);
-#pragma unroll
-          for (int u = 0; u < SUB; ++u) {
-            if (v0[u] != 0.0f) fma_vec<V>(a[u], v0[u], xv0[u]);
-            if (v1[u] != 0.0f) fma_vec<V>(a[u], v1[u], xv1[u]);
-          }
-        }
-      }
-      for (; c < d.w_pad; ++c) {
-        const int64_t e = off + (int64_t)c * hp + r0 + lane;
-        const float vl = okl ? ld_nt(val + e) : 0.0f;
-        const int32_t il = okl ? ld_nt(idx + e) : 0;
+      // column c + 1's entries are loaded while column c's X rows are in
+      // flight (a lane past the rows reads the workload's first entry)
+      const int64_t eb = okl ? off + r0 + lane : off;
+      const int64_t es = okl ? hp : 0;
+      float nv = ld_nt(val + eb);
+      int32_t ni = ld_nt(idx + eb);
+      for (int32_t c = 0; c < d.w_pad; ++c) {
+        const float vl = okl ? nv : 0.0f;
+        const int32_t il = okl ? ni : 0;
         float v[SUB], xv[SUB][V];
         step_gather<V, SUB>(vl, il, subs, groups, g, X, k, col, act, v, xv);
+        const int64_t en = eb + (c + 1 < d.w_pad ? (int64_t)(c + 1) * es : 0);
+        nv = ld_nt(val + en);
+        ni = ld_nt(idx + en);
 #pragma unroll
         for (int u = 0; u < SUB; ++u)
           if (v[u] != 0.0f) fma_vec<V>(a[u], v[u], xv[u]);
@@ -991,14 +1001,32 @@ __device__ inline int last_le(int n, int64_t j, K key) {
   return lo;
 }
 
+// MultiSeg as the kernel reads it: the same layout with every pointer typed
+// as device global memory.  A plain pointer read from memory is generic to the
+// compiler, and every access through it would be a flat (not global) access.
+#define TC_GLOBAL __attribute__((address_space(1)))
+struct MultiSegG {
+  const Wl* wl;  // one record per wavefront: left generic
+  int64_t begin;
+  const TC_GLOBAL int32_t* idx;
+  const TC_GLOBAL float* val;
+  const TC_GLOBAL int32_t* rowid;
+  const TC_GLOBAL float* x;
+  TC_GLOBAL float* y;
+  TC_GLOBAL double* partial;
+};
+#undef TC_GLOBAL
+static_assert(sizeof(MultiSegG) == sizeof(MultiSeg), "MultiSegG mirrors MultiSeg");
+
 __global__ void __launch_bounds__(kB) k_tile_spmv_multi(const MultiSeg* __restrict__ segs, int32_t n_segs,
                                                         int64_t total) {
   const int lane = lane_id();
   const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (j >= total) return;
   const int i = __builtin_amdgcn_readfirstlane(last_le(n_segs, j, [&](int m) { return segs[m].begin; }));
-  const MultiSeg s = segs[i];
-  run_workload(s.wl[j - s.begin], lane, s.idx, s.val, s.rowid, GlobalX<false>{s.x}, s.y, s.partial);
+  const MultiSegG s = ((const MultiSegG*)segs)[i];
+  run_workload(s.wl[j - s.begin], lane, (const int32_t*)s.idx, (const float*)s.val, (const int32_t*)s.rowid,
+               GlobalX<false>{(const float*)s.x}, (float*)s.y, (double*)s.partial);
 }
 
 // Per-graph element ranges: [begin, begin + n) of the launch's index space.
@@ -1089,61 +1117,114 @@ __global__ void k_map_ids_multi(const int32_t* const* __restrict__ maps, const i
 // ---- differentiable RWR: learned edge weights (Appendix F, Eq. 9)
 //
 // z_e = theta . f_e, w_e = softplus(z_e), W_e = w_e / S_j with S_j the sum of
-// w over column j.  Column quantities run one wavefront per column over the
-// CSR of the transpose (rows of A^T = columns of A; permT maps its entries
-// back to A's), so every sum has a fixed order.
+// w over column j.  The per-entry arrays of the gradient (features, z, w, G)
+// are kept in the order of A^T's CSR (the columns of A, each by increasing
+// row), so every column quantity is a contiguous segmented pass; the values
+// of W in A's own order are computed from A's copy of the features.
 __device__ inline double softplus_d(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
 
-__global__ void k_edge_softplus(const float* __restrict__ feats, int64_t nnz, int32_t nf,
-                                const double* __restrict__ theta, double* __restrict__ z, double* __restrict__ w) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
+// w of one entry; the same arithmetic in both orders, so W and W^T get
+// bit-identical values
+__device__ inline double edge_w(const float* __restrict__ f, const double* __restrict__ theta, int32_t nf,
+                                double* z_out) {
   double a = 0.0;
-  for (int32_t d = 0; d < nf; ++d) a = fma((double)feats[e * nf + d], theta[d], a);
-  z[e] = a;
-  w[e] = softplus_d(a);
+  for (int32_t d = 0; d < nf; ++d) a = fma((double)f[d], theta[d], a);
+  if (z_out) *z_out = a;
+  return softplus_d(a);
 }
 
-// S_j = sum over column j of w (wave per column), and the FP32 values of the
-// transpose's entries, W^T[j][i] = fl32(w_e / S_j)
-__global__ void __launch_bounds__(kB) k_col_norm(const int64_t* __restrict__ rpT, const int32_t* __restrict__ permT,
-                                                 int64_t n_cols, const double* __restrict__ w,
-                                                 double* __restrict__ S, float* __restrict__ valT) {
-  const int lane = lane_id();
-  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  if (j >= n_cols) return;
-  const int64_t a = rpT[j], b = rpT[j + 1];
-  double s = 0.0;
-  for (int64_t q0 = a; q0 < b; q0 += 8 * kWave) {  // eight gathers in flight (hub columns are long)
-    int32_t ee[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t q = q0 + u * kWave + lane;
-      ee[u] = q < b ? permT[q] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (ee[u] >= 0) s += w[ee[u]];
-  }
-  s = wave_sum(s);
-  if (lane == 0) S[j] = s;
-  for (int64_t q0 = a; q0 < b; q0 += 8 * kWave) {
-    int32_t ee[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t q = q0 + u * kWave + lane;
-      ee[u] = q < b ? permT[q] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (ee[u] >= 0) valT[q0 + u * kWave + lane] = (float)(w[ee[u]] / s);
-  }
+__global__ void k_edge_softplus(const float* __restrict__ featsT, int64_t nnz, int32_t nf,
+                                const double* __restrict__ theta, double* __restrict__ zT, double* __restrict__ wT) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  double z;
+  wT[q] = edge_w(featsT + q * nf, theta, nf, &z);
+  zT[q] = z;
 }
 
-__global__ void k_edge_values(const int32_t* __restrict__ col, int64_t nnz, const double* __restrict__ w,
-                              const double* __restrict__ S, float* __restrict__ val) {
+// W in A's order: val_e = fl32(w_e / S_col(e))
+__global__ void k_edge_values(const float* __restrict__ feats, const int32_t* __restrict__ col, int64_t nnz,
+                              int32_t nf, const double* __restrict__ theta, const double* __restrict__ S,
+                              float* __restrict__ val) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nnz) val[e] = (float)(w[e] / S[col[e]]);
+  if (e < nnz) val[e] = (float)(edge_w(feats + e * nf, theta, nf, nullptr) / S[col[e]]);
+}
+
+// Column sums over A^T's CSR: one wavefront per kColLanes-column group, a
+// group of kColLanes lanes per column, and a column of more than kColLong
+// entries by the whole wavefront (with more loads in flight).  Every lane
+// loads (a lane past the column's end at the column's first entry) and adds
+// only its own entries.  The per-entry passes that need a column's sum are
+// flat passes over the entries (the column of entry q: rowT[q]).
+constexpr int kColLanes = 8;
+constexpr int kColLong = 512;
+constexpr int kGradBlocks = 1024;
+constexpr int kMaxFeat = 16;
+
+// sum over each aligned group of kColLanes lanes (every lane gets the same bits)
+__device__ inline double group_sum8(double v) {
+  v += __shfl_xor(v, 1, kWave);
+  v += __shfl_xor(v, 2, kWave);
+  v += __shfl_xor(v, 4, kWave);
+  return v;
+}
+
+// this lane's part of the sum over q in [a, b) of f(q): LANES lanes from
+// offset gl, U loads in flight
+template <int LANES, int U, class F>
+__device__ inline double seg_part(int64_t a, int64_t b, int gl, F f) {
+  double s = 0.0;
+  for (int64_t q0 = a + gl; q0 < b; q0 += U * LANES) {
+    double t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t q = q0 + u * LANES;
+      t[u] = f(q < b ? q : a);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += q0 + u * LANES < b ? t[u] : 0.0;
+  }
+  return s;
+}
+
+// out[j] = post(j, sum over column j's entries q of f(q))
+template <class F, class P>
+__device__ inline void col_sums(const int64_t* __restrict__ rpT, int64_t n_cols, F f, P post,
+                                double* __restrict__ out) {
+  const int lane = lane_id(), gl = lane % kColLanes;
+  const int64_t cg = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t j0 = cg * (kWave / kColLanes);
+  if (j0 >= n_cols) return;
+  const int64_t j = j0 + lane / kColLanes;
+  int64_t a = 0, b = 0;
+  if (j < n_cols) {
+    a = rpT[j];
+    b = rpT[j + 1];
+  }
+  const bool lng = b - a > kColLong;
+  const double s = group_sum8(lng || j >= n_cols ? 0.0 : seg_part<kColLanes, 4>(a, b, gl, f));
+  if (!lng && j < n_cols && gl == 0) out[j] = post(j, s);
+  for (uint64_t m = __ballot(lng && gl == 0); m; m &= m - 1) {
+    const int src = __ffsll((unsigned long long)m) - 1;
+    const int64_t jj = j0 + src / kColLanes;
+    const int64_t aa = __shfl(a, src, kWave), bb = __shfl(b, src, kWave);
+    const double t = wave_sum(seg_part<kWave, 16>(aa, bb, lane, f));
+    if (lane == 0) out[jj] = post(jj, t);
+  }
+}
+
+// S_j = sum of w over column j
+__global__ void __launch_bounds__(kB) k_col_norm(const int64_t* __restrict__ rpT, int64_t n_cols,
+                                                 const double* __restrict__ wT, double* __restrict__ S) {
+  col_sums(
+      rpT, n_cols, [&](int64_t q) { return wT[q]; }, [](int64_t, double s) { return s; }, S);
+}
+
+// W^T's values fl32(w / S_j)
+__global__ void k_values_T(const int32_t* __restrict__ rowT, int64_t nnz, const double* __restrict__ wT,
+                           const double* __restrict__ S, float* __restrict__ valT) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nnz) valT[q] = (float)(wT[q] / S[rowT[q]]);
 }
 
 // r_next = fl32(c y + (1 - c) [i == seed]) (the same rounding as k_rwr_update)
@@ -1157,18 +1238,29 @@ __global__ void k_scale(const float* __restrict__ y, float* __restrict__ g, int6
   if (i < n) g[i] = (float)(c * (double)y[i]);
 }
 
-// G_e += sum over the steps of one checkpoint segment, latest step first, of
-// g^{k+1}_{row(e)} r^k_{col(e)}: gs holds g^{k+1} and rs holds r^k for
-// k = k0 + m - 1 down to k0 (step t at offset t * n)
-__global__ void k_edge_accum_seg(const int32_t* __restrict__ row_of, const int32_t* __restrict__ col, int64_t nnz,
-                                 const float* __restrict__ gs, const float* __restrict__ rs, int32_t m, int64_t n,
+// G_q += sum over the steps of one checkpoint segment, latest step first, of
+// g^{k+1}_i r^k_j for the entry q = (i, j) of A (row j of A^T, column i of
+// A^T: gidx = A^T's column array, ridx = A^T's row of every entry).  gi and ri
+// hold g^{k+1} and r^k of the segment's m steps k = k0 + t interleaved by node
+// (node i's m values at i * m), so an entry reads its values from one or two
+// cache lines.
+__global__ void k_edge_accum_seg(const int32_t* __restrict__ gidx, const int32_t* __restrict__ ridx, int64_t nnz,
+                                 const float* __restrict__ gi, const float* __restrict__ ri, int32_t m,
                                  double* __restrict__ G) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  const int32_t i = row_of[e], j = col[e];
-  double acc = G[e];
-  for (int32_t t = m - 1; t >= 0; --t) acc = fma((double)gs[(int64_t)t * n + i], (double)rs[(int64_t)t * n + j], acc);
-  G[e] = acc;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  const float* gp = gi + (int64_t)gidx[q] * m;
+  const float* rp = ri + (int64_t)ridx[q] * m;
+  double acc = G[q];
+  for (int32_t t = m - 1; t >= 0; --t) acc = fma((double)gp[t], (double)rp[t], acc);
+  G[q] = acc;
+}
+
+// dst[i * m + t] = src[t * n + i]: m vectors of n, interleaved by index
+__global__ void k_interleave(const float* __restrict__ src, int32_t m, int64_t n, float* __restrict__ dst) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n * m) return;
+  dst[x] = src[(x % m) * n + x / m];
 }
 
 
@@ -1200,52 +1292,33 @@ __global__ void k_onehot(float* __restrict__ r, int64_t n, int32_t seed) {
   if (i < n) r[i] = i == seed ? 1.0f : 0.0f;
 }
 
-// per column j: cs_j = sum over its entries of dL/dW_e W_e, with dL/dW = c G
-// and W_e = w_e / S_j (wave per column, over the transpose)
-__global__ void __launch_bounds__(kB) k_col_dot(const int64_t* __restrict__ rpT, const int32_t* __restrict__ permT,
-                                                int64_t n_cols, const double* __restrict__ G,
-                                                const double* __restrict__ w, const double* __restrict__ S,
-                                                double c, double* __restrict__ cs) {
-  const int lane = lane_id();
-  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  if (j >= n_cols) return;
-  const int64_t a = rpT[j], b = rpT[j + 1];
-  const double sj = S[j];
-  double s = 0.0;
-  for (int64_t q0 = a; q0 < b; q0 += 8 * kWave) {
-    int32_t ee[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t q = q0 + u * kWave + lane;
-      ee[u] = q < b ? permT[q] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (ee[u] >= 0) s += (c * G[ee[u]]) * (w[ee[u]] / sj);
-  }
-  s = wave_sum(s);
-  if (lane == 0) cs[j] = s;
+// per column j: cs_j = sum over its entries of dL/dW W, with dL/dW = c G and
+// W = w / S_j, taken as (c / S_j) sum G w
+__global__ void __launch_bounds__(kB) k_col_dot(const int64_t* __restrict__ rpT, int64_t n_cols,
+                                                const double* __restrict__ GT, const double* __restrict__ wT,
+                                                const double* __restrict__ S, double c, double* __restrict__ cs) {
+  col_sums(
+      rpT, n_cols, [&](int64_t q) { return GT[q] * wT[q]; }, [&](int64_t j, double s) { return c / S[j] * s; },
+      cs);
 }
 
-// dL/dz_e = (dL/dW_e - cs_j) / S_j * sigmoid(z_e); per-block partial sums of
-// dL/dz_e f_e (nf of them), combined afterwards in block order
-constexpr int kGradBlocks = 1024;
-constexpr int kMaxFeat = 16;
-__global__ void __launch_bounds__(kB) k_theta_grad(const int32_t* __restrict__ col, int64_t nnz, int32_t nf,
-                                                   const float* __restrict__ feats, const double* __restrict__ z,
-                                                   const double* __restrict__ S, const double* __restrict__ G,
+// dL/dz = (c G - cs_j) / S_j * sigmoid(z) per entry (column j = rowT[q]);
+// per-block partial sums of dL/dz f (nf of them), combined afterwards in
+// block order
+__global__ void __launch_bounds__(kB) k_theta_grad(const int32_t* __restrict__ rowT, int64_t nnz, int32_t nf,
+                                                   const float* __restrict__ featsT, const double* __restrict__ zT,
+                                                   const double* __restrict__ S, const double* __restrict__ GT,
                                                    const double* __restrict__ cs, double c,
                                                    double* __restrict__ parts) {
   double acc[kMaxFeat];
 #pragma unroll
   for (int d = 0; d < kMaxFeat; ++d) acc[d] = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * kB + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kB) {
-    const int32_t j = col[e];
-    const double dw = (c * G[e] - cs[j]) / S[j];
-    const double dz = dw / (1.0 + exp(-z[e]));
+  for (int64_t q = (int64_t)blockIdx.x * kB + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * kB) {
+    const int32_t j = rowT[q];
+    const double dz = (c * GT[q] - cs[j]) / S[j] / (1.0 + exp(-zT[q]));
 #pragma unroll
     for (int d = 0; d < kMaxFeat; ++d)
-      if (d < nf) acc[d] = fma(dz, (double)feats[e * nf + d], acc[d]);
+      if (d < nf) acc[d] = fma(dz, (double)featsT[q * nf + d], acc[d]);
   }
   __shared__ double sm[kMaxFeat][kB / kWave];
   const int lane = lane_id(), wv = threadIdx.x / kWave;
@@ -1451,9 +1524,9 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
   const int32_t pieces = h->mm_pieces;
   const int kchunks = (kq + kWave - 1) / kWave;
   // 4-wide lanes: four rows per sub-step group (fewer registers, more
-  // wavefronts resident), two columns per step, and each workload cut into
-  // four row slices (measured on a 31M-entry power-law matrix: 17% over one
-  // slice of eight rows and one column)
+  // wavefronts resident) and each workload cut into four row slices
+  // (measured on a 31M-entry power-law matrix at k = 32: 25% over one slice,
+  // and within 2% of two columns per step or eight rows per group)
   const int32_t slices = v4 ? 4 : 1;
   double* partial = nullptr;
   if (h->n_slots > 0) {
@@ -1481,7 +1554,7 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
                   st, (const Wl*)(h->d_wl + b), lead, pieces, (const int32_t*)h->d_idx, (const float*)h->d_val, X, k,
                   kg, partial);
     if (e > b + lead)
-      launch_tile(h, v4 ? k_tile_spmm<4, 4, 2> : k_tile_spmm<1, 8, 1>, dim3(nblk((e - b - lead) * slices, kWpb), kchunks),
+      launch_tile(h, v4 ? k_tile_spmm<4, 4> : k_tile_spmm<1, 8>, dim3(nblk((e - b - lead) * slices, kWpb), kchunks),
                   dim3(kB), 0, st, (const Wl*)(h->d_wl + b + lead), (int64_t)(e - b - lead), slices,
                   (const int32_t*)h->d_idx,
                   (const float*)h->d_val, (const int32_t*)h->d_rowid, X, Y, k, kg, partial);
@@ -2018,30 +2091,38 @@ int32_t n_checkpoints(int32_t K, int32_t every) { return K <= 0 ? 0 : (K + every
 }  // namespace tc
 
 extern "C" tc_status tc_rwr_edge_weights(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT,
-                                         const int32_t* d_permT, int32_t nf, const float* d_feats,
-                                         const double* theta, double* d_z, double* d_w, double* d_S, float* d_val,
-                                         float* d_valT, tc_stream_t stream) {
+                                         int32_t nf, const float* d_feats, const float* d_featsT, const double* theta,
+                                         double* d_zT, double* d_wT, double* d_S, float* d_val, float* d_valT,
+                                         tc_stream_t stream) {
   return guarded("tc_rwr_edge_weights", [&]() -> tc_status {
     if (n_cols < 0 || nnz < 0 || nf < 1 || nf > kMaxFeat) throw Err{TC_EINVAL, "need sizes >= 0 and 1 <= nf <= 16"};
-    if (!theta || !d_rpT || !d_S || (nnz > 0 && (!d_col || !d_permT || !d_feats || !d_z || !d_w || !d_val || !d_valT)))
+    if (!theta || !d_rpT || !d_S ||
+        (nnz > 0 && (!d_col || !d_feats || !d_featsT || !d_zT || !d_wT || !d_val || !d_valT)))
       throw Err{TC_EINVAL, "NULL argument"};
     hipStream_t st = (hipStream_t)stream;
     PoolBuf th(sizeof(double) * nf, st);
     HIPC(hipMemcpyAsync(th.p, theta, sizeof(double) * nf, hipMemcpyHostToDevice, st));
     if (nnz > 0) {
-      hipLaunchKernelGGL(k_edge_softplus, dim3(nblk(nnz, kB)), dim3(kB), 0, st, d_feats, nnz, nf,
-                         th.as<const double>(), d_z, d_w);
+      hipLaunchKernelGGL(k_edge_softplus, dim3(nblk(nnz, kB)), dim3(kB), 0, st, d_featsT, nnz, nf,
+                         th.as<const double>(), d_zT, d_wT);
       HIPC(hipGetLastError());
     }
     if (n_cols > 0) {
-      hipLaunchKernelGGL(k_col_norm, dim3(nblk(n_cols, kWpb)), dim3(kB), 0, st, d_rpT, d_permT, n_cols,
-                         (const double*)d_w, d_S, d_valT);
+      hipLaunchKernelGGL(k_col_norm, dim3(nblk(nblk(n_cols, kWave / kColLanes), kWpb)), dim3(kB), 0, st, d_rpT,
+                         n_cols, (const double*)d_wT, d_S);
       HIPC(hipGetLastError());
     }
     if (nnz > 0) {
-      hipLaunchKernelGGL(k_edge_values, dim3(nblk(nnz, kB)), dim3(kB), 0, st, d_col, nnz, (const double*)d_w,
-                         (const double*)d_S, d_val);
+      PoolBuf rowT(sizeof(int32_t) * (size_t)nnz, st);
+      hipLaunchKernelGGL(k_rows_of, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, d_rpT, n_cols, rowT.as<int32_t>());
       HIPC(hipGetLastError());
+      hipLaunchKernelGGL(k_values_T, dim3(nblk(nnz, kB)), dim3(kB), 0, st, rowT.as<const int32_t>(), nnz,
+                         (const double*)d_wT, (const double*)d_S, d_valT);
+      HIPC(hipGetLastError());
+      hipLaunchKernelGGL(k_edge_values, dim3(nblk(nnz, kB)), dim3(kB), 0, st, d_feats, d_col, nnz, nf,
+                         th.as<const double>(), (const double*)d_S, d_val);
+      HIPC(hipGetLastError());
+      HIPC(hipStreamSynchronize(st));  // before rowT goes back to the pool
     }
     HIPC(hipStreamSynchronize(st));  // theta's staging copy is released below
     return TC_OK;
@@ -2075,30 +2156,31 @@ extern "C" tc_status tc_rwr_iterates(const tc_handle* hc, int32_t seed, float c,
   });
 }
 
-extern "C" tc_status tc_rwr_adjoint(const tc_handle* hc, const tc_handle* htc, const int64_t* d_rp,
-                                    const int32_t* d_col, int32_t seed, float c, int32_t K, int32_t every,
+extern "C" tc_status tc_rwr_adjoint(const tc_handle* hc, const tc_handle* htc, const int64_t* d_rpT,
+                                    const int32_t* d_colT, int32_t seed, float c, int32_t K, int32_t every,
                                     const float* d_ckpt, const float* d_gK, double* d_G, float* d_g0,
                                     tc_stream_t stream) {
   return guarded("tc_rwr_adjoint", [&]() -> tc_status {
-    if (!hc || !htc || !d_rp || (hc->n_rows > 0 && !d_gK)) throw Err{TC_EINVAL, "NULL argument"};
+    if (!hc || !htc || !d_rpT || (hc->n_rows > 0 && !d_gK)) throw Err{TC_EINVAL, "NULL argument"};
     need_square(hc, "tc_rwr_adjoint");
     need_square(htc, "tc_rwr_adjoint");
     if (htc->n_rows != hc->n_rows || htc->nnz != hc->nnz) throw Err{TC_EINVAL, "the second handle must hold A^T"};
     if (K < 0 || every < 1 || !(c >= 0.0f && c <= 1.0f)) throw Err{TC_EINVAL, "need K >= 0, every >= 1, 0 <= c <= 1"};
     if (seed < 0 || seed >= hc->n_rows) throw Err{TC_EINVAL, "seed out of range"};
     const int64_t n = hc->n_rows, nnz = hc->nnz;
-    if (nnz > 0 && (!d_col || !d_G)) throw Err{TC_EINVAL, "NULL argument"};
+    if (nnz > 0 && (!d_colT || !d_G)) throw Err{TC_EINVAL, "NULL argument"};
     if (K > 0 && !d_ckpt) throw Err{TC_EINVAL, "NULL checkpoint array"};
     tc_handle* h = const_cast<tc_handle*>(hc);
     tc_handle* ht = const_cast<tc_handle*>(htc);
     hipStream_t st = (hipStream_t)stream;
     const int32_t seglen = std::min(every, std::max(K, 1));
     PoolBuf seg(sizeof(float) * (size_t)n * seglen, st), gseg(sizeof(float) * (size_t)n * seglen, st),
+        segi(sizeof(float) * (size_t)n * seglen, st), gsegi(sizeof(float) * (size_t)n * seglen, st),
         g(sizeof(float) * n, st), tmp(sizeof(float) * n, st),
         rows(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), st);
     if (nnz > 0) {
       HIPC(hipMemsetAsync(d_G, 0, sizeof(double) * nnz, st));
-      hipLaunchKernelGGL(k_rows_of, dim3(nblk(n, kB)), dim3(kB), 0, st, d_rp, n, rows.as<int32_t>());
+      hipLaunchKernelGGL(k_rows_of, dim3(nblk(n, kB)), dim3(kB), 0, st, d_rpT, n, rows.as<int32_t>());
       HIPC(hipGetLastError());
     }
     if (n > 0) HIPC(hipMemcpyAsync(g.p, d_gK, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
@@ -2125,8 +2207,15 @@ extern "C" tc_status tc_rwr_adjoint(const tc_handle* hc, const tc_handle* htc, c
         HIPC(hipGetLastError());
       }
       if (nnz > 0) {
-        hipLaunchKernelGGL(k_edge_accum_seg, dim3(nblk(nnz, kB)), dim3(kB), 0, st, rows.as<const int32_t>(), d_col,
-                           nnz, (const float*)GS, (const float*)S, k1 - k0, n, d_G);
+        const int32_t m = k1 - k0;
+        hipLaunchKernelGGL(k_interleave, dim3(nblk(n * m, kB)), dim3(kB), 0, st, (const float*)GS, m, n,
+                           gsegi.as<float>());
+        HIPC(hipGetLastError());
+        hipLaunchKernelGGL(k_interleave, dim3(nblk(n * m, kB)), dim3(kB), 0, st, (const float*)S, m, n,
+                           segi.as<float>());
+        HIPC(hipGetLastError());
+        hipLaunchKernelGGL(k_edge_accum_seg, dim3(nblk(nnz, kB)), dim3(kB), 0, st, d_colT, rows.as<const int32_t>(),
+                           nnz, gsegi.as<const float>(), segi.as<const float>(), m, d_G);
         HIPC(hipGetLastError());
       }
     }
@@ -2135,30 +2224,61 @@ extern "C" tc_status tc_rwr_adjoint(const tc_handle* hc, const tc_handle* htc, c
   });
 }
 
-extern "C" tc_status tc_rwr_theta_grad(int64_t n_cols, int64_t nnz, const int32_t* d_col, const int64_t* d_rpT,
-                                       const int32_t* d_permT, int32_t nf, const float* d_feats, const double* d_z,
-                                       const double* d_w, const double* d_S, const double* d_G, float c,
-                                       double* dtheta, tc_stream_t stream) {
+extern "C" tc_status tc_rwr_theta_grad(int64_t n_cols, int64_t nnz, const int64_t* d_rpT, int32_t nf,
+                                       const float* d_featsT, const double* d_zT, const double* d_wT,
+                                       const double* d_S, const double* d_G, float c, double* dtheta,
+                                       tc_stream_t stream) {
   return guarded("tc_rwr_theta_grad", [&]() -> tc_status {
     if (n_cols < 0 || nnz < 0 || nf < 1 || nf > kMaxFeat) throw Err{TC_EINVAL, "need sizes >= 0 and 1 <= nf <= 16"};
-    if (!dtheta || !d_rpT || !d_S ||
-        (nnz > 0 && (!d_col || !d_permT || !d_feats || !d_z || !d_w || !d_G)))
+    if (!dtheta || !d_rpT || !d_S || (nnz > 0 && (!d_featsT || !d_zT || !d_wT || !d_G)))
       throw Err{TC_EINVAL, "NULL argument"};
     hipStream_t st = (hipStream_t)stream;
     PoolBuf cs(sizeof(double) * (size_t)std::max<int64_t>(n_cols, 1), st),
+        rowT(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), st),
         parts(sizeof(double) * (size_t)kGradBlocks * nf, st), out(sizeof(double) * nf, st);
     if (n_cols > 0) {
-      hipLaunchKernelGGL(k_col_dot, dim3(nblk(n_cols, kWpb)), dim3(kB), 0, st, d_rpT, d_permT, n_cols, d_G, d_w, d_S,
-                         (double)c, cs.as<double>());
+      hipLaunchKernelGGL(k_col_dot, dim3(nblk(nblk(n_cols, kWave / kColLanes), kWpb)), dim3(kB), 0, st, d_rpT,
+                         n_cols, d_G, d_wT, d_S, (double)c, cs.as<double>());
+      HIPC(hipGetLastError());
+      hipLaunchKernelGGL(k_rows_of, dim3(nblk(n_cols, kB)), dim3(kB), 0, st, d_rpT, n_cols, rowT.as<int32_t>());
       HIPC(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_theta_grad, dim3(kGradBlocks), dim3(kB), 0, st, d_col, nnz, nf, d_feats, d_z, d_S, d_G,
-                       cs.as<const double>(), (double)c, parts.as<double>());
+    hipLaunchKernelGGL(k_theta_grad, dim3(kGradBlocks), dim3(kB), 0, st, rowT.as<const int32_t>(), nnz, nf, d_featsT,
+                       d_zT, d_S, d_G, cs.as<const double>(), (double)c, parts.as<double>());
     HIPC(hipGetLastError());
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, parts.as<const double>(), kGradBlocks, nf,
                        out.as<double>());
     HIPC(hipGetLastError());
     HIPC(hipMemcpyAsync(dtheta, out.p, sizeof(double) * nf, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    return TC_OK;
+  });
+}
+
+// dst row q = src row idx[q] (rows of `width` floats); idx is checked against
+// the source's n_src rows first
+__global__ void k_idx_check(const int32_t* __restrict__ idx, int64_t n, int64_t n_src, int32_t* __restrict__ bad) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n && (idx[q] < 0 || idx[q] >= n_src)) atomicOr(bad, 1);
+}
+
+extern "C" tc_status tc_gather_rows(const float* d_src, int64_t n_src, const int32_t* d_idx, int64_t n, int32_t width,
+                                    float* d_dst, tc_stream_t stream) {
+  return guarded("tc_gather_rows", [&]() -> tc_status {
+    if (n < 0 || n_src < 0 || width < 1) throw Err{TC_EINVAL, "need n, n_src >= 0 and width >= 1"};
+    if (n == 0) return TC_OK;
+    if (!d_src || !d_idx || !d_dst) throw Err{TC_EINVAL, "NULL argument"};
+    hipStream_t st = (hipStream_t)stream;
+    PoolBuf bad(sizeof(int32_t), st);
+    HIPC(hipMemsetAsync(bad.p, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_idx_check, dim3(nblk(n, kB)), dim3(kB), 0, st, d_idx, n, n_src, bad.as<int32_t>());
+    HIPC(hipGetLastError());
+    int32_t hbad = 0;
+    HIPC(hipMemcpyAsync(&hbad, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (hbad) throw Err{TC_EINVAL, "row index out of range"};
+    hipLaunchKernelGGL(k_gather_rows, dim3(nblk(n * width, kB)), dim3(kB), 0, st, d_src, d_idx, n, width, d_dst);
+    HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(st));
     return TC_OK;
   });

@@ -14,8 +14,10 @@ tensor of nf parameters).  The forward keeps only every ``every``-th iterate
     g^k = c W^T g^{k+1}            (tiled SpMV on a build of W^T)
     dL/dW_e += c g^{k+1}_i r^k_j   (per-entry kernel)
 
-then the normalisation and the softplus back to theta.  Every step runs in
-the HIP library (include/tcspmv.h); this module only marshals arguments.
+then the normalisation and the softplus back to theta.  The per-entry arrays
+of the gradient live in A^T's order (the features are gathered into it once),
+so the column passes read them contiguously.  Every step runs in the HIP
+library (include/tcspmv.h); this module only marshals arguments.
 """
 from __future__ import annotations
 
@@ -57,12 +59,16 @@ class EdgeWeightedRWR:
         n, nnz = self.n, self.nnz
         self.rpT = torch.empty(n + 1, dtype=torch.int64, device=dev)
         self.colT = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
-        self.permT = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        permT = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
         ones = torch.ones(max(nnz, 1), dtype=torch.float32, device=dev)
         A = CCsr(n, n, nnz, self.rp.data_ptr(), self.col.data_ptr(), ones.data_ptr())
-        _check(lib.tc_csr_transpose(ctypes.byref(A), _ptr(self.rpT), _ptr(self.colT), vp(None), _ptr(self.permT),
+        _check(lib.tc_csr_transpose(ctypes.byref(A), _ptr(self.rpT), _ptr(self.colT), vp(None), _ptr(permT),
                                     _stream(stream)), "tc_csr_transpose")
-        self.z = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+        self.featsT = torch.empty_like(self.feats)
+        _check(lib.tc_gather_rows(_ptr(self.feats), nnz, _ptr(permT), nnz, self.nf, _ptr(self.featsT),
+                                  _stream(stream)), "tc_gather_rows")
+        del permT, ones
+        self.z = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)  # A^T's order
         self.w = torch.empty_like(self.z)
         self.S = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
         self.val = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)
@@ -81,10 +87,10 @@ class EdgeWeightedRWR:
         th = np.ascontiguousarray(theta, np.float64)
         if th.size != self.nf:
             raise ValueError("theta must have one entry per feature")
-        _check(load_library().tc_rwr_edge_weights(self.n, self.nnz, _ptr(self.col), _ptr(self.rpT),
-                                                  _ptr(self.permT), self.nf, _ptr(self.feats),
-                                                  th.ctypes.data_as(vp), _ptr(self.z), _ptr(self.w), _ptr(self.S),
-                                                  _ptr(self.val), _ptr(self.valT), _stream(self.stream)),
+        _check(load_library().tc_rwr_edge_weights(self.n, self.nnz, _ptr(self.col), _ptr(self.rpT), self.nf,
+                                                  _ptr(self.feats), _ptr(self.featsT), th.ctypes.data_as(vp),
+                                                  _ptr(self.z), _ptr(self.w), _ptr(self.S), _ptr(self.val),
+                                                  _ptr(self.valT), _stream(self.stream)),
                "tc_rwr_edge_weights")
         self.close()
         n = self.n
@@ -107,13 +113,13 @@ class EdgeWeightedRWR:
         lib = load_library()
         gK = gK.to(torch.float32).contiguous()
         G = torch.empty(max(self.nnz, 1), dtype=torch.float64, device="cuda")
-        _check(lib.tc_rwr_adjoint(self.W.handle, self.Wt.handle, _ptr(self.rp), _ptr(self.col), self.seed, self.c,
-                                  self.K, self.every, _ptr(self.ckpt), _ptr(gK), _ptr(G), vp(None),
+        _check(lib.tc_rwr_adjoint(self.W.handle, self.Wt.handle, _ptr(self.rpT), _ptr(self.colT), self.seed,
+                                  self.c, self.K, self.every, _ptr(self.ckpt), _ptr(gK), _ptr(G), vp(None),
                                   _stream(self.stream)), "tc_rwr_adjoint")
         out = np.zeros(self.nf, np.float64)
-        _check(lib.tc_rwr_theta_grad(self.n, self.nnz, _ptr(self.col), _ptr(self.rpT), _ptr(self.permT), self.nf,
-                                     _ptr(self.feats), _ptr(self.z), _ptr(self.w), _ptr(self.S), _ptr(G), self.c,
-                                     out.ctypes.data_as(vp), _stream(self.stream)), "tc_rwr_theta_grad")
+        _check(lib.tc_rwr_theta_grad(self.n, self.nnz, _ptr(self.rpT), self.nf, _ptr(self.featsT), _ptr(self.z),
+                                     _ptr(self.w), _ptr(self.S), _ptr(G), self.c, out.ctypes.data_as(vp),
+                                     _stream(self.stream)), "tc_rwr_theta_grad")
         return out
 
     def scores(self, theta: torch.Tensor) -> torch.Tensor:

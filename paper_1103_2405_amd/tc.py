@@ -85,7 +85,7 @@ EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_inter
             "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
             "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory",
             "tc_rwr_multi", "tc_csr_transpose", "tc_rwr_edge_weights", "tc_rwr_iterates", "tc_rwr_adjoint",
-            "tc_rwr_theta_grad"]
+            "tc_rwr_theta_grad", "tc_gather_rows"]
 
 _lib = None
 
@@ -113,10 +113,11 @@ def load_library(path: str = LIB_PATH):
     lib.tc_rwr_multi.argtypes = [vp, i32, vp, ctypes.c_float, ctypes.c_float, i32, i32, i32, vp, P(i32), vp, vp]
     f32 = ctypes.c_float
     lib.tc_csr_transpose.argtypes = [P(CCsr), vp, vp, vp, vp, vp]
-    lib.tc_rwr_edge_weights.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.tc_gather_rows.argtypes = [vp, i64, vp, i64, i32, vp, vp]
+    lib.tc_rwr_edge_weights.argtypes = [i64, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.tc_rwr_iterates.argtypes = [vp, i32, f32, i32, i32, vp, vp, vp]
     lib.tc_rwr_adjoint.argtypes = [vp, vp, vp, vp, i32, f32, i32, i32, vp, vp, vp, vp, vp]
-    lib.tc_rwr_theta_grad.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, f32, vp, vp]
+    lib.tc_rwr_theta_grad.argtypes = [i64, i64, vp, i32, vp, vp, vp, vp, vp, f32, vp, vp]
     lib.tc_handle_info.argtypes = [vp, P(CInfo)]
     lib.tc_export_format.argtypes = [vp, P(CFormatView)]
     lib.tc_set_timing.argtypes = [vp, i32]

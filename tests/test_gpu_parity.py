@@ -426,6 +426,26 @@ def test_csr_transpose_bit_exact():
     assert np.array_equal(rpT.cpu().numpy(), np.concatenate([[0], np.cumsum(np.bincount(col, minlength=n))]))
 
 
+def test_gather_rows_bit_exact_and_index_check():
+    import ctypes
+    lib = tcmod.load_library()
+    n_src, n, width = 1000, 3001, 4
+    src = torch.from_numpy(gg.uniform_f32(n_src * width, 5)).cuda()
+    idx_h = gg.uniform_int(n, n_src, 6).astype(np.int32)
+    idx = torch.from_numpy(idx_h).cuda()
+    dst = torch.full((n * width,), -1.0, device="cuda")
+    vp = ctypes.c_void_p
+    assert lib.tc_gather_rows(vp(src.data_ptr()), n_src, vp(idx.data_ptr()), n, width, vp(dst.data_ptr()), None) == 0
+    want = src.cpu().numpy().reshape(n_src, width)[idx_h].ravel()
+    assert np.array_equal(dst.cpu().numpy().view(np.uint32), want.view(np.uint32))
+    # an index outside the source is an error, and nothing is written
+    idx_h[n // 2] = n_src
+    bad = torch.from_numpy(idx_h).cuda()
+    dst.fill_(-1.0)
+    assert lib.tc_gather_rows(vp(src.data_ptr()), n_src, vp(bad.data_ptr()), n, width, vp(dst.data_ptr()), None) != 0
+    assert torch.all(dst == -1.0)
+
+
 @pytest.mark.parametrize("scale,ef,every", [(10, 8, 7), (9, 12, 1), (11, 6, 30)])
 def test_rwr_gradient_matches_fp64_reference(scale, ef, every):
     from test_oracle_rwr_grad import problem
