@@ -632,9 +632,16 @@ __global__ void __launch_bounds__(kB) k_spmm_chunks(const Wl* __restrict__ wl, i
     for (int i = 0; i < V; ++i) partial[((int64_t)(d.info >> 2) * pieces + p) * k + col + i] = acc.a[i];
 }
 
+// Zero the rows no workload writes: block b takes rows b * rpb ..., thread
+// (r, q) of the block row r's entries q, q + kk, ... (kk = min(k, kB))
 __global__ void k_begin_spmm(float* __restrict__ Y, const int32_t* __restrict__ empty, int64_t n_empty, int32_t k) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n_empty * k) Y[(int64_t)empty[t / k] * k + t % k] = 0.0f;
+  const int32_t kk = min(k, kB), rpb = kB / kk;
+  const int32_t r = threadIdx.x / kk, q0 = threadIdx.x % kk;
+  if (r >= rpb) return;
+  for (int64_t i = (int64_t)blockIdx.x * rpb + r; i < n_empty; i += (int64_t)gridDim.x * rpb) {
+    float* row = Y + (int64_t)empty[i] * k;
+    for (int32_t q = q0; q < k; q += kk) row[q] = 0.0f;
+  }
 }
 
 __global__ void k_split_combine_mm(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
@@ -704,20 +711,24 @@ __device__ inline void block_sum_store(double (&v)[NV], double* out_base, int64_
 
 constexpr int kRedBlocks = 1024;
 
-// Sum of nparts consecutive partials for each of nv quantities, fixed order.
+// Sum of nparts consecutive partials for each of nv quantities, fixed order:
+// one wavefront per quantity (lane-strided sums, then the wavefront's tree),
+// quantities spread over the wavefronts of the grid.
 __global__ void k_finish(const double* __restrict__ parts, int nparts, int nv, double* __restrict__ out) {
-  __shared__ double sm[kB];
-  for (int q = 0; q < nv; ++q) {
+  const int lane = lane_id();
+  for (int q = blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); q < nv;
+       q += gridDim.x * kWpb) {
+    const double* pq = parts + (int64_t)q * nparts;
     double s = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += kB) s += parts[(int64_t)q * nparts + i];
-    sm[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int i = 0; i < kB; ++i) t += sm[i];
-      out[q] = t;
+    for (int i0 = lane; i0 < nparts; i0 += 8 * kWave) {  // eight loads in flight (past the end: pq[0], not added)
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = pq[i0 + u * kWave < nparts ? i0 + u * kWave : 0];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += i0 + u * kWave < nparts ? t[u] : 0.0;
     }
-    __syncthreads();
+    s = wave_sum(s);
+    if (lane == 0) out[q] = s;
   }
 }
 
@@ -800,11 +811,24 @@ __global__ void __launch_bounds__(kB) k_rwr_update(const float* __restrict__ Y, 
   double s = 0.0;
   if (rr < rpb) {
     const int32_t seed = seeds[q];
-    for (int64_t i = (int64_t)blockIdx.x * rpb + rr; i < n; i += (int64_t)gridDim.x * rpb) {
-      const int64_t e = i * k + q;
-      const float rn = (float)(c * (double)Y[e] + (i == seed ? (1.0 - c) : 0.0));
-      s += fabs((double)rn - (double)R[e]);
-      R[e] = rn;
+    const int64_t step = (int64_t)gridDim.x * rpb;
+    for (int64_t i0 = (int64_t)blockIdx.x * rpb + rr; i0 < n; i0 += 4 * step) {
+      float y[4], r[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {  // four rows' loads together (past n: row i0, not used)
+        const int64_t e = (i0 + u * step < n ? i0 + u * step : i0) * k + q;
+        y[u] = Y[e];
+        r[u] = R[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * step;
+        if (i < n) {
+          const float rn = (float)(c * (double)y[u] + (i == seed ? (1.0 - c) : 0.0));
+          s += fabs((double)rn - (double)r[u]);
+          R[i * k + q] = rn;
+        }
+      }
     }
   }
   sm[threadIdx.x] = s;
@@ -1513,7 +1537,9 @@ void spmm_plan(tc_handle* h) {
   h->mm_planned = true;
 }
 
-void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st) {
+// skip_zero: the rows no workload writes are already 0 in Y (an iteration
+// that reuses Y)
+void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st, bool skip_zero = false) {
   // four right-hand sides per lane when the rows allow 16-byte accesses
   const bool v4 = k % 4 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)Y % 16) == 0;
   const int32_t V = v4 ? 4 : 1;
@@ -1541,9 +1567,10 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
     }
     partial = h->d_mm_partial;
   }
-  if (h->n_empty > 0) {
-    hipLaunchKernelGGL(k_begin_spmm, dim3(nblk(h->n_empty * k, kB)), dim3(kB), 0, st, Y, (const int32_t*)h->d_empty,
-                       h->n_empty, k);
+  if (h->n_empty > 0 && !skip_zero) {
+    const int64_t rpb = kB / std::min(k, kB);
+    hipLaunchKernelGGL(k_begin_spmm, dim3((unsigned)std::min<int64_t>(nblk(h->n_empty, rpb), 1 << 16)), dim3(kB), 0,
+                       st, Y, (const int32_t*)h->d_empty, h->n_empty, k);
     HIPC(hipGetLastError());
   }
   for (int t = 0; t < h->n_tiles; ++t) {
@@ -1800,7 +1827,7 @@ extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k
     for (int32_t q = 0; q < k; ++q)
       if (seeds[q] < 0 || seeds[q] >= n) throw Err{TC_EINVAL, "seed out of range"};
     if (check_every < 1) check_every = 1;
-    const int nb = 256;  // reduction blocks
+    const int nb = 2048;  // update blocks (one partial per block and column)
     const size_t vb = ((sizeof(float) * (size_t)n * k + 255) / 256) * 256;
     const size_t need = 2 * vb + sizeof(double) * ((size_t)nb * k + k + 8) + 2 * sizeof(int32_t) * k;
     char* ws = (char*)workspace(h, need, st);
@@ -1824,13 +1851,13 @@ extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k
       HIPC(hipGetLastError());
       for (it = 0; it < max_iter;) {
         if (k == 1)
-          spmv_internal(h, Rm, Ym, st);
+          spmv_internal(h, Rm, Ym, st, false, it > 0);
         else
-          spmm_internal(h, Rm, Ym, k, st);
+          spmm_internal(h, Rm, Ym, k, st, it > 0);
         hipLaunchKernelGGL(k_rwr_update, dim3(nb), dim3(kB), 0, st, (const float*)Ym, Rm, n, k, (double)c,
                            (const int32_t*)dseeds, parts, nb);
         HIPC(hipGetLastError());
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)parts, nb, k, colres);
+        hipLaunchKernelGGL(k_finish, dim3(nblk(k, kWpb)), dim3(kB), 0, st, (const double*)parts, nb, k, colres);
         HIPC(hipGetLastError());
         hipLaunchKernelGGL(k_max_of, dim3(1), dim3(64), 0, st, (const double*)colres, k, mx);
         HIPC(hipGetLastError());
