@@ -329,6 +329,32 @@ def kernel_compare(A_cl23=None, reps: int = 20):
     return out
 
 
+def attainable_bandwidth(dev, gib: int = 2, reps: int = 10):
+    """What plain streaming reaches on this GPU, next to the nominal HBM peak:
+    a read-only reduction and a device copy over `gib` GiB (torch's own
+    kernels), GB/s from CUDA events on the current stream, median of reps."""
+    import torch
+    n = (gib << 30) // 4
+    a = torch.rand(n, device=dev)
+    b = torch.empty_like(a)
+    res = {}
+    for name, fn, nbytes in (("read", lambda: a.sum(), 4 * n), ("copy", lambda: b.copy_(a), 8 * n)):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        res[name + "_gbps"] = round(nbytes / (float(np.median(ts)) / 1e3) / 1e9, 1)
+    res["bytes"] = 4 * n
+    del a, b
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,6 +462,8 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    attainable = None if args.no_rwr else attainable_bandwidth(dev)
+
     kernels = None if args.no_rwr else kernel_compare(A)
     if kernels:
         log("kernels:", json.dumps(kernels))
@@ -472,6 +500,7 @@ def main():
         "pagerank_spmv_gbps": round(args.iters * spmv_bytes / (pr_ms / 1e3) / 1e9, 1),
         "csr_baseline_spmv_gbps": round(spmv_bytes / (csr_ms / 1e3) / 1e9, 1),
         "roofline": roofline,
+        "attainable": attainable,
         "rwr_batched": rwr,
         "kernels": kernels,
         "rmat20_drivers": drivers,
