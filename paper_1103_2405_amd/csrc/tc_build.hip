@@ -749,8 +749,6 @@ int32_t dev_max(const int32_t* a, int64_t n, Tmp& tmp, hipStream_t st) {
   return v;
 }
 
-int64_t ceil_to(int64_t v, int64_t s) { return (v + s - 1) / s * s; }
-
 // a1 for small inputs and very wide matrices: global atomics, with the
 // hottest columns (found from a 1/64 sample) counted in a per-block LDS table.
 void col_count_atomic(const int32_t* col_idx, int64_t nnz, int64_t n_cols, int32_t* clen, Tmp& tmp, hipStream_t st) {

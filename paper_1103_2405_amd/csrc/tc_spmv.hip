@@ -473,6 +473,33 @@ __device__ inline void add_y(float* __restrict__ Y, int32_t rid, int32_t k, int3
   }
 }
 
+// RWR restart fused into the product (one tile: each row's value is final
+// where it is written): R'[row][q] = fl32(c fl32(y) + (1 - c) [row == seed_q]),
+// the same rounding as the separate update after a stored y.
+struct RwrEpi {
+  double c;
+  const int32_t* seeds;  // internal ids, one per right-hand side
+};
+
+__device__ inline float rwr_restart(double c, float y, bool is_seed) {
+  return (float)(c * (double)y + (is_seed ? 1.0 - c : 0.0));
+}
+
+template <int V>
+__device__ inline void rwr_y(float* __restrict__ Y, int32_t rid, int32_t k, int32_t col, const Vec<V>& s,
+                             const RwrEpi& epi, const int32_t* seeds_lds) {
+  const int32_t* sd = seeds_lds + col;
+  const int32_t row = rid & ~kAddFlag;
+  float* p = Y + (int64_t)row * k + col;
+  float o[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) o[i] = rwr_restart(epi.c, (float)s.a[i], row == sd[i]);
+  if constexpr (V == 4)
+    *(float4*)p = make_float4(o[0], o[1], o[2], o[3]);
+  else
+    *p = o[0];
+}
+
 // Cross-group sum of a row-major row: the groups took interleaved entries,
 // and an xor tree over the group bits of the lane id adds their sums.
 template <int V>
@@ -534,12 +561,19 @@ __device__ inline Vec<V> rm_range(const int32_t* __restrict__ idx, const float* 
 // shows up here: it is then done whole, as one piece).
 // SUB: rows summed per lane group in one column step (accumulators per lane).
 // `slices` wavefronts share a workload, slice s taking every slices-th step.
-template <int V, int SUB>
+// RWR: rows are written through the fused restart (epi) instead of stored.
+template <int V, int SUB, bool RWR = false>
 __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int64_t n_wl, int32_t slices,
                                                   const int32_t* __restrict__ idx,
                                                   const float* __restrict__ val, const int32_t* __restrict__ rowid,
                                                   const float* __restrict__ X, float* __restrict__ Y, int32_t k,
-                                                  int32_t kg, double* __restrict__ partial) {
+                                                  int32_t kg, double* __restrict__ partial, RwrEpi epi) {
+  // fused restart: the seeds (k <= kB) in LDS, read only where rows are written
+  __shared__ int32_t sd[RWR ? kB : 1];
+  if constexpr (RWR) {
+    if ((int32_t)threadIdx.x < k) sd[threadIdx.x] = epi.seeds[threadIdx.x];
+    __syncthreads();
+  }
   const int lane = lane_id();
   const int64_t w = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (w >= n_wl * slices) return;
@@ -584,7 +618,12 @@ __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int
 #pragma unroll
         for (int u = 0; u < SUB; ++u) {
           const int32_t r = r0 + u * groups + g;
-          if (u < subs && r < d.n_rows) add_y<V>(Y, ld_nt(rowid + d.rowid_off + r), k, col, a[u]);
+          if (u < subs && r < d.n_rows) {
+            if constexpr (RWR)
+              rwr_y<V>(Y, ld_nt(rowid + d.rowid_off + r), k, col, a[u], epi, sd);
+            else
+              add_y<V>(Y, ld_nt(rowid + d.rowid_off + r), k, col, a[u]);
+          }
         }
       }
     }
@@ -598,7 +637,10 @@ __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int
 #pragma unroll
           for (int i = 0; i < V; ++i) partial[(int64_t)(d.info >> 2) * k + col + i] = acc.a[i];
         } else {
-          add_y<V>(Y, ld_nt(rowid + d.rowid_off + r), k, col, acc);
+          if constexpr (RWR)
+            rwr_y<V>(Y, ld_nt(rowid + d.rowid_off + r), k, col, acc, epi, sd);
+          else
+            add_y<V>(Y, ld_nt(rowid + d.rowid_off + r), k, col, acc);
         }
       }
     }
@@ -634,18 +676,21 @@ __global__ void __launch_bounds__(kB) k_spmm_chunks(const Wl* __restrict__ wl, i
 
 // Zero the rows no workload writes: block b takes rows b * rpb ..., thread
 // (r, q) of the block row r's entries q, q + kk, ... (kk = min(k, kB))
-__global__ void k_begin_spmm(float* __restrict__ Y, const int32_t* __restrict__ empty, int64_t n_empty, int32_t k) {
+// (with the fused restart, epi.seeds != NULL: the rows' restart values)
+__global__ void k_begin_spmm(float* __restrict__ Y, const int32_t* __restrict__ empty, int64_t n_empty, int32_t k,
+                             RwrEpi epi) {
   const int32_t kk = min(k, kB), rpb = kB / kk;
   const int32_t r = threadIdx.x / kk, q0 = threadIdx.x % kk;
   if (r >= rpb) return;
   for (int64_t i = (int64_t)blockIdx.x * rpb + r; i < n_empty; i += (int64_t)gridDim.x * rpb) {
-    float* row = Y + (int64_t)empty[i] * k;
-    for (int32_t q = q0; q < k; q += kk) row[q] = 0.0f;
+    const int32_t e = empty[i];
+    float* row = Y + (int64_t)e * k;
+    for (int32_t q = q0; q < k; q += kk) row[q] = epi.seeds ? rwr_restart(epi.c, 0.0f, e == epi.seeds[q]) : 0.0f;
   }
 }
 
 __global__ void k_split_combine_mm(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
-                                   int32_t pieces, float* __restrict__ Y, int32_t k) {
+                                   int32_t pieces, float* __restrict__ Y, int32_t k, RwrEpi epi) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * k) return;
   const int64_t i = t / k;
@@ -654,7 +699,9 @@ __global__ void k_split_combine_mm(const SplitRow* __restrict__ sr, int64_t n, c
   double acc = 0.0;
   for (int64_t u = (int64_t)s.slot_begin * pieces; u < (int64_t)(s.slot_begin + s.n_slots) * pieces; ++u)
     acc += partial[u * k + q];
-  if (s.store)
+  if (epi.seeds)  // fused restart (one tile: the chunks are all of the row)
+    Y[(int64_t)s.row * k + q] = rwr_restart(epi.c, (float)acc, s.row == epi.seeds[q]);
+  else if (s.store)
     Y[(int64_t)s.row * k + q] = (float)acc;
   else
     add_to_y(Y + (int64_t)s.row * k, q, acc);
@@ -686,8 +733,6 @@ __global__ void k_gather_rows(const float* __restrict__ in, const int32_t* __res
   const int32_t q = (int32_t)(t % w);
   out[t] = in[(int64_t)perm[k] * w + q];
 }
-
-__global__ void k_set_f64(double* p, double v) { *p = v; }
 
 template <int NV>
 __device__ inline void block_sum_store(double (&v)[NV], double* out_base, int64_t stride) {
@@ -833,7 +878,7 @@ __global__ void __launch_bounds__(kB) k_rwr_update(const float* __restrict__ Y, 
   }
   sm[threadIdx.x] = s;
   __syncthreads();
-  if (threadIdx.x < k) {
+  if ((int32_t)threadIdx.x < k) {
     double t = 0.0;
     for (int32_t u = 0; u < rpb; ++u) t += sm[u * k + threadIdx.x];
     parts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = t;
@@ -1352,7 +1397,7 @@ __global__ void __launch_bounds__(kB) k_theta_grad(const int32_t* __restrict__ r
     if (lane == 0) sm[d][wv] = t;
   }
   __syncthreads();
-  if (threadIdx.x < nf) {
+  if ((int32_t)threadIdx.x < nf) {
     double t = 0.0;
     for (int q = 0; q < kB / kWave; ++q) t += sm[threadIdx.x][q];
     parts[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
@@ -1537,9 +1582,14 @@ void spmm_plan(tc_handle* h) {
   h->mm_planned = true;
 }
 
-// skip_zero: the rows no workload writes are already 0 in Y (an iteration
-// that reuses Y)
-void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st, bool skip_zero = false) {
+// epi (one tile, k <= kB): write the RWR restart of every row instead of
+// the product.  skip_empty: the rows no workload writes already hold what
+// this call would write there (0, or with epi their restart values).
+void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st, bool skip_empty = false,
+                   const RwrEpi* epi = nullptr) {
+  if (epi && !(h->n_tiles == 1 && h->xcd_groups == 0 && k <= kB))
+    throw Err{TC_EINVAL, "fused restart needs one tile and k <= 256"};
+  const RwrEpi ep = epi ? *epi : RwrEpi{0.0, nullptr};
   // four right-hand sides per lane when the rows allow 16-byte accesses
   const bool v4 = k % 4 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)Y % 16) == 0;
   const int32_t V = v4 ? 4 : 1;
@@ -1567,10 +1617,10 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
     }
     partial = h->d_mm_partial;
   }
-  if (h->n_empty > 0 && !skip_zero) {
+  if (h->n_empty > 0 && !skip_empty) {
     const int64_t rpb = kB / std::min(k, kB);
     hipLaunchKernelGGL(k_begin_spmm, dim3((unsigned)std::min<int64_t>(nblk(h->n_empty, rpb), 1 << 16)), dim3(kB), 0,
-                       st, Y, (const int32_t*)h->d_empty, h->n_empty, k);
+                       st, Y, (const int32_t*)h->d_empty, h->n_empty, k, ep);
     HIPC(hipGetLastError());
   }
   for (int t = 0; t < h->n_tiles; ++t) {
@@ -1581,14 +1631,16 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
                   st, (const Wl*)(h->d_wl + b), lead, pieces, (const int32_t*)h->d_idx, (const float*)h->d_val, X, k,
                   kg, partial);
     if (e > b + lead)
-      launch_tile(h, v4 ? k_tile_spmm<4, 4> : k_tile_spmm<1, 8>, dim3(nblk((e - b - lead) * slices, kWpb), kchunks),
-                  dim3(kB), 0, st, (const Wl*)(h->d_wl + b + lead), (int64_t)(e - b - lead), slices,
-                  (const int32_t*)h->d_idx,
-                  (const float*)h->d_val, (const int32_t*)h->d_rowid, X, Y, k, kg, partial);
+      launch_tile(h,
+                  epi ? (v4 ? k_tile_spmm<4, 4, true> : k_tile_spmm<1, 8, true>)
+                      : (v4 ? k_tile_spmm<4, 4> : k_tile_spmm<1, 8>),
+                  dim3(nblk((e - b - lead) * slices, kWpb), kchunks), dim3(kB), 0, st,
+                  (const Wl*)(h->d_wl + b + lead), (int64_t)(e - b - lead), slices, (const int32_t*)h->d_idx,
+                  (const float*)h->d_val, (const int32_t*)h->d_rowid, X, Y, k, kg, partial, ep);
   }
   if (h->n_split_rows > 0) {
     hipLaunchKernelGGL(k_split_combine_mm, dim3(nblk(h->n_split_rows * k, kB)), dim3(kB), 0, st, h->d_split,
-                       h->n_split_rows, (const double*)partial, pieces, Y, k);
+                       h->n_split_rows, (const double*)partial, pieces, Y, k, ep);
     HIPC(hipGetLastError());
   }
   h->spmv_calls++;
@@ -1849,18 +1901,40 @@ extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k
     if (n > 0) {
       hipLaunchKernelGGL(k_rwr_init, dim3(nblk(n * k, kB)), dim3(kB), 0, st, Rm, n, k, (const int32_t*)dseeds);
       HIPC(hipGetLastError());
+      // Iterations whose L1 change is not read run the restart fused into the
+      // product, into the other buffer (one tile, k > 1); the others run the
+      // product and then the update with its per-column change.
+      const bool fuse = k > 1 && h->n_tiles == 1 && h->xcd_groups == 0;
+      const RwrEpi epi{(double)c, dseeds};
+      // what the rows without entries hold in each buffer (they change only
+      // between 0, for a product, and their restart values)
+      enum { kUnknown, kZero, kRestart };
+      float* buf[2] = {Rm, Ym};
+      int held[2] = {kUnknown, kUnknown};
+      int cur = 0;
       for (it = 0; it < max_iter;) {
-        if (k == 1)
-          spmv_internal(h, Rm, Ym, st, false, it > 0);
-        else
-          spmm_internal(h, Rm, Ym, k, st, it > 0);
-        hipLaunchKernelGGL(k_rwr_update, dim3(nb), dim3(kB), 0, st, (const float*)Ym, Rm, n, k, (double)c,
-                           (const int32_t*)dseeds, parts, nb);
-        HIPC(hipGetLastError());
-        hipLaunchKernelGGL(k_finish, dim3(nblk(k, kWpb)), dim3(kB), 0, st, (const double*)parts, nb, k, colres);
-        HIPC(hipGetLastError());
-        hipLaunchKernelGGL(k_max_of, dim3(1), dim3(64), 0, st, (const double*)colres, k, mx);
-        HIPC(hipGetLastError());
+        const bool need_res = it + 1 == max_iter || (tol > 0.0f && (it + 1) % check_every == 0);
+        float* Rcur = buf[cur];
+        float* Yb = buf[1 - cur];
+        if (fuse && !need_res) {
+          spmm_internal(h, Rcur, Yb, k, st, held[1 - cur] == kRestart, &epi);
+          held[1 - cur] = kRestart;
+          cur = 1 - cur;
+        } else {
+          if (k == 1)
+            spmv_internal(h, Rcur, Yb, st, false, held[1 - cur] == kZero);
+          else
+            spmm_internal(h, Rcur, Yb, k, st, held[1 - cur] == kZero);
+          held[1 - cur] = kZero;
+          hipLaunchKernelGGL(k_rwr_update, dim3(nb), dim3(kB), 0, st, (const float*)Yb, Rcur, n, k, (double)c,
+                             (const int32_t*)dseeds, parts, nb);
+          HIPC(hipGetLastError());
+          held[cur] = kRestart;  // the update wrote every row of R
+          hipLaunchKernelGGL(k_finish, dim3(nblk(k, kWpb)), dim3(kB), 0, st, (const double*)parts, nb, k, colres);
+          HIPC(hipGetLastError());
+          hipLaunchKernelGGL(k_max_of, dim3(1), dim3(64), 0, st, (const double*)colres, k, mx);
+          HIPC(hipGetLastError());
+        }
         ++it;
         if (tol > 0.0f && (it % check_every == 0 || it == max_iter)) {
           r = read_f64(mx, st);
@@ -1871,7 +1945,7 @@ extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k
         }
       }
       if (it > 0) r = read_f64(mx, st);
-      gather_rows(Rm, h->d_rowmap, n, k, R_out, st);
+      gather_rows(buf[cur], h->d_rowmap, n, k, R_out, st);
     }
     if (iters) *iters = it;
     if (resid) *resid = r;

@@ -339,10 +339,11 @@ def test_hits_matches_oracle():
         TiledMatrix(empty).hits(0.0, 2)
 
 
-def test_rwr_matches_oracle():
+@pytest.mark.parametrize("W", [1024, 0])  # several tiles; one tile (restart fused into the SpMM)
+def test_rwr_matches_oracle(W):
     g = gg.rmat(12, 16, seed=8)
     csr = gg.rwr_matrix(g)
-    gm = TiledMatrix(csr, tile_width=1024)
+    gm = TiledMatrix(csr, tile_width=W)
     seeds = gg.rwr_seeds(g, 32, 40)
     for k in (1, 5, 32):
         R, it, res = gm.rwr(seeds[:k], 0.85, 0.0, 30)
@@ -350,6 +351,27 @@ def test_rwr_matches_oracle():
         d = np.abs(R.cpu().numpy() - Rref).sum(axis=0)
         say("rwr L1 diff per column", d)
         assert np.all(d <= 1e-6)
+
+
+@pytest.mark.parametrize("split", [-1, 64])
+def test_rwr_fused_restart_equals_separate_update(split):
+    # with the change read every iteration no step is fused; with a fixed
+    # count every step but the last is: the iterates must agree bit for bit.
+    # A seed on a node without edges exercises the rows no workload writes.
+    g = gg.rmat(12, 8, seed=5)
+    csr = gg.rwr_matrix(g)
+    empty = np.flatnonzero(np.diff(csr[2]) == 0)
+    assert empty.size > 0
+    seeds = [int(v) for v in gg.rwr_seeds(g, 7, 3)] + [int(empty[0])]
+    gm = TiledMatrix(csr, split_len=split)
+    assert gm.info()["n_tiles"] == 1
+    for k in (8, 3):
+        a, it, ra = gm.rwr(seeds[-k:], 0.85, 1e-7, 500, 1)
+        b, it2, rb = gm.rwr(seeds[-k:], 0.85, 0.0, it)
+        assert it2 == it and ra == rb
+        assert torch.equal(a, b), k
+        ref, _, _ = oracle.rwr(csr, seeds[-k:], 0.85, 0.0, it)
+        assert np.all(np.abs(b.cpu().numpy() - ref).sum(axis=0) <= 1e-6)
 
 
 # ------------------------------------------------------------ several graphs per launch
