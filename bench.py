@@ -432,7 +432,8 @@ def main():
         traffic = read_traffic(os.path.join(ROOT, "profiles", "k_tile_spmv_%s_pagerank_counters.txt" % args.workload))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "k_tile_spmv", "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "kernel": "k_tile_spmv_pr",  # the product with the fused update; k_tile_spmv on the last iteration
+                    "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches_per_spmv": round(launches / max(calls, 1), 2),
                     "bytes_per_launch": int(per_launch_bytes)}
 

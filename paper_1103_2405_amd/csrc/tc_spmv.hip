@@ -299,6 +299,19 @@ struct StagedX {
   __device__ void addy(float* y, int32_t row, double s) const { addy_policy<true>(y, row, s); }
 };
 
+// ... or with the PageRank update fused into the row writes (one tile: each
+// row's value is final where it is written):
+//   p'[row] = fl32(c (fl32(s) + d/n) + (1 - c)/n),
+// the rounding of the separate update after a stored y.
+struct PrX {
+  const float* __restrict__ x;
+  double c, dn, tele;
+  __device__ float operator()(int32_t i) const { return x[i]; }
+  __device__ void addy(float* y, int32_t rid, double s) const {
+    y[rid & ~kAddFlag] = (float)(c * ((double)(float)s + dn) + tele);
+  }
+};
+
 // ... or writing a private copy of y: every row of a tile is written once,
 // so the copy is stored whatever the first-writer flag says.
 struct PrivX {
@@ -341,6 +354,20 @@ __global__ void __launch_bounds__(kB) k_tile_spmv(const Wl* __restrict__ wl, int
   if (j >= n_wl) return;
   const Wl d = wl[j];
   run_workload(d, lane, idx, val, rowid, GlobalX<YNT>{x}, y, partial);
+}
+
+// The tile kernel with the fused PageRank update (PrX); d = *dmass, the
+// dangling mass of x.
+__global__ void __launch_bounds__(kB) k_tile_spmv_pr(const Wl* __restrict__ wl, int64_t n_wl,
+                                                     const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                     const int32_t* __restrict__ rowid, const float* __restrict__ x,
+                                                     float* __restrict__ pn, double* __restrict__ partial, double c,
+                                                     const double* __restrict__ dmass, int64_t n) {
+  const int lane = lane_id();
+  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (j >= n_wl) return;
+  const Wl d = wl[j];
+  run_workload(d, lane, idx, val, rowid, PrX{x, c, *dmass / (double)n, (1.0 - c) / (double)n}, pn, partial);
 }
 
 // Concurrent pass over tiles 1..G of the XCD schedule.  Workgroups are
@@ -840,6 +867,34 @@ __global__ void __launch_bounds__(kB) k_hits_update(const float* __restrict__ y,
     v[0] += fabs((double)xn - (double)x[i]);
     x[i] = xn;
   }
+  block_sum_store<1>(v, parts + blockIdx.x, gridDim.x);
+}
+
+// Fused PageRank step, the rows the tile kernel does not write: split rows
+// (their chunks' sums) and rows without entries (y = 0), same formula as PrX.
+__global__ void k_pr_split_empty(const SplitRow* __restrict__ sr, int64_t n_split, const double* __restrict__ partial,
+                                 const int32_t* __restrict__ empty, int64_t n_empty, float* __restrict__ pn, double c,
+                                 const double* __restrict__ dmass, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double dn = *dmass / (double)n, tele = (1.0 - c) / (double)n;
+  if (t < n_split) {
+    const SplitRow s = sr[t];
+    double acc = 0.0;
+    for (int32_t q = 0; q < s.n_slots; ++q) acc += partial[s.slot_begin + q];
+    pn[s.row] = (float)(c * ((double)(float)acc + dn) + tele);
+  } else if (t < n_split + n_empty) {
+    pn[empty[t - n_split]] = (float)(c * ((double)0.0f + dn) + tele);
+  }
+}
+
+// Dangling mass of p, split over blocks exactly as k_pr_update splits it
+// (same elements per thread, same order), into parts[blockIdx.x]
+__global__ void __launch_bounds__(kB) k_dang_sum(const float* __restrict__ p, int64_t n, int64_t dang_begin,
+                                                 double* __restrict__ parts) {
+  const int64_t base = (int64_t)blockIdx.x * kB + threadIdx.x, stride = (int64_t)gridDim.x * kB;
+  const int64_t i0 = base >= dang_begin ? base : base + (dang_begin - base + stride - 1) / stride * stride;
+  double v[1] = {0.0};
+  for (int64_t i = i0; i < n; i += stride) v[0] += (double)p[i];
   block_sum_store<1>(v, parts + blockIdx.x, gridDim.x);
 }
 
@@ -1773,13 +1828,51 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
       HIPC(hipGetLastError());
       const bool xcd = h->xcd_groups > 0 && h->n_tiles > 1;
       const int32_t G = xcd ? h->n_tiles - 1 : 0;
+      // Iterations whose L1 change is not read run the update fused into the
+      // product, into the other buffer (one tile, composite kernel); their
+      // dangling mass comes from a pass over the dangling range alone.  The
+      // others run the product into the other buffer, then the update in place.
+      const bool fuse = !xcd && h->n_tiles == 1 && h->kernel == 0 && !tile_config().persist;
+      float* buf[2] = {p, y};
+      bool zero_rows[2] = {false, false};  // the buffer's rows without entries hold 0
+      int cur = 0;
       for (it = 0; it < max_iter;) {
-        spmv_internal(h, p, y, st, xcd, it > 0);
-        hipLaunchKernelGGL(k_pr_update, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)y, (const float*)h->d_ypriv,
-                           G, p, n, n - h->n_dangling, (double)c, (const double*)(res + 1), parts);
-        HIPC(hipGetLastError());
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)parts, kRedBlocks, 2, res);
-        HIPC(hipGetLastError());
+        const bool need_res = it + 1 == max_iter || (tol > 0.0f && (it + 1) % check_every == 0);
+        float* pc = buf[cur];
+        float* pn = buf[1 - cur];
+        if (fuse && !need_res) {
+          const int64_t b = h->tile_wl_begin[0], e = h->tile_wl_begin[1];
+          if (e > b)
+            launch_tile(h, k_tile_spmv_pr, dim3(nblk(e - b, kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
+                        (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
+                        (const int32_t*)h->d_rowid, (const float*)pc, pn, h->d_partial, (double)c,
+                        (const double*)(res + 1), n);
+          if (h->n_split_rows + h->n_empty > 0) {
+            hipLaunchKernelGGL(k_pr_split_empty, dim3(nblk(h->n_split_rows + h->n_empty, kB)), dim3(kB), 0, st,
+                               h->d_split, h->n_split_rows, (const double*)h->d_partial,
+                               (const int32_t*)h->d_empty, h->n_empty, pn, (double)c, (const double*)(res + 1), n);
+            HIPC(hipGetLastError());
+          }
+          hipLaunchKernelGGL(k_dang_sum, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)pn, n, n - h->n_dangling,
+                             parts + kRedBlocks);
+          HIPC(hipGetLastError());
+          hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)(parts + kRedBlocks), kRedBlocks, 1,
+                             res + 1);
+          HIPC(hipGetLastError());
+          h->spmv_calls++;
+          zero_rows[1 - cur] = false;
+          cur = 1 - cur;
+        } else {
+          spmv_internal(h, pc, pn, st, xcd, zero_rows[1 - cur]);
+          zero_rows[1 - cur] = true;
+          hipLaunchKernelGGL(k_pr_update, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)pn,
+                             (const float*)h->d_ypriv, G, pc, n, n - h->n_dangling, (double)c,
+                             (const double*)(res + 1), parts);
+          HIPC(hipGetLastError());
+          zero_rows[cur] = false;
+          hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)parts, kRedBlocks, 2, res);
+          HIPC(hipGetLastError());
+        }
         ++it;
         if (tol > 0.0f && (it % check_every == 0 || it == max_iter)) {
           r = read_f64(res, st);
@@ -1790,7 +1883,7 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
         }
       }
       if (it > 0) r = read_f64(res, st);
-      gather_rows(p, h->d_rowmap, n, 1, p_out, st);
+      gather_rows(buf[cur], h->d_rowmap, n, 1, p_out, st);
     }
     if (iters) *iters = it;
     if (resid) *resid = r;

@@ -312,6 +312,24 @@ def test_pagerank_rmat14_50_iterations():
     assert abs(res - rref[-1]) <= 1e-6
 
 
+@pytest.mark.parametrize("split", [-1, 64])
+def test_pagerank_fused_update_equals_separate_update(split):
+    # with the change read every iteration no step is fused; with a fixed
+    # count every step but the last is: the iterates must agree bit for bit
+    # (rows without entries, dangling columns and split rows included)
+    g = gg.rmat(13, 8, seed=21)
+    csr = gg.pagerank_matrix(g)
+    assert np.any(np.diff(csr[2]) == 0) and np.any(np.bincount(csr[3], minlength=csr[1]) == 0)
+    gm = TiledMatrix(csr, split_len=split)
+    assert gm.info()["n_tiles"] == 1
+    a, it, ra = gm.pagerank(0.85, 1e-7, 300, check_every=1)
+    b, it2, rb = gm.pagerank(0.85, 0.0, it)
+    assert it2 == it and ra == rb
+    assert torch.equal(a, b)
+    pref, _, _ = oracle.pagerank(csr, 0.85, 0.0, it)
+    assert np.abs(b.cpu().numpy() - pref).sum() <= 1e-6
+
+
 def test_pagerank_converges_to_tolerance():
     g = gg.rmat(12, 16, seed=1)
     csr = gg.pagerank_matrix(g)
