@@ -92,6 +92,10 @@ typedef struct {
                                  coordinate form, equal intervals per wavefront and a segmented
                                  sum (Section 3.1, Observation 3); the composite workloads are
                                  still built (SpMM and the metadata use them) */
+  int32_t value_map;          /* 1: keep, for every padded slot, the CSR entry it holds (4 bytes
+                                 per slot on the device), so tc_refresh_values can put new values
+                                 of the same pattern in place without a rebuild.  Composite
+                                 kernel only; default 0 */
   const char* perf_table;     /* path of a throughput table for the model; NULL = built-in */
   /* optional device allocator for the handle's buffers; NULL = hipMalloc / hipFree */
   void* (*alloc)(size_t bytes, void* ctx);
@@ -298,6 +302,14 @@ tc_status tc_csr_spmv(const tc_csr* A, const float* d_x, float* d_y, tc_stream_t
 
 /* Sizes and parameters of a handle (host, no GPU work). */
 tc_status tc_handle_info(const tc_handle* h, tc_info* info);
+
+/* New values for the pattern the handle was built from: d_val holds nnz
+ * floats in the order of that CSR's entries (device).  The format's values
+ * become exactly what a build from the same CSR with these values would hold;
+ * nothing else changes.  Needs a handle built with value_map = 1 (else
+ * TC_EINVAL).  Asynchronous on the stream; d_val may be released once the
+ * stream reaches this point. */
+tc_status tc_refresh_values(tc_handle* h, const float* d_val, tc_stream_t stream);
 
 /* Copy the format to host arrays (synchronous). */
 tc_status tc_export_format(const tc_handle* h, tc_format_view* view);

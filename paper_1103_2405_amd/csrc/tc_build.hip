@@ -536,7 +536,7 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
                                              const int32_t* __restrict__ rows_sorted,
                                              const int32_t* __restrict__ b_icol, const float* __restrict__ b_val,
                                              const int32_t* __restrict__ first, int32_t* __restrict__ idx,
-                                             float* __restrict__ val, int32_t* __restrict__ rowid) {
+                                             float* __restrict__ val, int32_t* __restrict__ rowid, float pad) {
   // kPackSlices wavefronts per workload, slice sl taking every kPackSlices-th
   // row (RM), row block of 64 (CM) or 64-entry block (chunk).  Four positions'
   // loads go out together, then their stores: a position past its row's L
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
         const int64_t c = c0 + u * step;
         if (c < d.w_pad) {
           idx[off + c] = c < L ? ti[u] : d.tile_first;
-          val[off + c] = c < L ? tv[u] : 0.0f;
+          val[off + c] = c < L ? tv[u] : pad;
         }
       }
     }
@@ -593,7 +593,7 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
           const int64_t c = c0 + u * kWave;
           if (c < d.w_pad) {
             idx[base + c] = c < L ? ti[u] : d.tile_first;
-            val[base + c] = c < L ? tv[u] : 0.0f;
+            val[base + c] = c < L ? tv[u] : pad;
           }
         }
       }
@@ -628,7 +628,7 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
           if (c < d.w_pad) {
             const int64_t e = off + (int64_t)c * d.h_pad + r;
             idx[e] = c < L ? ti[u] : d.tile_first;
-            val[e] = c < L ? tv[u] : 0.0f;
+            val[e] = c < L ? tv[u] : pad;
           }
         }
       }
@@ -638,8 +638,42 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
   if (sl == 0)
     for (int32_t c = lane; c < d.extra; c += kWave) {
       idx[end + c] = d.tile_first;
-      val[end + c] = 0.0f;
+      val[end + c] = pad;
     }
+}
+
+// the bit pattern of int32 -1 as a float (the value map's pad mark)
+float pad_minus_one() {
+  const int32_t m = -1;
+  float f;
+  std::memcpy(&f, &m, sizeof f);
+  return f;
+}
+
+// Value map: the build carries every entry's CSR index in place of its value
+// (bit pattern) and marks pads with -1; this keeps the map and puts the
+// values in.
+__global__ void k_iota_i32(int32_t* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (int32_t)i;
+}
+
+__global__ void k_vmap_finish(float* __restrict__ val, int64_t n, const float* __restrict__ src,
+                              int32_t* __restrict__ vmap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t e = __float_as_int(val[i]);
+  vmap[i] = e;
+  val[i] = e >= 0 ? src[e] : 0.0f;
+}
+
+__global__ void k_refresh_vals(const int32_t* __restrict__ vmap, int64_t n, const float* __restrict__ src,
+                               float* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t e = vmap[i];
+  const float v = src[e >= 0 ? e : 0];  // a pad reads entry 0 and stores 0
+  val[i] = e >= 0 ? v : 0.0f;
 }
 
 // ------------------------------------------------------ counting-sort ops
@@ -1093,6 +1127,14 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   int32_t *b_icol = nullptr, *b_row = nullptr;
   const float* b_val = nullptr;
   std::vector<int64_t> tstart(ntiles + 1, 0);
+  // value map: entry indices stand in for the values through a4-a7
+  const float* vsrc = A->val;
+  if (o->value_map && nnz > 0) {
+    int32_t* iota = tmp.get<int32_t>(nnz);
+    hipLaunchKernelGGL(k_iota_i32, dim3(nblk(nnz, kB)), dim3(kB), 0, st, iota, nnz);
+    HIPX(hipGetLastError());
+    vsrc = (const float*)iota;
+  }
   if (nnz > 0) {
     int32_t* icol = tmp.get<int32_t>(nnz);
     hipLaunchKernelGGL(k_icol, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, cpos, nnz, icol);
@@ -1100,7 +1142,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     const int tb = bits_for((uint64_t)(ntiles > 1 ? ntiles - 1 : 0));
     if (one_tile) {
       b_icol = icol;
-      b_val = A->val;
+      b_val = vsrc;
     } else {
       int32_t* row_of = tmp.get<int32_t>(nnz);
       hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, row_of);
@@ -1112,7 +1154,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       float* bv[2] = {tmp.get<float>(nnz), nullptr};
       const int32_t* ci = icol;
       const int32_t* cr = row_of;
-      const float* cv = A->val;
+      const float* cv = vsrc;
       int p = 0;
       for (int sh = 0; sh < tb; sh += 8, ++p) {
         const int s = p & 1;
@@ -1368,8 +1410,16 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipMemcpyAsync(d_pwl, pwl.data(), sizeof(PackWl) * nwl, hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(h->d_wl, dwl.data(), sizeof(Wl) * nwl, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_pack, dim3(nblk(nwl * kPackSlices, kB / kWave)), dim3(kB), 0, st, d_pwl, nwl, srt_start, rows_len,
-                       rows_sorted, b_icol, b_val, (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid);
+                       rows_sorted, b_icol, b_val, (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid,
+                       o->value_map ? pad_minus_one() : 0.0f);
     HIPX(hipGetLastError());
+  }
+  if (o->value_map) {
+    h->d_vmap = hold<int32_t>(h, doff);
+    if (doff > 0) {
+      hipLaunchKernelGGL(k_vmap_finish, dim3(nblk(doff, kB)), dim3(kB), 0, st, h->d_val, doff, A->val, h->d_vmap);
+      HIPX(hipGetLastError());
+    }
   }
   // TILE-COO: the bucketed entries themselves, with internal rows and the
   // first-touch flag of the coordinate kernel (a row's first tile stores)
@@ -1449,6 +1499,26 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
 
 using namespace tc;
 
+extern "C" tc_status tc_refresh_values(tc_handle* h, const float* d_val, tc_stream_t stream) {
+  if (!h || (h->nnz > 0 && !d_val)) {
+    set_error("tc_refresh_values: NULL argument");
+    return TC_EINVAL;
+  }
+  if (!h->d_vmap) {
+    set_error("tc_refresh_values: the handle was built without value_map");
+    return TC_EINVAL;
+  }
+  if (h->nnz_pad > 0) {
+    hipLaunchKernelGGL(k_refresh_vals, dim3(nblk(h->nnz_pad, kB)), dim3(kB), 0, (hipStream_t)stream,
+                       (const int32_t*)h->d_vmap, h->nnz_pad, d_val, h->d_val);
+    if (hipGetLastError() != hipSuccess) {
+      set_error("tc_refresh_values: launch failed");
+      return TC_EHIP;
+    }
+  }
+  return TC_OK;
+}
+
 extern "C" void tc_build_opts_default(tc_build_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
@@ -1482,7 +1552,7 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
     set_error("tc_build_tiled: NULL CSR array");
     return TC_EINVAL;
   }
-  if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->xcd_groups < 0 || o->xcd_groups > 64 || o->kernel < 0 || o->kernel > 1 || (o->kernel == 1 && o->xcd_groups > 0) || o->max_act_warp < 0 || o->wl_policy < 0 ||
+  if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->xcd_groups < 0 || o->xcd_groups > 64 || o->kernel < 0 || o->kernel > 1 || (o->kernel == 1 && o->xcd_groups > 0) || o->value_map < 0 || o->value_map > 1 || (o->value_map && o->kernel == 1) || o->max_act_warp < 0 || o->wl_policy < 0 ||
       o->wl_policy > 2 || (o->wl_policy == 1 && !o->wl_per_tile) || (o->relabel > 0 && A->n_rows != A->n_cols)) {
     set_error("tc_build_tiled: invalid option");
     return TC_EINVAL;

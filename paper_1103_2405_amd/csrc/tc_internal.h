@@ -142,6 +142,8 @@ struct tc_handle {
   int64_t n_zero0 = 0;
   int n_cu = 256;                   // compute units of the device
   int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
+  // value map (build option): the CSR entry of every padded slot, -1 for pads
+  int32_t* d_vmap = nullptr;
   // TILE-COO (kernel == 1): every tile's entries in coordinate form
   int32_t kernel = 0;
   int32_t* d_coo_row = nullptr;     // internal row | kAddFlag when an earlier tile holds the row

@@ -37,8 +37,9 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 class EdgeWeightedRWR:
-    """Pattern, features and the transposed structure, built once; a forward
-    per theta builds the tiled formats of W and W^T."""
+    """Pattern, features and the transposed structure, built once.  The first
+    forward builds the tiled formats of W and W^T (with value maps); later
+    forwards only put the new values into them."""
 
     def __init__(self, pattern, feats, seed: int, c: float = 0.85, K: int = 30, every: int = 6,
                  build_opts: Optional[dict] = None, stream=None):
@@ -92,12 +93,18 @@ class EdgeWeightedRWR:
                                                   _ptr(self.z), _ptr(self.w), _ptr(self.S), _ptr(self.val),
                                                   _ptr(self.valT), _stream(self.stream)),
                "tc_rwr_edge_weights")
-        self.close()
         n = self.n
+        refresh = self.opts.get("kernel", "composite") == "composite"
+        if refresh and self.W is not None:
+            # same pattern, new values: put them into the existing formats
+            self.W.refresh_values(self.val[:self.nnz], stream=self.stream)
+            self.Wt.refresh_values(self.valT[:self.nnz], stream=self.stream)
+            return
+        self.close()
         self.W = TiledMatrix(DeviceCsr((n, n, self.rp, self.col, self.val[:self.nnz])), stream=self.stream,
-                             **self.opts)
+                             value_map=refresh, **self.opts)
         self.Wt = TiledMatrix(DeviceCsr((n, n, self.rpT, self.colT[:self.nnz], self.valT[:self.nnz])),
-                              stream=self.stream, **self.opts)
+                              stream=self.stream, value_map=refresh, **self.opts)
 
     def forward(self, theta: np.ndarray) -> torch.Tensor:
         self._weights(theta)

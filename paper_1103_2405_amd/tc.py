@@ -44,7 +44,7 @@ class CBuildOpts(ctypes.Structure):
     _fields_ = [("tile_width", i32), ("n_tiles", i32), ("wl_policy", i32), ("wl_all", i32),
                 ("wl_per_tile", vp), ("n_wl_per_tile", i32), ("wave", i32), ("split_len", i32),
                 ("camping_pad", i32), ("relabel", i32), ("max_act_warp", i32), ("xcd_groups", i32), ("kernel", i32),
-                ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
+                ("value_map", i32), ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
 
 
 class CInfo(ctypes.Structure):
@@ -85,7 +85,7 @@ EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_inter
             "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
             "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory",
             "tc_rwr_multi", "tc_csr_transpose", "tc_rwr_edge_weights", "tc_rwr_iterates", "tc_rwr_adjoint",
-            "tc_rwr_theta_grad", "tc_gather_rows"]
+            "tc_rwr_theta_grad", "tc_gather_rows", "tc_refresh_values"]
 
 _lib = None
 
@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH):
     f32 = ctypes.c_float
     lib.tc_csr_transpose.argtypes = [P(CCsr), vp, vp, vp, vp, vp]
     lib.tc_gather_rows.argtypes = [vp, i64, vp, i64, i32, vp, vp]
+    lib.tc_refresh_values.argtypes = [vp, vp, vp]
     lib.tc_rwr_edge_weights.argtypes = [i64, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.tc_rwr_iterates.argtypes = [vp, i32, f32, i32, i32, vp, vp, vp]
     lib.tc_rwr_adjoint.argtypes = [vp, vp, vp, vp, i32, f32, i32, i32, vp, vp, vp, vp, vp]
@@ -191,7 +192,7 @@ class TiledMatrix:
     def __init__(self, csr, tile_width: int = 0, n_tiles: int = -1, wl: Optional[Sequence[int] | int] = None,
                  wave: int = 64, split_len: int = -1, camping_pad: bool = False, relabel: int = -1,
                  max_act_warp: int = 0, perf_table: Optional[str] = "default", xcd_groups: int = -1,
-                 kernel: str = "composite", stream=None):
+                 kernel: str = "composite", value_map: bool = False, stream=None):
         lib = load_library()
         A = csr if isinstance(csr, DeviceCsr) else DeviceCsr(csr)
         self.n_rows, self.n_cols, self.nnz = A.n_rows, A.n_cols, A.nnz
@@ -204,6 +205,7 @@ class TiledMatrix:
         if kernel not in ("composite", "coo"):
             raise ValueError("kernel must be 'composite' or 'coo'")
         o.kernel = 1 if kernel == "coo" else 0
+        o.value_map = int(bool(value_map))
         keep = None
         if wl is None:
             o.wl_policy = 0
@@ -277,6 +279,15 @@ class TiledMatrix:
         return arrays
 
     # -- products
+    def refresh_values(self, val: torch.Tensor, stream=None) -> None:
+        """New values (nnz floats, in the order of the CSR entries the handle
+        was built from) for the same pattern; needs value_map=True."""
+        v = val.to(torch.float32).contiguous()
+        if v.numel() != self.nnz or not v.is_cuda:
+            raise ValueError("need nnz float32 values on the GPU")
+        _check(load_library().tc_refresh_values(self.handle, _ptr(v), _stream(stream)), "tc_refresh_values")
+        self._vals = v  # kept alive until the stream has read it
+
     def spmv(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """y := A x (caller's ids)."""
         if y is None:

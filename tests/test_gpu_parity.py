@@ -444,6 +444,31 @@ def test_rwr_multi_tolerance_and_empty():
         rwr_multi(mats[:2], [seeds[0], -1], 0.85, 0.0, 5, 1)
 
 
+@pytest.mark.parametrize("W,split", [(0, -1), (0, 64), (1024, 64)])
+def test_refresh_values_equals_fresh_build(W, split):
+    # a handle built with the value map and then given new values holds
+    # exactly what a build from the new values holds
+    g = gg.rmat(12, 8, seed=31)
+    n, _, rp, col, val = gg.pagerank_matrix(g)
+    val2 = gg.uniform_f32(len(col), 32)
+    tm = TiledMatrix((n, n, rp, col, val), tile_width=W, split_len=split, value_map=True)
+    same = TiledMatrix((n, n, rp, col, val), tile_width=W, split_len=split)
+    fresh = TiledMatrix((n, n, rp, col, val2), tile_width=W, split_len=split)
+    a0, s0 = tm.export_format(), same.export_format()
+    for key in ("idx", "val", "rowid"):
+        assert np.array_equal(a0[key].view(np.uint32), s0[key].view(np.uint32)), key
+    tm.refresh_values(torch.from_numpy(val2).cuda())
+    a, b = tm.export_format(), fresh.export_format()
+    for key in ("idx", "val", "rowid"):
+        assert np.array_equal(a[key].view(np.uint32), b[key].view(np.uint32)), key
+    x = torch.from_numpy(gg.uniform_f32(n, 33)).cuda()
+    assert torch.equal(tm.spmv(x), fresh.spmv(x))
+    with pytest.raises(TcError):
+        fresh.refresh_values(torch.from_numpy(val2).cuda())
+    for m in (tm, same, fresh):
+        m.close()
+
+
 # ------------------------------------------------------------ differentiable RWR
 def test_csr_transpose_bit_exact():
     g = gg.rmat(11, 8, seed=12)
