@@ -312,6 +312,20 @@ struct PrX {
   }
 };
 
+// ... or with the RWR restart of one query fused in (one tile):
+//   r'[row] = fl32(c fl32(s) + (1 - c) [row == seed]),
+// the rounding of the separate update after a stored y.
+struct RwrX {
+  const float* __restrict__ x;
+  double c;
+  int32_t seed;
+  __device__ float operator()(int32_t i) const { return x[i]; }
+  __device__ void addy(float* y, int32_t rid, double s) const {
+    const int32_t row = rid & ~kAddFlag;
+    y[row] = (float)(c * (double)(float)s + (row == seed ? 1.0 - c : 0.0));
+  }
+};
+
 // ... or writing a private copy of y: every row of a tile is written once,
 // so the copy is stored whatever the first-writer flag says.
 struct PrivX {
@@ -368,6 +382,20 @@ __global__ void __launch_bounds__(kB) k_tile_spmv_pr(const Wl* __restrict__ wl, 
   if (j >= n_wl) return;
   const Wl d = wl[j];
   run_workload(d, lane, idx, val, rowid, PrX{x, c, *dmass / (double)n, (1.0 - c) / (double)n}, pn, partial);
+}
+
+// The tile kernel with the fused restart of a one-query RWR (RwrX); the seed
+// is an internal id on the device.
+__global__ void __launch_bounds__(kB) k_tile_spmv_rwr(const Wl* __restrict__ wl, int64_t n_wl,
+                                                      const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                      const int32_t* __restrict__ rowid, const float* __restrict__ x,
+                                                      float* __restrict__ rn, double* __restrict__ partial, double c,
+                                                      const int32_t* __restrict__ seed) {
+  const int lane = lane_id();
+  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (j >= n_wl) return;
+  const Wl d = wl[j];
+  run_workload(d, lane, idx, val, rowid, RwrX{x, c, *seed}, rn, partial);
 }
 
 // Concurrent pass over tiles 1..G of the XCD schedule.  Workgroups are
@@ -887,6 +915,25 @@ __global__ void k_pr_split_empty(const SplitRow* __restrict__ sr, int64_t n_spli
   }
 }
 
+// Fused one-query RWR step, the rows the tile kernel does not write: split
+// rows (their chunks' sums) and, when `empty` is given, rows without entries
+// (y = 0), same formula as RwrX.
+__global__ void k_rwr1_split_empty(const SplitRow* __restrict__ sr, int64_t n_split, const double* __restrict__ partial,
+                                   const int32_t* __restrict__ empty, int64_t n_empty, float* __restrict__ rn,
+                                   double c, const int32_t* __restrict__ seed) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t sd = *seed;
+  if (t < n_split) {
+    const SplitRow s = sr[t];
+    double acc = 0.0;
+    for (int32_t q = 0; q < s.n_slots; ++q) acc += partial[s.slot_begin + q];
+    rn[s.row] = (float)(c * (double)(float)acc + (s.row == sd ? 1.0 - c : 0.0));
+  } else if (empty && t < n_split + n_empty) {
+    const int32_t row = empty[t - n_split];
+    rn[row] = (float)(c * (double)0.0f + (row == sd ? 1.0 - c : 0.0));
+  }
+}
+
 // Dangling mass of p, split over blocks exactly as k_pr_update splits it
 // (same elements per thread, same order), into parts[blockIdx.x]
 __global__ void __launch_bounds__(kB) k_dang_sum(const float* __restrict__ p, int64_t n, int64_t dang_begin,
@@ -1112,6 +1159,7 @@ struct MultiSeg {
   const float* x;
   float* y;
   double* partial;
+  int64_t seed;  // internal id of the graph's restart node (fused RWR step)
 };
 
 // last i in [0, n) with key(i) <= j (keys increasing, key(0) = 0)
@@ -1138,9 +1186,22 @@ struct MultiSegG {
   const TC_GLOBAL float* x;
   TC_GLOBAL float* y;
   TC_GLOBAL double* partial;
+  int64_t seed;
 };
 #undef TC_GLOBAL
 static_assert(sizeof(MultiSegG) == sizeof(MultiSeg), "MultiSegG mirrors MultiSeg");
+
+// the same with the RWR restart of each graph fused into its row writes
+__global__ void __launch_bounds__(kB) k_tile_spmv_multi_rwr(const MultiSeg* __restrict__ segs, int32_t n_segs,
+                                                            int64_t total, double c) {
+  const int lane = lane_id();
+  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (j >= total) return;
+  const int i = __builtin_amdgcn_readfirstlane(last_le(n_segs, j, [&](int m) { return segs[m].begin; }));
+  const MultiSegG s = ((const MultiSegG*)segs)[i];
+  run_workload(s.wl[j - s.begin], lane, (const int32_t*)s.idx, (const float*)s.val, (const int32_t*)s.rowid,
+               RwrX{(const float*)s.x, c, (int32_t)s.seed}, (float*)s.y, (double*)s.partial);
+}
 
 __global__ void __launch_bounds__(kB) k_tile_spmv_multi(const MultiSeg* __restrict__ segs, int32_t n_segs,
                                                         int64_t total) {
@@ -1182,6 +1243,26 @@ __global__ void k_split_combine_multi(const MultiVec* __restrict__ v, int32_t nv
     m.y[s.row] = (float)acc;
   else
     add_to_y(m.y, s.row, acc);
+}
+
+// Fused RWR step of every graph, the rows the tile kernel does not write:
+// split rows (index space [0, s_tot) of spl) and rows without entries
+// ([s_tot, s_tot + e_tot), of emp), same formula as RwrX.
+__global__ void k_rwr_rest_multi(const MultiVec* __restrict__ spl, const MultiVec* __restrict__ emp, int32_t nv,
+                                 int64_t s_tot, int64_t e_tot, double c) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < s_tot) {
+    const MultiVec m = spl[last_le(nv, t, [&](int q) { return spl[q].begin; })];
+    const SplitRow s = m.split[t - m.begin];
+    double acc = 0.0;
+    for (int32_t q = 0; q < s.n_slots; ++q) acc += m.partial[s.slot_begin + q];
+    m.y[s.row] = (float)(c * (double)(float)acc + (s.row == m.seed ? 1.0 - c : 0.0));
+  } else if (t < s_tot + e_tot) {
+    const int64_t u = t - s_tot;
+    const MultiVec m = emp[last_le(nv, u, [&](int q) { return emp[q].begin; })];
+    const int32_t row = m.list[u - m.begin];
+    m.y[row] = (float)(c * (double)0.0f + (row == m.seed ? 1.0 - c : 0.0));
+  }
 }
 
 // RWR step of every graph, r <- c y + (1 - c) e_seed, with the L1 change.
@@ -1998,6 +2079,7 @@ extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k
       // product, into the other buffer (one tile, k > 1); the others run the
       // product and then the update with its per-column change.
       const bool fuse = k > 1 && h->n_tiles == 1 && h->xcd_groups == 0;
+      const bool fuse1 = k == 1 && h->n_tiles == 1 && h->xcd_groups == 0 && h->kernel == 0 && !tile_config().persist;
       const RwrEpi epi{(double)c, dseeds};
       // what the rows without entries hold in each buffer (they change only
       // between 0, for a product, and their restart values)
@@ -2011,6 +2093,23 @@ extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k
         float* Yb = buf[1 - cur];
         if (fuse && !need_res) {
           spmm_internal(h, Rcur, Yb, k, st, held[1 - cur] == kRestart, &epi);
+          held[1 - cur] = kRestart;
+          cur = 1 - cur;
+        } else if (fuse1 && !need_res) {
+          const int64_t b = h->tile_wl_begin[0], e = h->tile_wl_begin[1];
+          if (e > b)
+            launch_tile(h, k_tile_spmv_rwr, dim3(nblk(e - b, kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
+                        (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
+                        (const int32_t*)h->d_rowid, (const float*)Rcur, Yb, h->d_partial, (double)c,
+                        (const int32_t*)dseeds);
+          const int64_t ne = held[1 - cur] == kRestart ? 0 : h->n_empty;
+          if (h->n_split_rows + ne > 0) {
+            hipLaunchKernelGGL(k_rwr1_split_empty, dim3(nblk(h->n_split_rows + ne, kB)), dim3(kB), 0, st,
+                               h->d_split, h->n_split_rows, (const double*)h->d_partial,
+                               ne ? (const int32_t*)h->d_empty : nullptr, ne, Yb, (double)c, (const int32_t*)dseeds);
+            HIPC(hipGetLastError());
+          }
+          h->spmv_calls++;
           held[1 - cur] = kRestart;
           cur = 1 - cur;
         } else {
@@ -2073,10 +2172,19 @@ extern "C" tc_status tc_rwr_multi(tc_handle* const* hs, int32_t n_graphs, const 
       max_tiles = std::max(max_tiles, h->n_tiles);
       nv_total += h->n_rows;
     }
-    // host tables
-    std::vector<std::vector<MultiSeg>> segs(max_tiles);
+    // host tables, two sets: with parity p the iterate of every graph is in
+    // buffer p (R for 0, Y for 1) and the product goes to the other one
+    std::vector<std::vector<MultiSeg>> segs[2];
+    std::vector<std::vector<int32_t>> seg_graph(max_tiles);
+    segs[0].resize(max_tiles);
+    segs[1].resize(max_tiles);
     std::vector<int64_t> seg_total(max_tiles, 0);
-    std::vector<MultiVec> vec(n_graphs), emp(n_graphs), spl(n_graphs);
+    std::vector<MultiVec> vec[2], emp[2], spl[2];
+    for (int q = 0; q < 2; ++q) {
+      vec[q].resize(n_graphs);
+      emp[q].resize(n_graphs);
+      spl[q].resize(n_graphs);
+    }
     std::vector<int32_t> block_graph;
     std::vector<int64_t> block_first, graph_blocks(n_graphs + 1, 0);
     int64_t off = 0, e_tot = 0, s_tot = 0;
@@ -2088,18 +2196,23 @@ extern "C" tc_status tc_rwr_multi(tc_handle* const* hs, int32_t n_graphs, const 
       if (Y) pool_free(Y, st, false);
       throw Err{TC_ENOMEM, "tc_rwr_multi: vector allocation failed"};
     }
+    float* buf[2] = {R, Y};
     for (int32_t g = 0; g < n_graphs; ++g) {
       const tc_handle* h = hs[g];
       for (int t = 0; t < h->n_tiles; ++t) {
         const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];
         if (e == b) continue;
-        segs[t].push_back(MultiSeg{h->d_wl + b, seg_total[t], h->d_idx, h->d_val, h->d_rowid, R + off, Y + off,
-                                   h->d_partial});
+        for (int q = 0; q < 2; ++q)
+          segs[q][t].push_back(MultiSeg{h->d_wl + b, seg_total[t], h->d_idx, h->d_val, h->d_rowid, buf[q] + off,
+                                        buf[1 - q] + off, h->d_partial, -1});
+        seg_graph[t].push_back(g);
         seg_total[t] += e - b;
       }
-      vec[g] = MultiVec{off, h->n_rows, nullptr, nullptr, nullptr, Y + off, R + off, -1};
-      emp[g] = MultiVec{e_tot, h->n_empty, h->d_empty, nullptr, nullptr, Y + off, nullptr, -1};
-      spl[g] = MultiVec{s_tot, h->n_split_rows, nullptr, h->d_split, h->d_partial, Y + off, nullptr, -1};
+      for (int q = 0; q < 2; ++q) {
+        vec[q][g] = MultiVec{off, h->n_rows, nullptr, nullptr, nullptr, buf[1 - q] + off, buf[q] + off, -1};
+        emp[q][g] = MultiVec{e_tot, h->n_empty, h->d_empty, nullptr, nullptr, buf[1 - q] + off, nullptr, -1};
+        spl[q][g] = MultiVec{s_tot, h->n_split_rows, nullptr, h->d_split, h->d_partial, buf[1 - q] + off, nullptr, -1};
+      }
       e_tot += h->n_empty;
       s_tot += h->n_split_rows;
       const int64_t nb = (h->n_rows + (int64_t)kB * kMultiPer - 1) / ((int64_t)kB * kMultiPer);
@@ -2113,10 +2226,16 @@ extern "C" tc_status tc_rwr_multi(tc_handle* const* hs, int32_t n_graphs, const 
     // device tables in one pool block
     size_t bytes = 0;
     auto reserve = [&](size_t n) { const size_t at = bytes; bytes += (n + 255) / 256 * 256; return at; };
-    std::vector<size_t> seg_at(max_tiles);
-    for (int t = 0; t < max_tiles; ++t) seg_at[t] = reserve(sizeof(MultiSeg) * segs[t].size());
-    const size_t vec_at = reserve(sizeof(MultiVec) * n_graphs), emp_at = reserve(sizeof(MultiVec) * n_graphs),
-                 spl_at = reserve(sizeof(MultiVec) * n_graphs), bg_at = reserve(sizeof(int32_t) * block_graph.size()),
+    std::vector<size_t> seg_at[2];
+    size_t vec_at[2], emp_at[2], spl_at[2];
+    for (int q = 0; q < 2; ++q) {
+      seg_at[q].resize(max_tiles);
+      for (int t = 0; t < max_tiles; ++t) seg_at[q][t] = reserve(sizeof(MultiSeg) * segs[q][t].size());
+      vec_at[q] = reserve(sizeof(MultiVec) * n_graphs);
+      emp_at[q] = reserve(sizeof(MultiVec) * n_graphs);
+      spl_at[q] = reserve(sizeof(MultiVec) * n_graphs);
+    }
+    const size_t bg_at = reserve(sizeof(int32_t) * block_graph.size()),
                  bf_at = reserve(sizeof(int64_t) * block_first.size()),
                  gb_at = reserve(sizeof(int64_t) * graph_blocks.size()),
                  parts_at = reserve(sizeof(double) * block_graph.size()),
@@ -2135,7 +2254,6 @@ extern "C" tc_status tc_rwr_multi(tc_handle* const* hs, int32_t n_graphs, const 
     auto up = [&](size_t at, const void* src, size_t n) {
       if (n) HIPC(hipMemcpyAsync(tab + at, src, n, hipMemcpyHostToDevice, st));
     };
-    for (int t = 0; t < max_tiles; ++t) up(seg_at[t], segs[t].data(), sizeof(MultiSeg) * segs[t].size());
     // internal seed ids: seed_int = rowmap[seed] read on the device
     {
       std::vector<const int32_t*> maps(n_graphs);
@@ -2150,80 +2268,123 @@ extern "C" tc_status tc_rwr_multi(tc_handle* const* hs, int32_t n_graphs, const 
         HIPC(hipMemcpyAsync(sint.data(), tab + seeds_at, sizeof(int32_t) * n_graphs, hipMemcpyDeviceToHost, st));
         HIPC(hipStreamSynchronize(st));
       }
-      for (int32_t g = 0; g < n_graphs; ++g) vec[g].seed = sint[g];
+      for (int q = 0; q < 2; ++q) {
+        for (int32_t g = 0; g < n_graphs; ++g) vec[q][g].seed = emp[q][g].seed = spl[q][g].seed = sint[g];
+        for (int t = 0; t < max_tiles; ++t)
+          for (size_t i = 0; i < segs[q][t].size(); ++i) segs[q][t][i].seed = sint[seg_graph[t][i]];
+      }
     }
-    up(vec_at, vec.data(), sizeof(MultiVec) * n_graphs);
-    up(emp_at, emp.data(), sizeof(MultiVec) * n_graphs);
-    up(spl_at, spl.data(), sizeof(MultiVec) * n_graphs);
+    for (int q = 0; q < 2; ++q) {
+      for (int t = 0; t < max_tiles; ++t) up(seg_at[q][t], segs[q][t].data(), sizeof(MultiSeg) * segs[q][t].size());
+      up(vec_at[q], vec[q].data(), sizeof(MultiVec) * n_graphs);
+      up(emp_at[q], emp[q].data(), sizeof(MultiVec) * n_graphs);
+      up(spl_at[q], spl[q].data(), sizeof(MultiVec) * n_graphs);
+    }
     up(bg_at, block_graph.data(), sizeof(int32_t) * block_graph.size());
     up(bf_at, block_first.data(), sizeof(int64_t) * block_first.size());
     up(gb_at, graph_blocks.data(), sizeof(int64_t) * graph_blocks.size());
-    const MultiVec* d_vec = (const MultiVec*)(tab + vec_at);
     double* d_parts = (double*)(tab + parts_at);
     double* d_res = (double*)(tab + res_at);
     const int64_t nblocks = (int64_t)block_graph.size();
 
-    auto iteration = [&](hipStream_t s2) {
+    // Iterations whose L1 change is not read run the restart fused into the
+    // products (every graph one tile), into the other buffer: parity flips.
+    // The others run the products into the other buffer, then the update of
+    // the iterate in place, with its change.
+    const bool fuse = max_tiles <= 1;
+    auto iteration = [&](hipStream_t s2, int par, bool fused) {
+      if (fused) {
+        if (max_tiles == 1 && seg_total[0] > 0) {
+          hipLaunchKernelGGL(k_tile_spmv_multi_rwr, dim3(nblk(seg_total[0], kWpb)), dim3(kB), 0, s2,
+                             (const MultiSeg*)(tab + seg_at[par][0]), (int32_t)segs[par][0].size(), seg_total[0],
+                             (double)c);
+          HIPC(hipGetLastError());
+        }
+        if (s_tot + e_tot > 0) {
+          hipLaunchKernelGGL(k_rwr_rest_multi, dim3(nblk(s_tot + e_tot, kB)), dim3(kB), 0, s2,
+                             (const MultiVec*)(tab + spl_at[par]), (const MultiVec*)(tab + emp_at[par]), n_graphs,
+                             s_tot, e_tot, (double)c);
+          HIPC(hipGetLastError());
+        }
+        return;
+      }
       if (e_tot > 0) {
-        hipLaunchKernelGGL(k_begin_multi, dim3(nblk(e_tot, kB)), dim3(kB), 0, s2, (const MultiVec*)(tab + emp_at),
-                           n_graphs, e_tot);
+        hipLaunchKernelGGL(k_begin_multi, dim3(nblk(e_tot, kB)), dim3(kB), 0, s2,
+                           (const MultiVec*)(tab + emp_at[par]), n_graphs, e_tot);
         HIPC(hipGetLastError());
       }
       for (int t = 0; t < max_tiles; ++t) {
         if (seg_total[t] == 0) continue;
         hipLaunchKernelGGL(k_tile_spmv_multi, dim3(nblk(seg_total[t], kWpb)), dim3(kB), 0, s2,
-                           (const MultiSeg*)(tab + seg_at[t]), (int32_t)segs[t].size(), seg_total[t]);
+                           (const MultiSeg*)(tab + seg_at[par][t]), (int32_t)segs[par][t].size(), seg_total[t]);
         HIPC(hipGetLastError());
       }
       if (s_tot > 0) {
         hipLaunchKernelGGL(k_split_combine_multi, dim3(nblk(s_tot, kB)), dim3(kB), 0, s2,
-                           (const MultiVec*)(tab + spl_at), n_graphs, s_tot);
+                           (const MultiVec*)(tab + spl_at[par]), n_graphs, s_tot);
         HIPC(hipGetLastError());
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_rwr_update_multi, dim3((unsigned)nblocks), dim3(kB), 0, s2, d_vec,
-                           (const int32_t*)(tab + bg_at), (const int64_t*)(tab + bf_at), (double)c, d_parts);
+        hipLaunchKernelGGL(k_rwr_update_multi, dim3((unsigned)nblocks), dim3(kB), 0, s2,
+                           (const MultiVec*)(tab + vec_at[par]), (const int32_t*)(tab + bg_at),
+                           (const int64_t*)(tab + bf_at), (double)c, d_parts);
         HIPC(hipGetLastError());
         hipLaunchKernelGGL(k_multi_resid, dim3(1), dim3(kB), 0, s2, (const int64_t*)(tab + gb_at), n_graphs,
                            (const double*)d_parts, d_res, d_res + n_graphs);
         HIPC(hipGetLastError());
       }
     };
+    // iterations [it0, it0 + n) from parity par; returns the parity after them
+    auto run = [&](hipStream_t s2, int32_t it0, int32_t n, int par) {
+      for (int32_t q = it0; q < it0 + n; ++q) {
+        const bool need_res = q + 1 == max_iter || (tol > 0.0f && (q + 1) % check_every == 0);
+        const bool fused = fuse && !need_res;
+        iteration(s2, par, fused);
+        if (fused) par = 1 - par;
+      }
+      return par;
+    };
 
     int32_t it = 0;
+    int par = 0;
     double r = 0.0;
     bool conv = false;
     if (nv_total > 0) {
-      hipLaunchKernelGGL(k_rwr_init_multi, dim3(nblk(nv_total, kB)), dim3(kB), 0, st, d_vec, n_graphs, nv_total);
+      hipLaunchKernelGGL(k_rwr_init_multi, dim3(nblk(nv_total, kB)), dim3(kB), 0, st,
+                         (const MultiVec*)(tab + vec_at[0]), n_graphs, nv_total);
       HIPC(hipGetLastError());
       const int32_t chunk = tol > 0.0f ? check_every : std::max(max_iter, 1);
-      hipGraphExec_t exec = nullptr;
-      hipGraph_t graph = nullptr;
+      // one captured chunk per starting parity (a chunk of full length starts
+      // at a multiple of chunk, so its fused steps are the same every time)
+      hipGraphExec_t exec[2] = {nullptr, nullptr};
+      hipGraph_t graph[2] = {nullptr, nullptr};
+      int par_after[2] = {0, 1};
       hipStream_t cap = nullptr;
       struct GraphRelease {
         hipGraphExec_t* e; hipGraph_t* g; hipStream_t* s;
         ~GraphRelease() {
-          if (*e) (void)hipGraphExecDestroy(*e);
-          if (*g) (void)hipGraphDestroy(*g);
+          for (int q = 0; q < 2; ++q) {
+            if (e[q]) (void)hipGraphExecDestroy(e[q]);
+            if (g[q]) (void)hipGraphDestroy(g[q]);
+          }
           if (*s) (void)hipStreamDestroy(*s);
         }
-      } grel{&exec, &graph, &cap};
-      int32_t cap_iters = 0;
-      if ((flags & 1) && max_iter > 0) {
-        // capture `chunk` iterations once (kernels only) and replay the graph
-        cap_iters = std::min(chunk, max_iter);
-        HIPC(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        HIPC(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-        for (int32_t q = 0; q < cap_iters; ++q) iteration(cap);
-        HIPC(hipStreamEndCapture(cap, &graph));
-        HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-      }
+      } grel{exec, graph, &cap};
+      const bool use_graph = (flags & 1) && max_iter > 0;
       while (it < max_iter) {
         const int32_t step = std::min(chunk, max_iter - it);
-        if (exec && step == cap_iters) {
-          HIPC(hipGraphLaunch(exec, st));
+        if (use_graph && step == chunk) {
+          if (!exec[par]) {
+            if (!cap) HIPC(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            HIPC(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            par_after[par] = run(cap, it, step, par);
+            HIPC(hipStreamEndCapture(cap, &graph[par]));
+            HIPC(hipGraphInstantiate(&exec[par], graph[par], nullptr, nullptr, 0));
+          }
+          HIPC(hipGraphLaunch(exec[par], st));
+          par = par_after[par];
         } else {
-          for (int32_t q = 0; q < step; ++q) iteration(st);
+          par = run(st, it, step, par);
         }
         it += step;
         if (tol > 0.0f) {
@@ -2237,7 +2398,7 @@ extern "C" tc_status tc_rwr_multi(tc_handle* const* hs, int32_t n_graphs, const 
       if (it > 0) r = read_f64(d_res + n_graphs, st);
       off = 0;
       for (int32_t g = 0; g < n_graphs; ++g) {
-        gather_rows(R + off, hs[g]->d_rowmap, hs[g]->n_rows, 1, R_out[g], st);
+        gather_rows(buf[par] + off, hs[g]->d_rowmap, hs[g]->n_rows, 1, R_out[g], st);
         off += hs[g]->n_rows;
       }
       if (resid && n_graphs > 0) HIPC(hipMemcpyAsync(resid, d_res, sizeof(double) * n_graphs, hipMemcpyDeviceToHost, st));

@@ -383,7 +383,7 @@ def test_rwr_fused_restart_equals_separate_update(split):
     seeds = [int(v) for v in gg.rwr_seeds(g, 7, 3)] + [int(empty[0])]
     gm = TiledMatrix(csr, split_len=split)
     assert gm.info()["n_tiles"] == 1
-    for k in (8, 3):
+    for k in (8, 3, 1):  # 4-wide SpMM, 1-wide SpMM, the single-vector tile kernel
         a, it, ra = gm.rwr(seeds[-k:], 0.85, 1e-7, 500, 1)
         b, it2, rb = gm.rwr(seeds[-k:], 0.85, 0.0, it)
         assert it2 == it and ra == rb
@@ -393,13 +393,14 @@ def test_rwr_fused_restart_equals_separate_update(split):
 
 
 # ------------------------------------------------------------ several graphs per launch
-def _multi_set():
+def _multi_set(one_tile=False):
     mats, csrs, seeds = [], [], []
     for gi in range(6):
         g = gg.rmat(8 + gi % 4, 4 + 3 * gi, seed=700 + gi)
         csr = gg.rwr_matrix(g)
-        # mixed formats: several tiles, split rows, one tile
-        W = 128 if gi % 2 else 0
+        # mixed formats: several tiles, split rows, one tile (all one tile:
+        # the restart is fused into the products)
+        W = 128 if gi % 2 and not one_tile else 0
         split = 64 if gi % 3 == 0 else -1
         mats.append(TiledMatrix(csr, tile_width=W, split_len=split))
         csrs.append(csr)
@@ -407,9 +408,10 @@ def _multi_set():
     return mats, csrs, seeds
 
 
-def test_rwr_multi_matches_oracle_and_single_graph_driver():
+@pytest.mark.parametrize("one_tile", [False, True])
+def test_rwr_multi_matches_oracle_and_single_graph_driver(one_tile):
     from paper_1103_2405_amd import rwr_multi
-    mats, csrs, seeds = _multi_set()
+    mats, csrs, seeds = _multi_set(one_tile)
     eager, it, res = rwr_multi(mats, seeds, 0.85, 0.0, 30, 1, graph=False)
     assert it == 30
     for m, csr, s, r in zip(mats, csrs, seeds, eager):
@@ -430,12 +432,21 @@ def test_rwr_multi_matches_oracle_and_single_graph_driver():
         _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
 
 
-def test_rwr_multi_tolerance_and_empty():
+@pytest.mark.parametrize("one_tile,every", [(False, 5), (True, 5), (True, 4), (True, 1)])
+def test_rwr_multi_tolerance_and_empty(one_tile, every):
+    # with one tile per graph, a captured chunk of `every` iterations holds
+    # every - 1 fused steps: an odd count flips the buffers, so replays
+    # alternate between the two captured graphs
     from paper_1103_2405_amd import rwr_multi
-    mats, csrs, seeds = _multi_set()
-    out, it, res = rwr_multi(mats, seeds, 0.85, 1e-6, 500, 5, graph=True)
-    assert it % 5 == 0 and res.max() <= 1e-6
-    for csr, s, r in zip(csrs, seeds, out):
+    mats, csrs, seeds = _multi_set(one_tile)
+    out, it, res = rwr_multi(mats, seeds, 0.85, 1e-6, 500, every, graph=True)
+    assert it % every == 0 and res.max() <= 1e-6
+    eager, it2, res2 = rwr_multi(mats, seeds, 0.85, 1e-6, 500, every, graph=False)
+    assert it2 == it and np.array_equal(res, res2)
+    for m, csr, s, r, e in zip(mats, csrs, seeds, out, eager):
+        assert torch.equal(r, e)
+        one, _, _ = m.rwr([s], 0.85, 0.0, it)
+        assert torch.equal(one[:, 0], r)
         ref, _, _ = oracle.rwr(csr, [s], 0.85, 0.0, it)
         assert np.abs(r.cpu().numpy() - ref[:, 0]).sum() <= 1e-6
     out, it, res = rwr_multi([], [], 0.85, 0.0, 30, 1)
