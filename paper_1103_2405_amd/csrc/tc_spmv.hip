@@ -451,6 +451,22 @@ __global__ void __launch_bounds__(kPB) k_tile_persist(const Wl* __restrict__ wl,
   }
 }
 
+// p[0] + p[s] + ... + p[(n-1) s], added in that order; eight loads go out
+// together (a split row can have dozens of chunks, summed by one thread)
+__device__ inline double sum_slots(const double* __restrict__ p, int64_t n, int64_t s = 1) {
+  double acc = 0.0;
+  int64_t q = 0;
+  for (; q + 8 <= n; q += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[(q + u) * s];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += t[u];
+  }
+  for (; q < n; ++q) acc += p[q * s];
+  return acc;
+}
+
 // Sum of every split row's chunks in (tile, chunk) order, added to y (or
 // stored when no tile wrote the row).
 __global__ void k_split_combine(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
@@ -458,8 +474,7 @@ __global__ void k_split_combine(const SplitRow* __restrict__ sr, int64_t n, cons
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const SplitRow s = sr[i];
-  double acc = 0.0;
-  for (int32_t q = 0; q < s.n_slots; ++q) acc += partial[s.slot_begin + q];
+  const double acc = sum_slots(partial + s.slot_begin, s.n_slots);
   if (s.store && !force_add)
     y[s.row] = (float)acc;
   else
@@ -751,9 +766,8 @@ __global__ void k_split_combine_mm(const SplitRow* __restrict__ sr, int64_t n, c
   const int64_t i = t / k;
   const int32_t q = (int32_t)(t % k);
   const SplitRow s = sr[i];
-  double acc = 0.0;
-  for (int64_t u = (int64_t)s.slot_begin * pieces; u < (int64_t)(s.slot_begin + s.n_slots) * pieces; ++u)
-    acc += partial[u * k + q];
+  const int64_t u0 = (int64_t)s.slot_begin * pieces;
+  const double acc = sum_slots(partial + u0 * k + q, (int64_t)s.n_slots * pieces, k);
   if (epi.seeds)  // fused restart (one tile: the chunks are all of the row)
     Y[(int64_t)s.row * k + q] = rwr_restart(epi.c, (float)acc, s.row == epi.seeds[q]);
   else if (s.store)
@@ -907,8 +921,7 @@ __global__ void k_pr_split_empty(const SplitRow* __restrict__ sr, int64_t n_spli
   const double dn = *dmass / (double)n, tele = (1.0 - c) / (double)n;
   if (t < n_split) {
     const SplitRow s = sr[t];
-    double acc = 0.0;
-    for (int32_t q = 0; q < s.n_slots; ++q) acc += partial[s.slot_begin + q];
+    const double acc = sum_slots(partial + s.slot_begin, s.n_slots);
     pn[s.row] = (float)(c * ((double)(float)acc + dn) + tele);
   } else if (t < n_split + n_empty) {
     pn[empty[t - n_split]] = (float)(c * ((double)0.0f + dn) + tele);
@@ -925,8 +938,7 @@ __global__ void k_rwr1_split_empty(const SplitRow* __restrict__ sr, int64_t n_sp
   const int32_t sd = *seed;
   if (t < n_split) {
     const SplitRow s = sr[t];
-    double acc = 0.0;
-    for (int32_t q = 0; q < s.n_slots; ++q) acc += partial[s.slot_begin + q];
+    const double acc = sum_slots(partial + s.slot_begin, s.n_slots);
     rn[s.row] = (float)(c * (double)(float)acc + (s.row == sd ? 1.0 - c : 0.0));
   } else if (empty && t < n_split + n_empty) {
     const int32_t row = empty[t - n_split];
@@ -1237,8 +1249,7 @@ __global__ void k_split_combine_multi(const MultiVec* __restrict__ v, int32_t nv
   if (t >= total) return;
   const MultiVec m = v[last_le(nv, t, [&](int q) { return v[q].begin; })];
   const SplitRow s = m.split[t - m.begin];
-  double acc = 0.0;
-  for (int32_t q = 0; q < s.n_slots; ++q) acc += m.partial[s.slot_begin + q];
+  const double acc = sum_slots(m.partial + s.slot_begin, s.n_slots);
   if (s.store)
     m.y[s.row] = (float)acc;
   else
@@ -1254,8 +1265,7 @@ __global__ void k_rwr_rest_multi(const MultiVec* __restrict__ spl, const MultiVe
   if (t < s_tot) {
     const MultiVec m = spl[last_le(nv, t, [&](int q) { return spl[q].begin; })];
     const SplitRow s = m.split[t - m.begin];
-    double acc = 0.0;
-    for (int32_t q = 0; q < s.n_slots; ++q) acc += m.partial[s.slot_begin + q];
+    const double acc = sum_slots(m.partial + s.slot_begin, s.n_slots);
     m.y[s.row] = (float)(c * (double)(float)acc + (s.row == m.seed ? 1.0 - c : 0.0));
   } else if (t < s_tot + e_tot) {
     const int64_t u = t - s_tot;
