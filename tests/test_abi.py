@@ -71,3 +71,28 @@ def test_struct_layouts_match_the_binding(tmp_path):
         assert int(got["%s size" % cname]) == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_invalid_options_rejected_without_gpu_work():
+    # option checks come before any device work (the CSR pointers are never
+    # read here, so placeholders do)
+    import ctypes
+    from paper_1103_2405_amd import tc
+    lib = tc.load_library()
+    fake = 0x1000
+    A = tc.CCsr(10, 10, 5, fake, fake, fake)
+    h = ctypes.c_void_p()
+    for field, value in [("value_map", 2), ("kernel", 2), ("split_len", -2), ("xcd_groups", 65), ("wl_policy", 3)]:
+        o = tc.CBuildOpts()
+        lib.tc_build_opts_default(ctypes.byref(o))
+        setattr(o, field, value)
+        assert lib.tc_build_tiled(ctypes.byref(A), ctypes.byref(o), None, ctypes.byref(h)) == tc.TC_EINVAL, field
+        assert not h.value
+    o = tc.CBuildOpts()
+    lib.tc_build_opts_default(ctypes.byref(o))
+    o.value_map, o.kernel = 1, 1  # the value map serves the composite kernel only
+    assert lib.tc_build_tiled(ctypes.byref(A), ctypes.byref(o), None, ctypes.byref(h)) == tc.TC_EINVAL
+    assert lib.tc_refresh_values(None, None, None) == tc.TC_EINVAL
+    assert lib.tc_gather_rows(None, 0, None, -1, 1, None, None) == tc.TC_EINVAL
+    assert lib.tc_gather_rows(None, 0, None, 5, 0, None, None) == tc.TC_EINVAL
