@@ -1064,10 +1064,17 @@ __global__ void __launch_bounds__(kB) k_tile_coo(const int32_t* __restrict__ cro
   const int cnt = lane <= last ? (int)min<int64_t>(kCooPer, e - s0) : 0;
   int32_t rr[kCooPer];
   double pp[kCooPer];
+  // every load on every lane (past the lane's entries: its last one, or the
+  // interval's first), so the loads and gathers go out together
+  const int64_t qlast = cnt > 0 ? s0 + cnt - 1 : b;
 #pragma unroll
   for (int j = 0; j < kCooPer; ++j) {
-    rr[j] = j < cnt ? crow[s0 + j] : 0;
-    pp[j] = j < cnt ? (double)cval[s0 + j] * (double)x[ccol[s0 + j]] : 0.0;
+    const int64_t q = min(s0 + j, qlast);
+    const int32_t rv = crow[q];
+    const float vv = cval[q];
+    const float xv = x[ccol[q]];
+    rr[j] = j < cnt ? rv : 0;
+    pp[j] = j < cnt ? (double)vv * (double)xv : 0.0;
   }
   // lane pass
   const int32_t first = rr[0];
