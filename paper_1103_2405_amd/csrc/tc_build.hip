@@ -838,8 +838,12 @@ void col_count_bucketed(const int32_t* col, int64_t nnz, int64_t n_cols, int csh
                      nb, chunk, nchunks, hist);
   HIPX(hipGetLastError());
   excl_scan<int32_t, int64_t>(hist, (int64_t)nb * nchunks, offs, tmp, st);
-  hipLaunchKernelGGL((k_cs_scatter<ColBucketOp>), dim3(grid), dim3(kCsBlock), kCsWaves * nb * sizeof(int64_t), st, op,
-                     nnz, nb, nbits, chunk, nchunks, (const int64_t*)offs);
+  // staged in LDS, so each bucket's run of a chunk is written coalesced
+  const size_t stage = (size_t)kCsWaves * (chunk * sizeof(ColBucketOp::Item) + 16 * (size_t)nb);
+  HIPX(hipFuncSetAttribute((const void*)k_cs_scatter_staged<ColBucketOp>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)stage));
+  hipLaunchKernelGGL((k_cs_scatter_staged<ColBucketOp>), dim3(grid), dim3(kCsBlock), stage, st, op, nnz, nb, nbits,
+                     chunk, nchunks, (const int64_t*)offs, (const int32_t*)hist);
   HIPX(hipGetLastError());
   // bucket starts: offs[b * nchunks]
   int64_t* d_bs = tmp.get<int64_t>(nb);

@@ -191,4 +191,82 @@ __global__ void __launch_bounds__(kCsBlock) k_cs_scatter(Op op, int64_t n, int32
   }
 }
 
+// The same pass with each chunk staged in LDS: the items are first placed in
+// chunk-local bucket order, then every bucket's run of the chunk goes out with
+// consecutive lanes, so the stores are coalesced instead of touching a line
+// per lane.  Positions (and so the result) are those of k_cs_scatter.  hist
+// holds the (bucket, chunk) counts; nbuckets must be a multiple of 64.
+// Dynamic LDS per block: kCsWaves * (chunk * sizeof(Item) + 16 * nbuckets).
+template <class Op>
+__global__ void __launch_bounds__(kCsBlock) k_cs_scatter_staged(Op op, int64_t n, int32_t nbuckets, int32_t nbits,
+                                                                int64_t chunk, int64_t nchunks,
+                                                                const int64_t* __restrict__ offs,
+                                                                const int32_t* __restrict__ hist) {
+  using Item = typename Op::Item;
+  extern __shared__ int64_t cs_stage[];
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  const int64_t c = (int64_t)blockIdx.x * kCsWaves + wv;
+  if (c >= nchunks) return;  // whole wavefront leaves; no block barrier below
+  char* base = (char*)cs_stage + (size_t)wv * (chunk * sizeof(Item) + 16 * (size_t)nbuckets);
+  Item* li = (Item*)base;
+  int64_t* gst = (int64_t*)(base + chunk * sizeof(Item));  // bucket's first global slot for this chunk
+  int32_t* lst = (int32_t*)(gst + nbuckets);                 // bucket's first local slot
+  int32_t* lrun = lst + nbuckets;                            // next local slot
+  // local starts: exclusive scan of this chunk's counts (lane l: buckets l*per ...)
+  const int per = nbuckets / kWave;
+  int32_t mine = 0;
+  for (int q = 0; q < per; ++q) mine += hist[(int64_t)(lane * per + q) * nchunks + c];
+  int32_t incl = mine;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  int32_t acc = incl - mine;
+  for (int q = 0; q < per; ++q) {
+    const int b = lane * per + q;
+    lst[b] = acc;
+    lrun[b] = acc;
+    gst[b] = offs[(int64_t)b * nchunks + c];
+    acc += hist[(int64_t)b * nchunks + c];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int64_t first = c * chunk, end = min(n, (c + 1) * chunk);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t base0 = first; base0 < end; base0 += 4 * kWave) {
+    Item it[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = base0 + u * kWave + lane;
+      it[u] = op.load(k < end ? k : first);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = base0 + u * kWave + lane;
+      const bool valid = k < end;
+      const uint32_t b = op.bucket_of(it[u]);
+      uint64_t peers = __ballot(valid);
+      for (int bit = 0; bit < nbits; ++bit) {
+        const bool set = (b >> bit) & 1u;
+        const uint64_t bal = __ballot(set);
+        peers &= set ? bal : ~bal;
+      }
+      const int32_t pos = valid ? lrun[b] + (int32_t)__popcll(peers & lt) : 0;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (valid) li[pos] = it[u];
+      if (valid && (peers >> lane) == 1ull) lrun[b] += (int32_t)__popcll(peers);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+  }
+  // out in local order: a bucket's run is consecutive lanes and slots
+  const int32_t cl = (int32_t)(end - first);
+  for (int32_t i = lane; i < cl; i += kWave) {
+    const Item v = li[i];
+    const uint32_t b = op.bucket_of(v);
+    op.store(gst[b] + (i - lst[b]), v);
+  }
+}
+
 }  // namespace tc
