@@ -94,7 +94,7 @@ def cpu_baseline(csr, budget_s: float):
             "cpu_model": model}
 
 
-def rwr_batched(c: float = 0.85, tol: float = 1e-6, ks=(1, 8, 32, 64)):
+def rwr_batched(c: float = 0.85, tol: float = 1e-6, ks=(1, 8, 32, 64, 128)):
     """Batched RWR (multi-RHS SpMM) on the symmetrised R-MAT scale-20 graph:
     queries/s for k one-hot restart vectors solved together to an L1 change of
     tol, against k = 32 sequential single-query solves with (a) PyTorch's

@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(kB) k_tile_spmm(const Wl* __restrict__ wl, int
   const int32_t sl = (int32_t)(w % slices);
   const int groups = kWave / kg;
   const int g = lane / kg;
-  const int32_t col = ((int32_t)blockIdx.y * kWave + lane % kg) * V;
+  const int32_t col = ((int32_t)blockIdx.y * kg + lane % kg) * V;
   const bool act = col < k;
   const Wl d = wl[j];
   const int layout = d.info & 3;
@@ -733,7 +733,7 @@ __global__ void __launch_bounds__(kB) k_spmm_chunks(const Wl* __restrict__ wl, i
   const int32_t p = (int32_t)(w % pieces);
   const int groups = kWave / kg;
   const int g = lane / kg;
-  const int32_t col = ((int32_t)blockIdx.y * kWave + lane % kg) * V;
+  const int32_t col = ((int32_t)blockIdx.y * kg + lane % kg) * V;
   const bool act = col < k;
   const Wl d = wl[j];
   const int64_t lo = min<int64_t>((int64_t)p * kPiece, d.w_pad), hi = min<int64_t>(lo + kPiece, d.w_pad);
@@ -1747,11 +1747,16 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
   const bool v4 = k % 4 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)Y % 16) == 0;
   const int32_t V = v4 ? 4 : 1;
   const int32_t kq = (k + V - 1) / V;
+  // one pass (grid row) covers at most 32 right-hand sides: 128 bytes of each
+  // X row, one cache line per gather. Wider passes spread the gathers over
+  // n * 4k bytes, past the 256 MB MALL at a million rows and k = 64 (measured
+  // on a 31M-entry power-law matrix, 1M rows: k = 64 1262 -> 1152 us, k = 128
+  // 2718 -> 2244 us per product; 16 per pass slows k = 32 by 40%)
   int32_t kg = 1;
-  while (kg < kq && kg < kWave) kg <<= 1;
+  while (kg < kq && kg < 32 / V) kg <<= 1;
   spmm_plan(h);
   const int32_t pieces = h->mm_pieces;
-  const int kchunks = (kq + kWave - 1) / kWave;
+  const int kchunks = (kq + kg - 1) / kg;
   // 4-wide lanes: four rows per sub-step group (fewer registers, more
   // wavefronts resident) and each workload cut into four row slices
   // (measured on a 31M-entry power-law matrix at k = 32: 25% over one slice,

@@ -362,8 +362,8 @@ def test_rwr_matches_oracle(W):
     g = gg.rmat(12, 16, seed=8)
     csr = gg.rwr_matrix(g)
     gm = TiledMatrix(csr, tile_width=W)
-    seeds = gg.rwr_seeds(g, 32, 40)
-    for k in (1, 5, 32):
+    seeds = gg.rwr_seeds(g, 40, 40)
+    for k in (1, 5, 32, 37, 40):  # 37, 40: right-hand sides in two passes
         R, it, res = gm.rwr(seeds[:k], 0.85, 0.0, 30)
         Rref, _, rr = oracle.rwr(csr, seeds[:k], 0.85, 0.0, 30)
         d = np.abs(R.cpu().numpy() - Rref).sum(axis=0)
@@ -380,10 +380,11 @@ def test_rwr_fused_restart_equals_separate_update(split):
     csr = gg.rwr_matrix(g)
     empty = np.flatnonzero(np.diff(csr[2]) == 0)
     assert empty.size > 0
-    seeds = [int(v) for v in gg.rwr_seeds(g, 7, 3)] + [int(empty[0])]
+    seeds = [int(v) for v in gg.rwr_seeds(g, 39, 3)] + [int(empty[0])]
     gm = TiledMatrix(csr, split_len=split)
     assert gm.info()["n_tiles"] == 1
-    for k in (8, 3, 1):  # 4-wide SpMM, 1-wide SpMM, the single-vector tile kernel
+    # 4-wide SpMM (40: two passes), 1-wide SpMM, the single-vector tile kernel
+    for k in (40, 8, 3, 1):
         a, it, ra = gm.rwr(seeds[-k:], 0.85, 1e-7, 500, 1)
         b, it2, rb = gm.rwr(seeds[-k:], 0.85, 0.0, it)
         assert it2 == it and ra == rb
