@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output as short text files for profiles/.
 
-Two kinds:
+Three kinds:
 
 * ``stats``: the kernel-trace statistics (rocprofv3 --kernel-trace --stats) of
   one run, the kernels sorted by total time, with calls and mean duration.
@@ -11,10 +11,13 @@ Two kinds:
   so the figures are bytes that really crossed the L2/fabric boundary.  The
   file records a hash of the library sources; bench.py reports the traffic
   only while the kernels are unchanged.
+* ``pmc``: the mean per dispatch of every counter collected for one kernel in
+  one or more counter runs (cache hits and misses, requests to the fabric).
 
     python -m paper_1103_2405_amd.profsum stats RUN_DIR --cmd "..." --out FILE
     python -m paper_1103_2405_amd.profsum counters FETCH_DIR WRITE_DIR --kernel REGEX \\
         --copy-bytes N --cmd "..." --out FILE
+    python -m paper_1103_2405_amd.profsum pmc RUN_DIR [RUN_DIR ...] --kernel REGEX --cmd "..." --out FILE
 """
 from __future__ import annotations
 
@@ -109,6 +112,27 @@ def summarize_counters(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: 
     return "\n".join(lines) + "\n"
 
 
+def summarize_pmc(run_dirs, kernel: str, cmd: str) -> str:
+    rx = re.compile(kernel)
+    means, n_disp = {}, {}
+    for d in run_dirs:
+        for r in csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))):
+            if not rx.search(r["Kernel_Name"]):
+                continue
+            c = r["Counter_Name"]
+            means[c] = means.get(c, 0.0) + float(r["Counter_Value"])
+            n_disp[c] = n_disp.get(c, 0) + 1
+    if not means:
+        raise SystemExit("kernel %r not found in the counter runs" % kernel)
+    lines = ["# rocprofv3 counters of one kernel, mean per dispatch",
+             "# command: " + cmd,
+             "kernel: " + kernel,
+             "source_sha256: " + source_hash()]
+    for c in sorted(means):
+        lines.append("%s: %.1f  (%d dispatches)" % (c, means[c] / n_disp[c], n_disp[c]))
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic(path: str):
     """traffic_bytes_per_launch from a counters summary, or None when the file
     is missing or the library sources changed since it was taken."""
@@ -142,9 +166,18 @@ def main(argv=None):
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
+    m = sub.add_parser("pmc")
+    m.add_argument("run_dirs", nargs="+")
+    m.add_argument("--kernel", required=True)
+    m.add_argument("--cmd", required=True)
+    m.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    text = (summarize_stats(a.run_dir, a.cmd) if a.what == "stats"
-            else summarize_counters(a.fetch_dir, a.write_dir, a.kernel, a.copy_bytes, a.cmd))
+    if a.what == "stats":
+        text = summarize_stats(a.run_dir, a.cmd)
+    elif a.what == "counters":
+        text = summarize_counters(a.fetch_dir, a.write_dir, a.kernel, a.copy_bytes, a.cmd)
+    else:
+        text = summarize_pmc(a.run_dirs, a.kernel, a.cmd)
     with open(a.out, "w") as f:
         f.write(text)
     print(text, end="")
