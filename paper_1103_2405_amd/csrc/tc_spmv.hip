@@ -94,11 +94,11 @@ __device__ inline double dot4(v4i i, v4f v, const G& xg) {
 //   w_pad = 128: a chunk holds 2 rows, 32 lanes each
 //   otherwise:   one row at a time, chunks of 256 (last one masked)
 // Two chunks are in flight per iteration (8 gathers per lane).
-template <class G>
+template <int S, class G>
 __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict__ idx,
                                const float* __restrict__ val, const int32_t* __restrict__ rowid,
                                const G& x, float* __restrict__ y, double* __restrict__ partial,
-                               bool chunk) {
+                               bool chunk, int32_t sl) {
   const int64_t off = d.data_off;
   const int32_t wp = d.w_pad, nr = d.n_rows;
   if (wp == 64 || wp == 128) {
@@ -106,7 +106,7 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
     const int rpc = kWave / lpr;         // rows per chunk
     const int my = lane / lpr;           // my row inside the chunk
     const int nchunk = (nr + rpc - 1) / rpc;
-    for (int q = 0; q < nchunk; q += 2) {
+    for (int q = 2 * sl; q < nchunk; q += 2 * S) {
       const int ra = q * rpc + my, rb = (q + 1) * rpc + my;
       const bool oka = ra < nr, okb = rb < nr;
       double sa = 0.0, sb = 0.0;
@@ -140,7 +140,7 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
     }
     return;
   }
-  for (int32_t r = 0; r < nr; ++r) {
+  for (int32_t r = sl; r < nr; r += S) {
     const int64_t base = off + (int64_t)r * wp;
     double acc = 0.0;
     int32_t c = 4 * lane;
@@ -166,19 +166,20 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
 // entry and takes index 0 and value 0 instead (its sum is never stored).  A
 // load under a per-lane branch would end its branch with a wait for it, so
 // the loads would go out one at a time.
-template <int U, int C, class G>
+template <int U, int C, int S, class G>
 __device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict__ idx,
                                const float* __restrict__ val, const int32_t* __restrict__ rowid,
-                               const G& x, float* __restrict__ y) {
+                               const G& x, float* __restrict__ y, int32_t sl) {
   const int64_t off = d.data_off, hp = d.h_pad;
   const int32_t w = d.w_pad, nr = d.n_rows;
-  for (int32_t r0 = 0; r0 < nr; r0 += U * kWave) {
+  // slice sl of S takes the 64-row blocks sl, sl + S, ..., U of them at a time
+  for (int32_t r0 = sl * kWave; r0 < nr; r0 += U * S * kWave) {
     double acc[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       acc[u] = 0.0;
-      ok[u] = r0 + u * kWave + lane < nr;
+      ok[u] = r0 + u * S * kWave + lane < nr;
     }
     int32_t c = 0;
     for (; c + C <= w; c += C) {
@@ -188,7 +189,7 @@ __device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict_
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-          const int64_t e = ok[u] ? off + (int64_t)(c + k) * hp + r0 + u * kWave + lane : off;
+          const int64_t e = ok[u] ? off + (int64_t)(c + k) * hp + r0 + u * S * kWave + lane : off;
           const int32_t ti = ld_nt(idx + e);
           const float tv = ld_nt(val + e);
           ii[u][k] = ok[u] ? ti : 0;
@@ -208,7 +209,7 @@ __device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict_
       float vv[U], xv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t e = ok[u] ? off + (int64_t)c * hp + r0 + u * kWave + lane : off;
+        const int64_t e = ok[u] ? off + (int64_t)c * hp + r0 + u * S * kWave + lane : off;
         const int32_t ti = ld_nt(idx + e);
         const float tv = ld_nt(val + e);
         ii[u] = ok[u] ? ti : 0;
@@ -221,18 +222,19 @@ __device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict_
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (ok[u]) x.addy(y, ld_nt(rowid + d.rowid_off + r0 + u * kWave + lane), acc[u]);
+      if (ok[u]) x.addy(y, ld_nt(rowid + d.rowid_off + r0 + u * S * kWave + lane), acc[u]);
   }
 }
 
 // Any layout, any padding (used when the rectangle is not 64-aligned).
-template <class G>
+template <int S, class G>
 __device__ inline void generic_wl(const Wl& d, int lane, int layout, const int32_t* __restrict__ idx,
                                   const float* __restrict__ val, const int32_t* __restrict__ rowid,
-                                  const G& x, float* __restrict__ y, double* __restrict__ partial) {
+                                  const G& x, float* __restrict__ y, double* __restrict__ partial,
+                                  int32_t sl) {
   if (layout == kCM) {
     const int64_t hp = d.h_pad;
-    for (int32_t r = lane; r < d.n_rows; r += kWave) {
+    for (int32_t r = sl * kWave + lane; r < d.n_rows; r += kWave * S) {
       double acc = 0.0;
       for (int32_t c = 0; c < d.w_pad; ++c) {
         const int64_t e = d.data_off + (int64_t)c * hp + r;
@@ -243,7 +245,7 @@ __device__ inline void generic_wl(const Wl& d, int lane, int layout, const int32
     return;
   }
   const int64_t wp = d.w_pad;
-  for (int32_t r = 0; r < d.n_rows; ++r) {
+  for (int32_t r = sl; r < d.n_rows; r += S) {
     const int64_t base = d.data_off + r * wp;
     double acc = 0.0;
     for (int64_t c = lane; c < wp; c += kWave) acc = fma((double)val[base + c], (double)x(idx[base + c]), acc);
@@ -334,68 +336,72 @@ struct PrivX {
   __device__ void addy(float* y, int32_t rid, double s) const { y[rid & ~kAddFlag] = (float)s; }
 };
 
-template <class G>
+template <int S = 1, class G>
 __device__ __attribute__((always_inline)) inline void run_workload(const Wl& d, int lane, const int32_t* __restrict__ idx,
                                     const float* __restrict__ val, const int32_t* __restrict__ rowid, const G& x,
-                                    float* __restrict__ y, double* __restrict__ partial) {
+                                    float* __restrict__ y, double* __restrict__ partial, int32_t sl = 0) {
   const int layout = d.info & 3;
   const bool aligned = (d.data_off & 3) == 0;
   if (layout == kCM && (d.h_pad & 63) == 0) {
-    const int32_t blocks = (d.n_rows + kWave - 1) / kWave;
+    // row blocks of this slice
+    const int32_t blocks = ((d.n_rows + kWave - 1) / kWave - sl + S - 1) / S;
     if (blocks >= 8)
-      cm_rows<8, 1>(d, lane, idx, val, rowid, x, y);
+      cm_rows<8, 1, S>(d, lane, idx, val, rowid, x, y, sl);
     else if (blocks >= 4)
-      cm_rows<4, 2>(d, lane, idx, val, rowid, x, y);
+      cm_rows<4, 2, S>(d, lane, idx, val, rowid, x, y, sl);
     else if (blocks >= 2)
-      cm_rows<2, 4>(d, lane, idx, val, rowid, x, y);
+      cm_rows<2, 4, S>(d, lane, idx, val, rowid, x, y, sl);
     else
-      cm_rows<1, 8>(d, lane, idx, val, rowid, x, y);
+      cm_rows<1, 8, S>(d, lane, idx, val, rowid, x, y, sl);
   } else if (layout != kCM && aligned && (d.w_pad & 63) == 0) {
-    rm_wide(d, lane, idx, val, rowid, x, y, partial, layout == kChunk);
+    rm_wide<S>(d, lane, idx, val, rowid, x, y, partial, layout == kChunk, sl);
   } else {
-    generic_wl(d, lane, layout, idx, val, rowid, x, y, partial);
+    generic_wl<S>(d, lane, layout, idx, val, rowid, x, y, partial, sl);
   }
 }
 
-// One wavefront per workload of the tile (grid = workloads / 4).
-template <bool YNT>
+// S wavefronts per workload of the tile (row slices; grid = workloads * S / 4).
+template <bool YNT, int S>
 __global__ void __launch_bounds__(kB) k_tile_spmv(const Wl* __restrict__ wl, int64_t n_wl,
                                                   const int32_t* __restrict__ idx, const float* __restrict__ val,
                                                   const int32_t* __restrict__ rowid, const float* __restrict__ x,
                                                   float* __restrict__ y, double* __restrict__ partial) {
   const int lane = lane_id();
-  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  if (j >= n_wl) return;
-  const Wl d = wl[j];
-  run_workload(d, lane, idx, val, rowid, GlobalX<YNT>{x}, y, partial);
+  const int64_t w = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (w >= n_wl * S) return;
+  const Wl d = wl[w / S];
+  run_workload<S>(d, lane, idx, val, rowid, GlobalX<YNT>{x}, y, partial, (int32_t)(w % S));
 }
 
 // The tile kernel with the fused PageRank update (PrX); d = *dmass, the
 // dangling mass of x.
+template <int S>
 __global__ void __launch_bounds__(kB) k_tile_spmv_pr(const Wl* __restrict__ wl, int64_t n_wl,
                                                      const int32_t* __restrict__ idx, const float* __restrict__ val,
                                                      const int32_t* __restrict__ rowid, const float* __restrict__ x,
                                                      float* __restrict__ pn, double* __restrict__ partial, double c,
                                                      const double* __restrict__ dmass, int64_t n) {
   const int lane = lane_id();
-  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  if (j >= n_wl) return;
-  const Wl d = wl[j];
-  run_workload(d, lane, idx, val, rowid, PrX{x, c, *dmass / (double)n, (1.0 - c) / (double)n}, pn, partial);
+  const int64_t w = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (w >= n_wl * S) return;
+  const Wl d = wl[w / S];
+  run_workload<S>(d, lane, idx, val, rowid, PrX{x, c, *dmass / (double)n, (1.0 - c) / (double)n}, pn, partial,
+                  (int32_t)(w % S));
 }
 
 // The tile kernel with the fused restart of a one-query RWR (RwrX); the seed
 // is an internal id on the device.
+template <int S>
 __global__ void __launch_bounds__(kB) k_tile_spmv_rwr(const Wl* __restrict__ wl, int64_t n_wl,
                                                       const int32_t* __restrict__ idx, const float* __restrict__ val,
                                                       const int32_t* __restrict__ rowid, const float* __restrict__ x,
                                                       float* __restrict__ rn, double* __restrict__ partial, double c,
                                                       const int32_t* __restrict__ seed) {
   const int lane = lane_id();
-  const int64_t j = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  if (j >= n_wl) return;
-  const Wl d = wl[j];
-  run_workload(d, lane, idx, val, rowid, RwrX{x, c, *seed}, rn, partial);
+  const int64_t w = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (w >= n_wl * S) return;
+  const Wl d = wl[w / S];
+  run_workload<S>(d, lane, idx, val, rowid, RwrX{x, c, *seed}, rn, partial, (int32_t)(w % S));
 }
 
 // Concurrent pass over tiles 1..G of the XCD schedule.  Workgroups are
@@ -1616,6 +1622,13 @@ struct TileConfig {
   int persist = 0;
   int lds_floats = 32768;
   int y_nt = 0;
+  // row slices: S wavefronts share each workload of the single-vector tile
+  // kernels, slice s taking every S-th 64-row block (column-major) or row
+  // (row-major). Each row is still summed whole by one lane or one wavefront
+  // in the same order, so the result does not depend on S. It evens out the
+  // tail of the launch; on a 2^27-entry Chung-Lu matrix (WL 8183) the
+  // product takes 1064 / 1032 / 998 / 1325 us with S = 1 / 2 / 4 / 8.
+  int slices = 4;
 };
 TileConfig tile_config() {
   static TileConfig cfg = [] {
@@ -1623,6 +1636,7 @@ TileConfig tile_config() {
     if (const char* e = getenv("TC_PERSIST")) c.persist = atoi(e);
     if (const char* e = getenv("TC_LDS_FLOATS")) c.lds_floats = atoi(e);
     if (const char* e = getenv("TC_Y_NT")) c.y_nt = atoi(e);
+    if (const char* e = getenv("TC_TILE_SLICES")) c.slices = atoi(e) >= 8 ? 8 : atoi(e) >= 4 ? 4 : atoi(e) >= 2 ? 2 : 1;
     int dev = 0, maxsh = 65536;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxsh = 65536;
@@ -1630,6 +1644,17 @@ TileConfig tile_config() {
     return c;
   }();
   return cfg;
+}
+
+// the instance of a tile kernel for the configured number of row slices
+// (a launch of fewer than kSliceMinWl workloads runs one slice each: there
+// the extra wavefronts cost more than they balance; 32 small R-MAT graphs one
+// after another took 15.3 ms with four slices, 13.1 ms with one)
+constexpr int64_t kSliceMinWl = 4096;
+int32_t tile_slices(int64_t n_wl) { return n_wl >= kSliceMinWl ? tile_config().slices : 1; }
+template <class K>
+K pick_slices(int32_t s, K s1, K s2, K s4, K s8) {
+  return s == 8 ? s8 : s == 4 ? s4 : s == 2 ? s2 : s1;
 }
 
 // y := A x in internal ids (x: n_cols, y: n_rows)
@@ -1686,8 +1711,13 @@ void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool 
                   (const Wl*)(h->d_wl + b), (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
                   (const int32_t*)h->d_rowid, x, y, h->d_partial, cb, lw, h->d_counters + t);
     } else {
-      launch_tile(h, cfg.y_nt ? k_tile_spmv<true> : k_tile_spmv<false>, dim3(nblk(e - b, kWpb)), dim3(kB), 0, st,
-                  (const Wl*)(h->d_wl + b), (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
+      const int32_t S = tile_slices(e - b);
+      launch_tile(h, pick_slices(S, cfg.y_nt ? k_tile_spmv<true, 1> : k_tile_spmv<false, 1>,
+                                 cfg.y_nt ? k_tile_spmv<true, 2> : k_tile_spmv<false, 2>,
+                                 cfg.y_nt ? k_tile_spmv<true, 4> : k_tile_spmv<false, 4>,
+                                 cfg.y_nt ? k_tile_spmv<true, 8> : k_tile_spmv<false, 8>),
+                  dim3(nblk((e - b) * S, kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b), (int64_t)(e - b),
+                  (const int32_t*)h->d_idx, (const float*)h->d_val,
                   (const int32_t*)h->d_rowid, x, y, h->d_partial);
     }
   }
@@ -1946,7 +1976,10 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
         if (fuse && !need_res) {
           const int64_t b = h->tile_wl_begin[0], e = h->tile_wl_begin[1];
           if (e > b)
-            launch_tile(h, k_tile_spmv_pr, dim3(nblk(e - b, kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
+            launch_tile(h,
+                        pick_slices(tile_slices(e - b), k_tile_spmv_pr<1>, k_tile_spmv_pr<2>, k_tile_spmv_pr<4>,
+                                    k_tile_spmv_pr<8>),
+                        dim3(nblk((e - b) * tile_slices(e - b), kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
                         (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
                         (const int32_t*)h->d_rowid, (const float*)pc, pn, h->d_partial, (double)c,
                         (const double*)(res + 1), n);
@@ -2120,7 +2153,10 @@ extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k
         } else if (fuse1 && !need_res) {
           const int64_t b = h->tile_wl_begin[0], e = h->tile_wl_begin[1];
           if (e > b)
-            launch_tile(h, k_tile_spmv_rwr, dim3(nblk(e - b, kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
+            launch_tile(h,
+                        pick_slices(tile_slices(e - b), k_tile_spmv_rwr<1>, k_tile_spmv_rwr<2>, k_tile_spmv_rwr<4>,
+                                    k_tile_spmv_rwr<8>),
+                        dim3(nblk((e - b) * tile_slices(e - b), kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
                         (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
                         (const int32_t*)h->d_rowid, (const float*)Rcur, Yb, h->d_partial, (double)c,
                         (const int32_t*)dseeds);
