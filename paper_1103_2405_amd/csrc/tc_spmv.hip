@@ -1647,11 +1647,17 @@ TileConfig tile_config() {
 }
 
 // the instance of a tile kernel for the configured number of row slices
-// (a launch of fewer than kSliceMinWl workloads runs one slice each: there
-// the extra wavefronts cost more than they balance; 32 small R-MAT graphs one
-// after another took 15.3 ms with four slices, 13.1 ms with one)
+// Slices pay where workloads are large and many. A tile of fewer than
+// kSliceMinWl workloads, or with a workload size below kSliceMinSize entries,
+// runs one slice per workload: there the extra wavefronts cost more than they
+// balance (R-MAT 20 at WL 512: 85 us with one slice, 90 us with four; 32
+// small R-MAT graphs at WL 128-256, one after another: 13.1 ms with one,
+// 15.3 ms with four; at WL 1984 four slices win, 98 against 104 us).
 constexpr int64_t kSliceMinWl = 4096;
-int32_t tile_slices(int64_t n_wl) { return n_wl >= kSliceMinWl ? tile_config().slices : 1; }
+constexpr int64_t kSliceMinSize = 1024;
+int32_t tile_slices(const tc_handle* h, int t, int64_t n_wl) {
+  return n_wl >= kSliceMinWl && h->tile_wl[t] >= kSliceMinSize ? tile_config().slices : 1;
+}
 template <class K>
 K pick_slices(int32_t s, K s1, K s2, K s4, K s8) {
   return s == 8 ? s8 : s == 4 ? s4 : s == 2 ? s2 : s1;
@@ -1711,7 +1717,7 @@ void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool 
                   (const Wl*)(h->d_wl + b), (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
                   (const int32_t*)h->d_rowid, x, y, h->d_partial, cb, lw, h->d_counters + t);
     } else {
-      const int32_t S = tile_slices(e - b);
+      const int32_t S = tile_slices(h, t, e - b);
       launch_tile(h, pick_slices(S, cfg.y_nt ? k_tile_spmv<true, 1> : k_tile_spmv<false, 1>,
                                  cfg.y_nt ? k_tile_spmv<true, 2> : k_tile_spmv<false, 2>,
                                  cfg.y_nt ? k_tile_spmv<true, 4> : k_tile_spmv<false, 4>,
@@ -1977,9 +1983,9 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
           const int64_t b = h->tile_wl_begin[0], e = h->tile_wl_begin[1];
           if (e > b)
             launch_tile(h,
-                        pick_slices(tile_slices(e - b), k_tile_spmv_pr<1>, k_tile_spmv_pr<2>, k_tile_spmv_pr<4>,
-                                    k_tile_spmv_pr<8>),
-                        dim3(nblk((e - b) * tile_slices(e - b), kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
+                        pick_slices(tile_slices(h, 0, e - b), k_tile_spmv_pr<1>, k_tile_spmv_pr<2>,
+                                    k_tile_spmv_pr<4>, k_tile_spmv_pr<8>),
+                        dim3(nblk((e - b) * tile_slices(h, 0, e - b), kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
                         (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
                         (const int32_t*)h->d_rowid, (const float*)pc, pn, h->d_partial, (double)c,
                         (const double*)(res + 1), n);
@@ -2154,9 +2160,9 @@ extern "C" tc_status tc_rwr(const tc_handle* hc, const int32_t* seeds, int32_t k
           const int64_t b = h->tile_wl_begin[0], e = h->tile_wl_begin[1];
           if (e > b)
             launch_tile(h,
-                        pick_slices(tile_slices(e - b), k_tile_spmv_rwr<1>, k_tile_spmv_rwr<2>, k_tile_spmv_rwr<4>,
-                                    k_tile_spmv_rwr<8>),
-                        dim3(nblk((e - b) * tile_slices(e - b), kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
+                        pick_slices(tile_slices(h, 0, e - b), k_tile_spmv_rwr<1>, k_tile_spmv_rwr<2>,
+                                    k_tile_spmv_rwr<4>, k_tile_spmv_rwr<8>),
+                        dim3(nblk((e - b) * tile_slices(h, 0, e - b), kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b),
                         (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val,
                         (const int32_t*)h->d_rowid, (const float*)Rcur, Yb, h->d_partial, (double)c,
                         (const int32_t*)dseeds);
