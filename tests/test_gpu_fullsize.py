@@ -62,13 +62,32 @@ def test_full_size_pagerank_100_iterations(cl23, cl23_handle):
     assert abs(p.sum() - 1.0) <= 1e-5
 
 
-def test_full_size_batched_rwr_k32():
+@pytest.fixture(scope="module")
+def rmat20_rwr():
     g = gg.rmat(20, 16, seed=20)
     W = gg.rwr_matrix(g)
-    seeds = gg.rwr_seeds(g, 32, 40)
     tm = TiledMatrix(DeviceCsr(W))
+    yield g, W, tm
+    tm.close()
+
+
+def test_full_size_batched_rwr_k32(rmat20_rwr):
+    g, W, tm = rmat20_rwr
+    seeds = gg.rwr_seeds(g, 32, 40)
     R, it, _ = tm.rwr(seeds, 0.85, 0.0, 20)
     ref, _, _ = oracle.rwr(W, seeds, 0.85, 0.0, 20)
     d = np.abs(R.cpu().numpy().astype(np.float64) - ref).sum(axis=0)
     assert np.all(d <= 1e-6), d.max()
-    tm.close()
+
+
+def test_full_size_single_query_rwr_fused_equals_separate(rmat20_rwr):
+    # the single-vector tile kernel with the restart fused in (row slices at
+    # this size) against iterations that all read the change (no fused step)
+    g, W, tm = rmat20_rwr
+    seeds = gg.rwr_seeds(g, 1, 40)
+    a, it, ra = tm.rwr(seeds, 0.85, 1e-7, 500, 1)
+    b, it2, rb = tm.rwr(seeds, 0.85, 0.0, it)
+    assert it2 == it and ra == rb
+    assert torch.equal(a, b)
+    ref, _, _ = oracle.rwr(W, seeds, 0.85, 0.0, it)
+    assert np.abs(b.cpu().numpy().astype(np.float64) - ref).sum() <= 1e-6
