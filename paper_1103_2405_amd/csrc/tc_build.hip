@@ -986,6 +986,33 @@ struct PhaseClock {
   }
 };
 
+// Every device descriptor must address only its own part of the packed
+// arrays before any kernel is launched on it: rows within the stored rows,
+// elements within [0, nnz_pad), row ids within [0, n_rowid), chunk slots
+// within [0, n_slots), and its rows within its tile's sorted rows.  The
+// offsets come from a running sum, so a violation is a bug in the partition;
+// it is reported instead of handing a kernel an address outside a buffer.
+void check_descriptors(const std::vector<Wl>& dwl, const std::vector<HostWl>& wls,
+                       const std::vector<int64_t>& tile_row_off, int64_t n_slots, int64_t nnz_pad, int64_t n_rowid) {
+  const int64_t ntiles = (int64_t)tile_row_off.size() - 1;
+  for (size_t j = 0; j < dwl.size(); ++j) {
+    const Wl& d = dwl[j];
+    const HostWl& w = wls[j];
+    const int layout = d.info & 3;
+    bool ok = d.w_pad >= 0 && d.h_pad >= 1 && d.n_rows >= 1 && d.n_rows <= d.h_pad && d.data_off >= 0 &&
+              d.rowid_off >= 0 && d.data_off + (int64_t)d.w_pad * d.h_pad <= nnz_pad &&
+              d.rowid_off + d.h_pad <= n_rowid && layout <= kChunk && w.tile >= 0 && w.tile < ntiles;
+    if (ok && layout == kChunk) ok = d.n_rows == 1 && d.h_pad == 1 && (d.info >> 2) < n_slots;
+    if (ok) {
+      const int64_t rb = tile_row_off[w.tile], re = tile_row_off[w.tile + 1];
+      ok = (int64_t)w.row_begin >= rb && (int64_t)w.row_begin + (layout == kChunk ? 1 : w.n_rows) <= re;
+    }
+    if (!ok)
+      throw Fail{TC_EINVAL, "internal error: workload " + std::to_string(j) + " (tile " + std::to_string(w.tile) +
+                                ") addresses outside the packed arrays"};
+  }
+}
+
 void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h) {
   PhaseClock clk(st);
   const int64_t n_rows = A->n_rows, n_cols = A->n_cols, nnz = A->nnz;
@@ -1402,6 +1429,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->nnz_pad = doff;
   h->n_rowid = roff;
   if (doff >= ((int64_t)1 << 40)) throw Fail{TC_EUNSUPPORTED, "padded format too large"};
+  check_descriptors(dwl, wls, h->tile_row_off, h->n_slots, doff, roff);
 
   clk.mark("a6 partition");
   // ---- a7: pack

@@ -76,6 +76,9 @@ class EdgeWeightedRWR:
         self.valT = torch.empty_like(self.val)
         self.W = self.Wt = None
         self.ckpt = None
+        # forwards run so far: the checkpoints, weights and formats belong to
+        # the latest one, so a backward for an earlier forward recomputes them
+        self.generation = 0
 
     def close(self):
         for m in (self.W, self.Wt):
@@ -107,6 +110,7 @@ class EdgeWeightedRWR:
                               stream=self.stream, value_map=refresh, **self.opts)
 
     def forward(self, theta: np.ndarray) -> torch.Tensor:
+        self.generation += 1
         self._weights(theta)
         m = (self.K + self.every - 1) // self.every
         self.ckpt = torch.empty((max(m, 1), self.n), dtype=torch.float32, device="cuda")
@@ -118,7 +122,9 @@ class EdgeWeightedRWR:
     def backward(self, gK: torch.Tensor) -> np.ndarray:
         """dL/dtheta for dL/dr^K = gK (after a forward with the same theta)."""
         lib = load_library()
-        gK = gK.to(torch.float32).contiguous()
+        gK = gK.to(device="cuda", dtype=torch.float32).contiguous()
+        if gK.numel() != self.n:
+            raise ValueError("dL/dr^K must have n entries")
         G = torch.empty(max(self.nnz, 1), dtype=torch.float64, device="cuda")
         _check(lib.tc_rwr_adjoint(self.W.handle, self.Wt.handle, _ptr(self.rpT), _ptr(self.colT), self.seed,
                                   self.c, self.K, self.every, _ptr(self.ckpt), _ptr(gK), _ptr(G), vp(None),
@@ -139,9 +145,18 @@ class _RWRFunction(torch.autograd.Function):
     def forward(ctx, theta, model):
         ctx.model = model
         ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
-        return model.forward(theta.detach().cpu().double().numpy())
+        ctx.theta = theta.detach().cpu().double().numpy().copy()
+        out = model.forward(ctx.theta)
+        ctx.generation = model.generation
+        return out
 
     @staticmethod
     def backward(ctx, grad_rK):
-        g = ctx.model.backward(grad_rK)
+        model = ctx.model
+        if model.generation != ctx.generation:
+            # another forward ran since this one: its weights and checkpoints
+            # replaced ours, so rebuild them for this theta first
+            model.forward(ctx.theta)
+            ctx.generation = model.generation
+        g = model.backward(grad_rK)
         return torch.from_numpy(g).to(dtype=ctx.theta_dtype, device=ctx.theta_device), None

@@ -152,6 +152,23 @@ def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _need(t, shape, name: str) -> torch.Tensor:
+    """A float32, contiguous GPU tensor of exactly `shape` (checked before any
+    pointer reaches the library: a wrong dtype, device or length would make the
+    kernels read or write outside the buffer)."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU" % name)
+    if t.dtype != torch.float32:
+        raise ValueError("%s must be float32, not %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if tuple(t.shape) != tuple(shape) and not (len(shape) == 1 and t.dim() == 1 and t.numel() == shape[0]):
+        raise ValueError("%s must have shape %s, not %s" % (name, tuple(shape), tuple(t.shape)))
+    return t
+
+
 def _dev(a, dtype, device) -> torch.Tensor:
     if isinstance(a, torch.Tensor):
         t = a.to(device=device, dtype=dtype)
@@ -179,8 +196,10 @@ class DeviceCsr:
 def csr_spmv(A: DeviceCsr, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Plain CSR SpMV (one thread per row) -- the baseline kernel."""
     lib = load_library()
+    _need(x, (A.n_cols,), "x")
     if y is None:
         y = torch.empty(A.n_rows, dtype=torch.float32, device=x.device)
+    _need(y, (A.n_rows,), "y")
     c = A.c()
     _check(lib.tc_csr_spmv(ctypes.byref(c), _ptr(x), _ptr(y), _stream(stream)), "tc_csr_spmv")
     return y
@@ -282,29 +301,34 @@ class TiledMatrix:
     def refresh_values(self, val: torch.Tensor, stream=None) -> None:
         """New values (nnz floats, in the order of the CSR entries the handle
         was built from) for the same pattern; needs value_map=True."""
-        v = val.to(torch.float32).contiguous()
-        if v.numel() != self.nnz or not v.is_cuda:
-            raise ValueError("need nnz float32 values on the GPU")
+        v = _need(val, (self.nnz,), "val")
         _check(load_library().tc_refresh_values(self.handle, _ptr(v), _stream(stream)), "tc_refresh_values")
         self._vals = v  # kept alive until the stream has read it
 
     def spmv(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """y := A x (caller's ids)."""
+        _need(x, (self.n_cols,), "x")
         if y is None:
             y = torch.empty(self.n_rows, dtype=torch.float32, device=x.device)
+        _need(y, (self.n_rows,), "y")
         _check(load_library().tc_spmv(self.handle, _ptr(x), _ptr(y), _stream(stream)), "tc_spmv")
         return y
 
     def spmv_internal(self, x: torch.Tensor, y: torch.Tensor, stream=None) -> torch.Tensor:
+        _need(x, (self.n_cols,), "x")
+        _need(y, (self.n_rows,), "y")
         _check(load_library().tc_spmv_internal(self.handle, _ptr(x), _ptr(y), _stream(stream)), "tc_spmv_internal")
         return y
 
     def spmm(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """Y := A X for X (n_cols x k, row-major)."""
-        X = X.contiguous()
-        k = X.shape[1]
+        if not isinstance(X, torch.Tensor) or X.dim() != 2:
+            raise ValueError("X must be a 2-D tensor (n_cols x k)")
+        k = int(X.shape[1])
+        _need(X, (self.n_cols, k), "X")
         if Y is None:
             Y = torch.empty((self.n_rows, k), dtype=torch.float32, device=X.device)
+        _need(Y, (self.n_rows, k), "Y")
         _check(load_library().tc_spmm(self.handle, _ptr(X), _ptr(Y), k, _stream(stream)), "tc_spmm")
         return Y
 
@@ -312,6 +336,7 @@ class TiledMatrix:
     def pagerank(self, c: float = 0.85, tol: float = 0.0, max_iter: int = 50, check_every: int = 1,
                  out: Optional[torch.Tensor] = None, stream=None, raise_not_converged: bool = True):
         p = out if out is not None else torch.empty(self.n_rows, dtype=torch.float32, device="cuda")
+        _need(p, (self.n_rows,), "out")
         it, res = i32(0), ctypes.c_double(0.0)
         st = load_library().tc_pagerank(self.handle, c, tol, max_iter, check_every, _ptr(p), ctypes.byref(it),
                                         ctypes.byref(res), _stream(stream))

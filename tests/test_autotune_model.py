@@ -73,3 +73,34 @@ def test_choose_wl_bounds():
 
 def test_nearest_log2():
     assert [nearest_log2(v) for v in (1, 2, 3, 5, 6, 11, 12, 64, 90, 91)] == [0, 1, 2, 2, 3, 3, 4, 6, 6, 7]
+
+
+def test_tile_split_len_by_hand():
+    from oracle.autotune import tile_split_len
+    # given lengths are used as they are (0: never split, the paper's rule)
+    assert tile_split_len(0, 10 ** 9, 8192, 64) == 0
+    assert tile_split_len(777, 10, 8192, 64) == 777
+    # automatic: the tile's entries per resident wavefront, rounded up to a
+    # multiple of S, kept within [S, 8192]
+    assert tile_split_len(-1, 8192 * 100 + 1, 8192, 64) == 128      # ceil(100.0001) = 101 -> 128
+    assert tile_split_len(-1, 8192 * 128, 8192, 64) == 128          # exactly 128 per wavefront
+    assert tile_split_len(-1, 8192 * 128 + 1, 8192, 64) == 192      # 129 -> 192
+    assert tile_split_len(-1, 5, 8192, 64) == 64                    # below one wave width: S
+    assert tile_split_len(-1, 0, 8192, 64) == 64                    # empty tile: S
+    assert tile_split_len(-1, 1 << 27, 8192, 64) == 8192            # 16384 capped at 8192
+    assert tile_split_len(-1, 1000, 10, 4) == 100                   # other S and wavefront counts
+    assert tile_split_len(-1, 1001, 10, 4) == 104
+
+
+def test_perf_table_lookup_rounds_and_clamps():
+    # value = 100 lw + lh on a 4 x 3 grid makes every lookup's cell visible
+    g = np.array([[100 * a + b for b in range(3)] for a in range(4)], np.int64)
+    t = PerfTable(g, 2 * g)
+    assert t.perf("dense", 1, 1) == 0
+    assert t.perf("dense", 2, 4) == 102
+    assert t.perf("dense", 3, 3) == 202        # 3 rounds up to 4 in log scale
+    assert t.perf("dense", 5, 1) == 200        # 5 rounds down to 4
+    assert t.perf("dense", 6, 1) == 300        # 6 rounds up to 8
+    assert t.perf("dense", 1000, 1) == 300     # past the grid: the last column
+    assert t.perf("dense", 8, 4096) == 302     # past the grid in h as well
+    assert t.perf("sparse", 1000, 4096) == 604  # the sparse grid, clamped the same way

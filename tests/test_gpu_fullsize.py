@@ -1,13 +1,19 @@
 """Parity at the benchmark's full sizes, in the configuration bench.py times
-(default build options): the 2^23-node / 2^27-edge Chung-Lu PageRank matrix
-and the symmetrised R-MAT 20 graph.  SpMV is checked on sampled rows the
-oracle computes one by one (plus the longest and the empty rows) and by an
-identity over all rows; PageRank and batched RWR against the full oracle."""
+(default build options): the 2^23-node / 2^27-edge Chung-Lu PageRank matrix,
+the R-MAT 20 PageRank and HITS matrices and the symmetrised R-MAT 20 graph.
+Every SpMV row is checked against the oracle, every format array bit for bit
+against the reference builder, and PageRank, HITS, batched RWR and the
+differentiable RWR's gradient against the full FP64 oracle."""
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import graphgen as gg
 import oracle
+from oracle import ref_format as rf
+from oracle.autotune import PerfTable
 
 pytestmark = pytest.mark.gpu
 
@@ -18,6 +24,43 @@ if not torch.cuda.is_available():  # these tests need a GPU
 from paper_1103_2405_amd import DeviceCsr, TiledMatrix  # noqa: E402
 
 TOL = 1e-5
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TABLE = os.path.join(ROOT, "paper_1103_2405_amd", "data", "perf_table_gfx950.txt")
+FMT_KEYS = ["cperm", "rowmap", "tile_col_begin", "tile_col_end", "tile_nnz", "tile_wl", "tile_split", "tile_row_off",
+            "rows_sorted", "rows_len", "wl_tile", "wl_layout", "wl_w", "wl_w_pad", "wl_h_pad", "wl_row_begin",
+            "wl_n_rows", "wl_chunk", "wl_n_chunks", "wl_data_off", "wl_rowid_off", "idx", "rowid"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def reference_default_format(csr):
+    """The reference builder with the library's default options."""
+    return rf.build(csr, W=1 << 23, table=PerfTable.load(TABLE), split_len=-1)
+
+
+def assert_format_bit_exact(tm, csr):
+    say("reference build of", len(csr[3]), "entries")
+    ref = reference_default_format(csr)
+    g = tm.export_format()
+    assert g["T"] == ref["T"] and g["n_tiles_total"] == ref["n_tiles_total"] and g["nnz_pad"] == ref["nnz_pad"]
+    for k in FMT_KEYS:
+        a, b = np.asarray(g[k]), np.asarray(ref[k])
+        assert a.shape == b.shape, (k, a.shape, b.shape)
+        assert np.array_equal(a.astype(np.int64), b.astype(np.int64)), k
+    assert np.array_equal(g["val"].view(np.uint32), ref["val"].view(np.uint32)), "val"
+
+
+def assert_spmv_all_rows(tm, csr, x):
+    y = tm.spmv(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    ref = oracle.spmv(csr, x)
+    bound = TOL * oracle.absmv(csr, x)
+    err = np.abs(y - ref)
+    bad = np.flatnonzero(err > bound)
+    assert bad.size == 0, (bad[:5], err[bad[:5]], bound[bad[:5]])
+    return y
 
 
 @pytest.fixture(scope="module")
@@ -33,24 +76,18 @@ def cl23_handle(cl23):
     tm.close()
 
 
-def test_full_size_spmv_sampled_rows(cl23, cl23_handle):
+def test_full_size_spmv_all_rows(cl23, cl23_handle):
     n, _, rp, col, val = cl23
     x = gg.uniform_f32(n, 101)
-    y = cl23_handle.spmv(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
-    lens = np.diff(rp)
-    rows = np.unique(np.concatenate([
-        gg.uniform_int(200000, n, 7),                 # uniform sample
-        np.argsort(-lens, kind="stable")[:2000],      # the heaviest rows (split across wavefronts)
-        np.flatnonzero(lens == 0)[:2000],             # empty rows
-        [0, n - 1]]))
-    ref, absref = oracle.spmv_rows(cl23, x, rows)
-    err = np.abs(y[rows] - ref)
-    bad = np.flatnonzero(err > TOL * absref)
-    assert bad.size == 0, (rows[bad[:5]], err[bad[:5]], absref[bad[:5]])
-    # all rows: sum y = sum over non-empty columns of x (the matrix is column-stochastic)
+    y = assert_spmv_all_rows(cl23_handle, cl23, x)
+    # sum y = sum over non-empty columns of x (the matrix is column-stochastic)
     clen = np.bincount(col, minlength=n)
     want = float(np.sum(x[clen > 0].astype(np.float64)))
     assert abs(float(y.sum()) - want) <= 1e-6 * want
+
+
+def test_full_size_format_bit_exact(cl23, cl23_handle):
+    assert_format_bit_exact(cl23_handle, cl23)
 
 
 def test_full_size_pagerank_100_iterations(cl23, cl23_handle):
@@ -91,3 +128,52 @@ def test_full_size_single_query_rwr_fused_equals_separate(rmat20_rwr):
     assert torch.equal(a, b)
     ref, _, _ = oracle.rwr(W, seeds, 0.85, 0.0, it)
     assert np.abs(b.cpu().numpy().astype(np.float64) - ref).sum() <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def rmat20():
+    return gg.rmat(20, 16, seed=20)
+
+
+def test_rmat20_pagerank_matrix_spmv_format_and_50_iterations(rmat20):
+    csr = gg.pagerank_matrix(rmat20)
+    with TiledMatrix(DeviceCsr(csr)) as tm:
+        assert_spmv_all_rows(tm, csr, gg.uniform_f32(rmat20.n, 101))
+        assert_format_bit_exact(tm, csr)
+        p, it, res = tm.pagerank(0.85, 0.0, 50)
+        pref, _, rref = oracle.pagerank(csr, 0.85, 0.0, 50)
+        d = np.abs(p.cpu().numpy().astype(np.float64) - pref).sum()
+        say("rmat20 pagerank L1 diff", d)
+        assert it == 50 and d <= 1e-6
+        assert abs(res - rref[-1]) <= 1e-6
+
+
+def test_rmat20_hits(rmat20):
+    csr = gg.hits_matrix(rmat20)
+    n = rmat20.n
+    with TiledMatrix(DeviceCsr(csr)) as tm:
+        a, h, it, _ = tm.hits(0.0, 30)
+        x, _, _ = oracle.hits(csr, 0.0, 30)
+        d = np.abs(a.cpu().numpy() - x[:n]).sum() + np.abs(h.cpu().numpy() - x[n:]).sum()
+        say("rmat20 hits L1 diff", d)
+        assert it == 30 and d <= 1e-6
+
+
+def test_rmat20_rwr_gradient_matches_fp64_reference():
+    # the benchmark's differentiable RWR at full size: symmetrised R-MAT 20,
+    # 4 features per entry, 30 iterations, checkpoints every 6, 16 targets
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_oracle_rwr_grad import problem
+    from oracle import rwr_grad as rg
+    from paper_1103_2405_amd.rwr_grad import EdgeWeightedRWR
+    n, rp, col, feats, theta, s, targets = problem(20, 16, 20)
+    say("rmat20 gradient problem: n", n, "nnz", len(col))
+    model = EdgeWeightedRWR((n, n, rp, col), feats, s, 0.85, 30, every=6)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    loss = -torch.log(model.scores(th)[torch.as_tensor(targets).cuda()].double()).sum()
+    loss.backward()
+    model.close()
+    ref_loss, ref_grad, _ = rg.loss_and_grad(n, rp, col, feats, theta, s, targets, 0.85, 30)
+    say("loss", loss.item(), ref_loss, "grad", th.grad.numpy(), ref_grad)
+    assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
+    assert np.linalg.norm(th.grad.numpy() - ref_grad) <= 1e-4 * np.linalg.norm(ref_grad)

@@ -605,3 +605,26 @@ def test_dense_2000_matrix_both_kernels():
     x = gg.uniform_f32(n, 2001)
     for kernel in ("composite", "coo"):
         check_spmv(TiledMatrix(csr, kernel=kernel), csr, x)
+
+
+def test_rwr_gradient_of_an_earlier_forward():
+    # two forwards on one model, then the backward of the first: the gradient
+    # must be the first theta's (the model's state belongs to the second)
+    from test_oracle_rwr_grad import problem
+    from oracle import rwr_grad as rg
+    from paper_1103_2405_amd.rwr_grad import EdgeWeightedRWR
+    n, rp, col, feats, theta, s, targets = problem(9, 8, 78)
+    model = EdgeWeightedRWR((n, n, rp, col), feats, s, 0.85, 30, every=7)
+    tg = torch.as_tensor(targets).cuda()
+    th1 = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    theta2 = np.asarray(theta) * -0.5 + 0.3
+    th2 = torch.tensor(theta2, dtype=torch.float64, requires_grad=True)
+    loss1 = -torch.log(model.scores(th1)[tg].double()).sum()
+    loss2 = -torch.log(model.scores(th2)[tg].double()).sum()
+    loss1.backward()
+    loss2.backward()
+    for th, t in ((th1, theta), (th2, theta2)):
+        ref_loss, ref_grad, _ = rg.loss_and_grad(n, rp, col, feats, t, s, targets, 0.85, 30)
+        say("grad", th.grad.numpy(), ref_grad)
+        assert np.linalg.norm(th.grad.numpy() - ref_grad) <= 1e-4 * np.linalg.norm(ref_grad)
+    model.close()
