@@ -96,6 +96,11 @@ typedef struct {
                                  per slot on the device), so tc_refresh_values can put new values
                                  of the same pattern in place without a rebuild.  Composite
                                  kernel only; default 0 */
+  int32_t slices;             /* row slices per workload of the single-vector tile kernels: 0 =
+                                 automatic (4 on tiles of at least 4096 workloads of at least
+                                 1024 entries, else 1); 1, 2, 4 or 8 = that count on every
+                                 tile.  Each row is summed whole, in the same order, by one lane
+                                 or one wavefront, so the result does not depend on it */
   const char* perf_table;     /* path of a throughput table for the model; NULL = built-in */
   /* optional device allocator for the handle's buffers; NULL = hipMalloc / hipFree */
   void* (*alloc)(size_t bytes, void* ctx);

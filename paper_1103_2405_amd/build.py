@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtcspmv.so")
-SOURCES = ["tc_build.hip", "tc_spmv.hip", "tc_partition.cpp", "tc_api.cpp", "tc_mem.cpp"]
+SOURCES = ["tc_build.hip", "tc_spmv.hip", "tc_spmm.hip", "tc_drivers.hip", "tc_multi.hip", "tc_grad.hip",
+           "tc_partition.cpp", "tc_api.cpp", "tc_mem.cpp"]
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: no packed FP32 instructions are generated (they are not

@@ -1585,6 +1585,7 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
     return TC_EINVAL;
   }
   if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->xcd_groups < 0 || o->xcd_groups > 64 || o->kernel < 0 || o->kernel > 1 || (o->kernel == 1 && o->xcd_groups > 0) || o->value_map < 0 || o->value_map > 1 || (o->value_map && o->kernel == 1) || o->max_act_warp < 0 || o->wl_policy < 0 ||
+      !(o->slices == 0 || o->slices == 1 || o->slices == 2 || o->slices == 4 || o->slices == 8) ||
       o->wl_policy > 2 || (o->wl_policy == 1 && !o->wl_per_tile) || (o->relabel > 0 && A->n_rows != A->n_cols)) {
     set_error("tc_build_tiled: invalid option");
     return TC_EINVAL;
@@ -1605,6 +1606,7 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   h->max_act_warp = o->max_act_warp > 0 ? o->max_act_warp : 8192;
   h->xcd_groups = o->xcd_groups;
   h->kernel = o->kernel;
+  h->slices = o->slices;
   h->alloc = o->alloc;
   h->dfree = o->free;
   h->alloc_ctx = o->alloc_ctx;

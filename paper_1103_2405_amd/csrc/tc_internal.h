@@ -103,6 +103,7 @@ struct tc_handle {
   int32_t W = 0, S = 64, split_len = 0, T = 0, n_tiles = 0;
   bool relabel = false, camping_pad = false;
   int64_t max_act_warp = 8192;
+  int32_t slices = 0;               // row slices of the single-vector tile kernels (0 = automatic)
   int64_t nnz_pad = 0, n_rowid = 0, n_rows_sorted = 0, n_dangling = 0;
   int64_t n_wl = 0, n_slots = 0, n_split_rows = 0;
   double build_us = 0.0;

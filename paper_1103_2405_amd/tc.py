@@ -44,7 +44,7 @@ class CBuildOpts(ctypes.Structure):
     _fields_ = [("tile_width", i32), ("n_tiles", i32), ("wl_policy", i32), ("wl_all", i32),
                 ("wl_per_tile", vp), ("n_wl_per_tile", i32), ("wave", i32), ("split_len", i32),
                 ("camping_pad", i32), ("relabel", i32), ("max_act_warp", i32), ("xcd_groups", i32), ("kernel", i32),
-                ("value_map", i32), ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
+                ("value_map", i32), ("slices", i32), ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
 
 
 class CInfo(ctypes.Structure):
@@ -211,7 +211,7 @@ class TiledMatrix:
     def __init__(self, csr, tile_width: int = 0, n_tiles: int = -1, wl: Optional[Sequence[int] | int] = None,
                  wave: int = 64, split_len: int = -1, camping_pad: bool = False, relabel: int = -1,
                  max_act_warp: int = 0, perf_table: Optional[str] = "default", xcd_groups: int = -1,
-                 kernel: str = "composite", value_map: bool = False, stream=None):
+                 kernel: str = "composite", value_map: bool = False, slices: int = 0, stream=None):
         lib = load_library()
         A = csr if isinstance(csr, DeviceCsr) else DeviceCsr(csr)
         self.n_rows, self.n_cols, self.nnz = A.n_rows, A.n_cols, A.nnz
@@ -225,6 +225,7 @@ class TiledMatrix:
             raise ValueError("kernel must be 'composite' or 'coo'")
         o.kernel = 1 if kernel == "coo" else 0
         o.value_map = int(bool(value_map))
+        o.slices = int(slices)
         keep = None
         if wl is None:
             o.wl_policy = 0

@@ -628,3 +628,29 @@ def test_rwr_gradient_of_an_earlier_forward():
         say("grad", th.grad.numpy(), ref_grad)
         assert np.linalg.norm(th.grad.numpy() - ref_grad) <= 1e-4 * np.linalg.norm(ref_grad)
     model.close()
+
+
+@pytest.mark.parametrize("W,split,wave", [(1 << 14, 256, 64), (2048, 128, 64), (1 << 14, 96, 32)])
+def test_row_slices_do_not_change_results(W, split, wave):
+    # the same format with 1, 2, 4 and 8 row slices forced on every tile:
+    # column-major blocks, 64/128-wide and wider row-major rows, split-row
+    # chunks and (wave 32) the generic path give bit-identical products and
+    # PageRank iterates, within the bound of the oracle
+    g = gg.rmat(14, 16, seed=14)
+    csr = gg.pagerank_matrix(g)
+    x = torch.from_numpy(gg.uniform_f32(g.n, 101)).cuda()
+    ys, ps = [], []
+    for S in (1, 2, 4, 8):
+        gm = TiledMatrix(csr, tile_width=W, split_len=split, wave=wave, slices=S)
+        if S == 1:
+            lay = gm.export_format(metadata_only=True)
+            say("layouts", np.bincount(lay["wl_layout"], minlength=3), "w_pad", sorted(set(lay["wl_w_pad"].tolist()))[:8])
+        ys.append(gm.spmv(x))
+        ps.append(gm.pagerank(0.85, 0.0, 20)[0])
+        gm.close()
+    for S, y, p in zip((2, 4, 8), ys[1:], ps[1:]):
+        assert torch.equal(y, ys[0]), S
+        assert torch.equal(p, ps[0]), S
+    xs = x.cpu().numpy()
+    yy = ys[0].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(yy - oracle.spmv(csr, xs)) <= TOL * oracle.absmv(csr, xs))
