@@ -101,6 +101,17 @@ typedef struct {
                                  1024 entries, else 1); 1, 2, 4 or 8 = that count on every
                                  tile.  Each row is summed whole, in the same order, by one lane
                                  or one wavefront, so the result does not depend on it */
+  const int32_t* tile_bounds; /* host array of n_tile_bounds increasing internal column ids in
+                                 (0, n_cols]: dense tiles [0, b0), [b0, b1), ... [b_{k-2}, b_{k-1}),
+                                 then the sparse tile [b_{k-1}, n_cols) when b_{k-1} < n_cols.
+                                 Tiles of different widths (Solution 1 with one width per cache
+                                 level); tile_width and n_tiles are then not used.  NULL = none */
+  int32_t n_tile_bounds;      /* length of tile_bounds (0 = none) */
+  int32_t lds_stage;          /* 0 (default): a tile no wider than one workgroup's LDS (160 KB,
+                                 40960 columns) with at least 8 entries per float staged has its
+                                 x segment staged in LDS by a persistent kernel, so its gathers
+                                 are LDS reads; 1: every tile that fits is staged; -1: every
+                                 tile gathers x through the caches */
   const char* perf_table;     /* path of a throughput table for the model; NULL = built-in */
   /* optional device allocator for the handle's buffers; NULL = hipMalloc / hipFree */
   void* (*alloc)(size_t bytes, void* ctx);

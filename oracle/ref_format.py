@@ -51,7 +51,7 @@ def xcd_boundaries(clen_sorted: np.ndarray, W: int, groups: int) -> list:
 def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S: int = 64,
           split_len: int = -1, camping_pad: bool = False, relabel: Optional[bool] = None,
           table: Optional[PerfTable] = None, max_act_warp: int = 8192, xcd_groups: int = 0,
-          coo: bool = False) -> dict:
+          coo: bool = False, bounds: Optional[Sequence[int]] = None) -> dict:
     n_rows, n_cols, rp, col, val = csr
     rp = np.asarray(rp, np.int64)
     col = np.asarray(col, np.int32)
@@ -71,7 +71,17 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
     rmap = cpos.copy() if relabel else np.arange(n_rows, dtype=np.int64)
 
     # a3: Algorithm 1
-    if xcd_groups > 0:
+    if bounds:
+        # given boundaries: dense tiles [0, b0), [b0, b1), ..., then the
+        # columns past the last bound as the sparse tile
+        b = [0] + [int(v) for v in bounds]
+        if any(b[i + 1] <= b[i] for i in range(len(b) - 1)) or b[-1] > n_cols:
+            raise ValueError("bounds must increase within (0, n_cols]")
+        ranges = [(b[i], b[i + 1]) for i in range(len(b) - 1)]
+        if b[-1] < n_cols:
+            ranges.append((b[-1], n_cols))
+        T = len(bounds)
+    elif xcd_groups > 0:
         # MI355X schedule: hot head tile, then column ranges of equal entries
         b = xcd_boundaries(clen[cperm], W, xcd_groups)
         ranges = [(b[i], b[i + 1]) for i in range(len(b) - 1)]
@@ -196,7 +206,7 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
                      coo_val=val[order].astype(np.float32))
     return dict(
         **extra,
-        n_rows=n_rows, n_cols=n_cols, nnz=nnz, W=W, S=S, split_len=split_len, T=T, xcd_groups=xcd_groups,
+        n_rows=n_rows, n_cols=n_cols, nnz=nnz, W=W, S=S, split_len=split_len, T=T, xcd_groups=xcd_groups, bounds=list(bounds) if bounds else None,
         tile_split=np.asarray(split_used, np.int64),
         n_tiles_total=ntiles, relabel=bool(relabel),
         clen=clen, cperm=cperm.astype(np.int32), cpos=cpos.astype(np.int32),

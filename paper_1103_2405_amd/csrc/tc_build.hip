@@ -1120,6 +1120,13 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     for (int g = 1; g < G; ++g) starts.push_back((int32_t)std::max<int64_t>(head + hcut[g], starts.back()));
     T = 1;
     ntiles = 1 + G;
+  } else if (o->n_tile_bounds > 0) {
+    // given tile boundaries: dense tiles up to the last bound, then the
+    // sparse tile if columns remain
+    for (int i = 0; i < o->n_tile_bounds; ++i)
+      if (o->tile_bounds[i] < n_cols) starts.push_back(o->tile_bounds[i]);
+    T = o->n_tile_bounds;
+    ntiles = (int32_t)starts.size() + 1;
   } else {
     if (o->n_tiles >= 0) {
       T = (int32_t)std::min<int64_t>(o->n_tiles, NT);
@@ -1144,7 +1151,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     h->tile_col_end[t] = t + 1 < ntiles ? starts[t] : n_cols;
   }
   TileMap tmap{W, T, nullptr, 0};
-  if (h->xcd_groups > 0 && ntiles > 1) {
+  if ((h->xcd_groups > 0 || o->n_tile_bounds > 0) && ntiles > 1) {
     int32_t* d_starts = tmp.get<int32_t>(ntiles - 1);
     HIPX(hipMemcpyAsync(d_starts, starts.data(), sizeof(int32_t) * (ntiles - 1), hipMemcpyHostToDevice, st));
     tmap = TileMap{W, T, d_starts, ntiles - 1};
@@ -1521,6 +1528,16 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipGetDevice(&dev));
     HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     h->n_cu = cus > 0 ? cus : 256;
+    // LDS a workgroup may use (the opt-in limit) and LDS per compute unit
+    int blk = 0, optin = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) blk = 65536;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+      per_cu = 0;
+    (void)hipGetLastError();
+    const int64_t wg = std::max(blk, optin);
+    h->lds_cu_bytes = per_cu > 0 ? per_cu : wg;
+    h->lds_floats = std::min<int64_t>(std::min<int64_t>(wg, h->lds_cu_bytes) / 4, kLdsMaxFloats);
   }
   HIPX(hipStreamSynchronize(st));
   clk.mark("a7 pack + metadata");
@@ -1586,9 +1603,17 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   }
   if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->xcd_groups < 0 || o->xcd_groups > 64 || o->kernel < 0 || o->kernel > 1 || (o->kernel == 1 && o->xcd_groups > 0) || o->value_map < 0 || o->value_map > 1 || (o->value_map && o->kernel == 1) || o->max_act_warp < 0 || o->wl_policy < 0 ||
       !(o->slices == 0 || o->slices == 1 || o->slices == 2 || o->slices == 4 || o->slices == 8) ||
+      o->n_tile_bounds < 0 || o->lds_stage < -1 || o->lds_stage > 1 || (o->n_tile_bounds > 0 && (!o->tile_bounds || o->xcd_groups > 0)) ||
       o->wl_policy > 2 || (o->wl_policy == 1 && !o->wl_per_tile) || (o->relabel > 0 && A->n_rows != A->n_cols)) {
     set_error("tc_build_tiled: invalid option");
     return TC_EINVAL;
+  }
+  for (int i = 0; i < o->n_tile_bounds; ++i) {
+    const int64_t b = o->tile_bounds[i];
+    if (b <= (i ? (int64_t)o->tile_bounds[i - 1] : 0) || b > A->n_cols) {
+      set_error("tc_build_tiled: tile_bounds must increase within (0, n_cols]");
+      return TC_EINVAL;
+    }
   }
   if ((o->alloc == nullptr) != (o->free == nullptr)) {
     set_error("tc_build_tiled: give both alloc and free or neither");
@@ -1607,6 +1632,7 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   h->xcd_groups = o->xcd_groups;
   h->kernel = o->kernel;
   h->slices = o->slices;
+  h->lds_tiles = o->lds_stage + 1;  // 0 never, 1 automatic, 2 every tile that fits
   h->alloc = o->alloc;
   h->dfree = o->free;
   h->alloc_ctx = o->alloc_ctx;

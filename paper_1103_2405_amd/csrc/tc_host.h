@@ -38,6 +38,10 @@ void launch_tile(tc_handle* h, void (*kern)(KArgs...), dim3 grid, dim3 block, ui
   HIPC(hipGetLastError());
 }
 
+// LDS staging of tile t's x segment: the width to stage, or 0 (global gathers)
+int64_t lds_tile_width(const tc_handle* h, int t);
+int64_t lds_tile_blocks(const tc_handle* h, int64_t lw);
+
 // Row slices of tile t's workloads (the build option, or the measured rule).
 int32_t tile_slices(const tc_handle* h, int t, int64_t n_wl);
 template <class K>

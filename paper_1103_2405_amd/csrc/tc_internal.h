@@ -14,6 +14,9 @@ namespace tc {
 
 constexpr int kWave = 64;
 
+// Most floats of x a tile stages in LDS (160 KB, the LDS of one gfx950 CU).
+constexpr int64_t kLdsMaxFloats = 40960;
+
 // Row ids stored in `rowid` carry bit 30 when an earlier tile already wrote
 // that row of y (the tile adds); without it the tile is the row's first
 // writer and stores.  Rows are therefore limited to 2^30.
@@ -142,6 +145,9 @@ struct tc_handle {
   int64_t* d_tile_wl_begin = nullptr;  // device copy of tile_wl_begin
   int64_t n_zero0 = 0;
   int n_cu = 256;                   // compute units of the device
+  int32_t lds_tiles = 1;            // LDS staging of narrow tiles: 0 never, 1 automatic, 2 whenever it fits
+  int64_t lds_floats = 0;           // floats of x one workgroup can stage (device limit)
+  int64_t lds_cu_bytes = 0;         // LDS bytes per compute unit
   int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
   // value map (build option): the CSR entry of every padded slot, -1 for pads
   int32_t* d_vmap = nullptr;

@@ -27,6 +27,48 @@ __global__ void __launch_bounds__(kB) k_tile_spmv(const Wl* __restrict__ wl, int
   run_workload<S>(d, lane, idx, val, rowid, GlobalX{x}, y, partial, (int32_t)(w % S));
 }
 
+// x of a tile whose whole column range sits in LDS (a tile no wider than the
+// LDS of one workgroup): every gather of the tile is an LDS read.
+struct LdsX {
+  const float* xs;  // LDS copy of x[cb, cb + width)
+  int32_t cb;
+  __device__ float operator()(int32_t i) const { return xs[i - cb]; }
+  __device__ void addy(float* y, int32_t rid, double s) const { addy_first_touch(y, rid, s); }
+};
+
+// Tile pass with the tile's x segment staged in LDS (Section 3.1, Solution 1:
+// the segment of x a tile reads is kept in the nearest memory; on gfx950 that
+// is the 160 KB LDS of a compute unit).  Persistent: each workgroup copies
+// x[cb, cb + lw) into LDS once, then its wavefronts take the work items
+// (workload slices) w = global wavefront id, + total wavefronts, ... until
+// none is left, so every wavefront ends after a bounded number of items.
+constexpr int kLdsB = 1024;  // threads of an LDS-tile workgroup
+template <int S>
+__global__ void __launch_bounds__(kLdsB) k_tile_lds(const Wl* __restrict__ wl, int64_t n_wl,
+                                                    const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                    const int32_t* __restrict__ rowid, const float* __restrict__ x,
+                                                    int32_t cb, int32_t lw, float* __restrict__ y,
+                                                    double* __restrict__ partial) {
+  extern __shared__ float xs[];
+  const float* xsrc = x + cb;
+  if (((uintptr_t)xsrc & 15) == 0 && (lw & 3) == 0) {
+    for (int32_t k = 4 * (int32_t)threadIdx.x; k < lw; k += 4 * kLdsB)
+      *(float4*)(xs + k) = *(const float4*)(xsrc + k);
+  } else {
+    for (int32_t k = threadIdx.x; k < lw; k += kLdsB) xs[k] = xsrc[k];
+  }
+  __syncthreads();
+  const int lane = lane_id();
+  const int64_t waves = (int64_t)gridDim.x * (kLdsB / kWave);
+  const int64_t items = n_wl * S;
+  const LdsX xg{xs, cb};
+  for (int64_t w = (int64_t)blockIdx.x * (kLdsB / kWave) + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+       w < items; w += waves) {
+    const Wl d = wl[w / S];
+    run_workload<S>(d, lane, idx, val, rowid, xg, y, partial, (int32_t)(w % S));
+  }
+}
+
 // Concurrent pass over tiles 1..G of the XCD schedule.  Workgroups are
 // dispatched round-robin over the 8 XCDs, so block b runs on XCD b % 8: tile
 // 1 + (b % G) takes blocks b with that residue, and its x range stays in one
@@ -273,6 +315,26 @@ int32_t tile_slices(const tc_handle* h, int t, int64_t n_wl) {
   return n_wl >= kSliceMinWl && h->tile_wl[t] >= kSliceMinSize ? kSlicesDefault : 1;
 }
 
+// LDS staging of a tile's x segment: the tile must fit the LDS of one
+// workgroup, and carry enough entries for the copy (lw floats into every
+// resident workgroup) to be a small part of its traffic: at least
+// kLdsMinReuse gathers per staged float.  Returns the width to stage, or 0.
+constexpr int64_t kLdsMinReuse = 8;
+int64_t lds_tile_width(const tc_handle* h, int t) {
+  if (!h->lds_tiles || h->lds_floats <= 0) return 0;
+  const int64_t lw = h->tile_col_end[t] - h->tile_col_begin[t];
+  if (lw <= 0 || lw > h->lds_floats) return 0;
+  if (h->lds_tiles == 1 && h->tile_nnz[t] < kLdsMinReuse * lw * lds_tile_blocks(h, lw)) return 0;
+  return lw;
+}
+
+// Resident workgroups of the LDS tile kernel for a segment of lw floats (one
+// grid of them covers the GPU once).
+int64_t lds_tile_blocks(const tc_handle* h, int64_t lw) {
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(2, h->lds_cu_bytes / std::max<int64_t>(4 * lw, 1)));
+  return per_cu * h->n_cu;
+}
+
 void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine, bool skip_zero) {
   const bool xcd = h->xcd_groups > 0 && h->n_tiles > 1;
   const int64_t nzero = xcd ? h->n_zero0 : h->n_empty;
@@ -309,6 +371,17 @@ void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool 
     const int64_t b = h->tile_wl_begin[t], e = h->tile_wl_begin[t + 1];
     if (e == b) continue;
     const int32_t S = tile_slices(h, t, e - b);
+    const int64_t lw = lds_tile_width(h, t);
+    if (lw > 0) {
+      auto kern = pick_slices(S, k_tile_lds<1>, k_tile_lds<2>, k_tile_lds<4>, k_tile_lds<8>);
+      if (lw * 4 > 65536) HIPC(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)(lw * 4)));
+      const unsigned grid = (unsigned)std::min<int64_t>(lds_tile_blocks(h, lw), nblk((e - b) * S, kLdsB / kWave));
+      launch_tile(h, kern, dim3(grid), dim3(kLdsB), (uint32_t)(lw * 4), st, (const Wl*)(h->d_wl + b),
+                  (int64_t)(e - b), (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, x,
+                  (int32_t)h->tile_col_begin[t], (int32_t)lw, y, h->d_partial);
+      continue;
+    }
     launch_tile(h, pick_slices(S, k_tile_spmv<1>, k_tile_spmv<2>, k_tile_spmv<4>, k_tile_spmv<8>),
                 dim3(nblk((e - b) * S, kWpb)), dim3(kB), 0, st, (const Wl*)(h->d_wl + b), (int64_t)(e - b),
                 (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, x, y, h->d_partial);

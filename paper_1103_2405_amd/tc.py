@@ -44,7 +44,9 @@ class CBuildOpts(ctypes.Structure):
     _fields_ = [("tile_width", i32), ("n_tiles", i32), ("wl_policy", i32), ("wl_all", i32),
                 ("wl_per_tile", vp), ("n_wl_per_tile", i32), ("wave", i32), ("split_len", i32),
                 ("camping_pad", i32), ("relabel", i32), ("max_act_warp", i32), ("xcd_groups", i32), ("kernel", i32),
-                ("value_map", i32), ("slices", i32), ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
+                ("value_map", i32), ("slices", i32), ("tile_bounds", vp), ("n_tile_bounds", i32),
+                ("lds_stage", i32),
+                ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
 
 
 class CInfo(ctypes.Structure):
@@ -211,7 +213,8 @@ class TiledMatrix:
     def __init__(self, csr, tile_width: int = 0, n_tiles: int = -1, wl: Optional[Sequence[int] | int] = None,
                  wave: int = 64, split_len: int = -1, camping_pad: bool = False, relabel: int = -1,
                  max_act_warp: int = 0, perf_table: Optional[str] = "default", xcd_groups: int = -1,
-                 kernel: str = "composite", value_map: bool = False, slices: int = 0, stream=None):
+                 kernel: str = "composite", value_map: bool = False, slices: int = 0,
+                 tile_bounds: Optional[Sequence[int]] = None, lds_stage: int = 0, stream=None):
         lib = load_library()
         A = csr if isinstance(csr, DeviceCsr) else DeviceCsr(csr)
         self.n_rows, self.n_cols, self.nnz = A.n_rows, A.n_cols, A.nnz
@@ -226,6 +229,11 @@ class TiledMatrix:
         o.kernel = 1 if kernel == "coo" else 0
         o.value_map = int(bool(value_map))
         o.slices = int(slices)
+        o.lds_stage = int(lds_stage)
+        keep_b = None
+        if tile_bounds is not None and len(tile_bounds) > 0:
+            keep_b = (ctypes.c_int32 * len(tile_bounds))(*[int(v) for v in tile_bounds])
+            o.tile_bounds, o.n_tile_bounds = ctypes.cast(keep_b, vp), len(tile_bounds)
         keep = None
         if wl is None:
             o.wl_policy = 0
@@ -243,7 +251,7 @@ class TiledMatrix:
         _check(lib.tc_build_tiled(ctypes.byref(c), ctypes.byref(o), _stream(stream), ctypes.byref(h)),
                "tc_build_tiled")
         self._h = h
-        del keep
+        del keep, keep_b
 
     # -- lifetime
     def close(self):

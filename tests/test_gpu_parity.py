@@ -49,16 +49,16 @@ def assert_same_format(g, r):
 
 
 def build_both(csr, W, wl=None, S=64, split_len=-1, n_tiles=-1, camping_pad=False, table_path=None,
-               max_act_warp=8192, xcd_groups=0, kernel="composite"):
+               max_act_warp=8192, xcd_groups=0, kernel="composite", bounds=None):
     say("build", csr[0], csr[1], len(csr[3]), "W", W, "wl", wl if not isinstance(wl, list) else wl[:3], "S", S,
         "split", split_len)
     wl_list = wl if wl is None or isinstance(wl, list) else [wl] * 4096
     ref = rf.build(csr, W=W, n_tiles=n_tiles, wl=wl_list, S=S, split_len=split_len, camping_pad=camping_pad,
                    table=PerfTable.load(table_path) if table_path else None, max_act_warp=max_act_warp,
-                   xcd_groups=xcd_groups, coo=kernel == "coo")
+                   xcd_groups=xcd_groups, coo=kernel == "coo", bounds=bounds)
     gm = TiledMatrix(csr, tile_width=W, n_tiles=n_tiles, wl=wl, wave=S, split_len=split_len,
                      camping_pad=camping_pad, perf_table=table_path, max_act_warp=max_act_warp,
-                     xcd_groups=xcd_groups, kernel=kernel)
+                     xcd_groups=xcd_groups, kernel=kernel, tile_bounds=bounds)
     return gm, ref
 
 
@@ -654,3 +654,62 @@ def test_row_slices_do_not_change_results(W, split, wave):
     xs = x.cpu().numpy()
     yy = ys[0].cpu().numpy().astype(np.float64)
     assert np.all(np.abs(yy - oracle.spmv(csr, xs)) <= TOL * oracle.absmv(csr, xs))
+
+
+@pytest.mark.parametrize("bounds,wl,split", [([300, 2000, 6000], 512, 256), ([16384], 2048, -1),
+                                             ([64, 4096], 300, 64), ([1000, 1001, 9000, 16384], 1024, 128)])
+def test_tiles_of_given_widths(bounds, wl, split):
+    # tiles of different widths: the format bit for bit against the reference
+    # builder, products within the bound, bit-exact on dyadic inputs, and
+    # PageRank iterates against the oracle
+    g = gg.rmat(14, 16, seed=14)
+    csr = gg.pagerank_matrix(g)
+    gm, ref = build_both(csr, W=4096, wl=wl, split_len=split, bounds=bounds)
+    fmt = gm.export_format()
+    assert_same_format(fmt, ref)
+    check_spmv(gm, csr, gg.uniform_f32(g.n, 101))
+    p, _, _ = gm.pagerank(0.85, 0.0, 30)
+    pref, _, _ = oracle.pagerank(csr, 0.85, 0.0, 30)
+    assert np.abs(p.cpu().numpy() - pref).sum() <= 1e-6
+    gm.close()
+    dy = gg.random_csr(3000, 3000, 0.004, 5, values="dyadic", power=1.2)
+    x = ((np.arange(3000) * 7 + 5) % 7 - 3).astype(np.float32)
+    gm2 = TiledMatrix(dy, wl=wl, split_len=split, tile_bounds=[b for b in bounds if b < 3000] or [3000])
+    check_spmv(gm2, dy, x, exact=True)
+    gm2.close()
+
+
+def test_tile_bounds_rejected_when_invalid():
+    csr = gg.pagerank_matrix(gg.rmat(9, 8, seed=2))
+    for bad in ([0], [10, 10], [20, 10], [csr[1] + 1]):
+        with pytest.raises(TcError):
+            TiledMatrix(csr, tile_bounds=bad)
+
+
+@pytest.mark.parametrize("bounds,wl,split,S", [([4096], 512, 128, 0), ([32768], 1024, 256, 4), ([333, 9000], 300, 64, 2),
+                                               ([1024, 2048, 3072], 2048, -1, 1)])
+def test_lds_staged_tiles(bounds, wl, split, S):
+    # tiles whose x segment is staged in LDS (forced on every tile that fits):
+    # the same format as without staging, the products bit-identical to the
+    # cache-gather kernel's, within the oracle's bound and bit-exact on
+    # dyadic inputs; PageRank iterates against the oracle
+    g = gg.rmat(15, 16, seed=15)
+    csr = gg.pagerank_matrix(g)
+    x = torch.from_numpy(gg.uniform_f32(g.n, 101)).cuda()
+    a = TiledMatrix(csr, wl=wl, split_len=split, tile_bounds=bounds, lds_stage=1, slices=S)
+    b = TiledMatrix(csr, wl=wl, split_len=split, tile_bounds=bounds, lds_stage=-1, slices=S)
+    ya, yb = a.spmv(x), b.spmv(x)
+    assert torch.equal(ya, yb)
+    xs = x.cpu().numpy()
+    assert np.all(np.abs(ya.cpu().numpy().astype(np.float64) - oracle.spmv(csr, xs)) <= TOL * oracle.absmv(csr, xs))
+    pa = a.pagerank(0.85, 0.0, 25)[0]
+    assert torch.equal(pa, b.pagerank(0.85, 0.0, 25)[0])
+    pref, _, _ = oracle.pagerank(csr, 0.85, 0.0, 25)
+    assert np.abs(pa.cpu().numpy() - pref).sum() <= 1e-6
+    a.close()
+    b.close()
+    dy = gg.random_csr(50000, 50000, 0.0004, 6, values="dyadic", power=1.3)
+    xd = ((np.arange(50000) * 7 + 6) % 7 - 3).astype(np.float32)
+    gm = TiledMatrix(dy, wl=wl, split_len=split, tile_bounds=bounds, lds_stage=1, slices=S)
+    check_spmv(gm, dy, xd, exact=True)
+    gm.close()

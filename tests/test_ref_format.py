@@ -77,7 +77,7 @@ def check_invariants(csr, fmt):
     b, e = fmt["tile_col_begin"], fmt["tile_col_end"]
     if len(b):
         assert b[0] == 0 and e[-1] == n_cols and np.all(b[1:] == e[:-1])
-    if not fmt.get("xcd_groups"):
+    if not fmt.get("xcd_groups") and not fmt.get("bounds"):
         for t in range(fmt["T"]):
             assert b[t] == t * fmt["W"]
             assert cs[b[t]] >= 2 or fmt["T"] == 0
@@ -253,3 +253,29 @@ def test_coo_arrays_follow_the_bucketed_order():
     want = sorted(zip(f["rowmap"][rows].tolist(), f["cpos"][col].tolist(), val.view(np.uint32).tolist()))
     got = sorted(zip(row.tolist(), f["coo_col"].tolist(), f["coo_val"].view(np.uint32).tolist()))
     assert want == got
+
+
+@pytest.mark.parametrize("seed,bounds,wl,split", [(0, [5, 37, 120], 64, 0), (1, [300], 40, 16),
+                                                  (2, [1, 2, 3, 250], 30, -1), (3, [64, 128], 200, 32)])
+def test_tiles_of_given_widths(seed, bounds, wl, split):
+    # tiles of different widths (one per cache level): the invariants, the
+    # exact round trip, and each tile's columns exactly its given range
+    csr = gg.random_csr(300, 300, 0.03, seed, power=1.2)
+    fmt = rf.build(csr, W=16, wl=[wl] * 8, S=64, split_len=split, bounds=bounds)
+    check_invariants(csr, fmt)
+    want_b = [0] + bounds[:-1] if bounds[-1] == 300 else [0] + bounds
+    assert list(fmt["tile_col_begin"]) == want_b
+    assert fmt["T"] == len(bounds)
+    x = gg.uniform_f32(300, seed)
+    assert np.allclose(rf.spmv_format(fmt, x), oracle.spmv(csr, x), rtol=1e-12, atol=1e-14)
+
+
+def test_given_bounds_at_a_fixed_width_equal_algorithm_1_tiles():
+    # bounds every W columns reproduce the fixed-width tiles exactly
+    csr = gg.random_csr(400, 400, 0.02, 9, power=1.1)
+    a = rf.build(csr, W=50, n_tiles=3, wl=[77] * 8, S=64, split_len=20)
+    b = rf.build(csr, W=999, wl=[77] * 8, S=64, split_len=20, bounds=[50, 100, 150])
+    for k in a:
+        if isinstance(a[k], np.ndarray):
+            assert np.array_equal(a[k], b[k]), k
+    assert a["T"] == b["T"] == 3
