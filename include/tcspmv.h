@@ -112,6 +112,20 @@ typedef struct {
                                  x segment staged in LDS by a persistent kernel, so its gathers
                                  are LDS reads; 1: every tile that fits is staged; -1: every
                                  tile gathers x through the caches */
+  int32_t panels;             /* row panels (MI355X reading of Section 3.2's row partition, applied
+                                 to the workgroups of one GPU): 0 (default) = none; -1 = about
+                                 4096 rows per panel, at most two panels per compute unit; P > 0 =
+                                 P panels.  Internal rows are cut into contiguous panels of at
+                                 most panel_rows rows holding about equal numbers of the entries
+                                 that stay with their row (a segment longer than its column
+                                 tile's split length is chunked and belongs to no panel); every
+                                 (panel, column tile) pair is a tile of the format, panel-major.
+                                 One workgroup per panel keeps the panel's y in LDS and sweeps
+                                 the column tiles in order.  Not with xcd_groups or kernel = 1 */
+  int32_t panel_rows;         /* most rows of a panel; 0 = half the LDS of a compute unit, in
+                                 floats (20480 on gfx950); at most one workgroup's LDS */
+  int32_t panel_waves;        /* wavefronts of a panel's workgroup (4, 8 or 16; 0 = 16), also the
+                                 resident-wavefront count of the model (Eq. 1) for panel tiles */
   const char* perf_table;     /* path of a throughput table for the model; NULL = built-in */
   /* optional device allocator for the handle's buffers; NULL = hipMalloc / hipFree */
   void* (*alloc)(size_t bytes, void* ctx);
@@ -137,6 +151,11 @@ typedef struct {
   double build_us;            /* wall time of tc_build_tiled */
   double model_us;            /* Eq. 1-5 prediction for one product with the built workload sizes, summed
                                  over tiles (microseconds; the throughput table is in entries per us) */
+  int32_t n_panels;           /* row panels (0 = none); tile g is panel g / n_col_tiles, column
+                                 tile g % n_col_tiles */
+  int32_t n_col_tiles;        /* column tiles (dense tiles plus the sparse tile) */
+  int32_t panel_rows;         /* most rows per panel used by the build (0 without panels) */
+  int32_t panel_waves;        /* wavefronts per panel workgroup (0 without panels) */
 } tc_info;
 
 /* Host copies of the whole format, for checking it entry by entry.  The caller
@@ -170,6 +189,8 @@ typedef struct {
   int32_t* coo_row;           /* internal row id, bit 30 set when an earlier tile holds the row */
   int32_t* coo_col;           /* internal column id */
   float* coo_val;             /* value */
+  /* handles built with row panels only: */
+  int64_t* panel_begin;       /* [n_panels + 1] first internal row of each panel, then n_rows */
 } tc_format_view;
 
 /* Accumulated time of the tile kernels when timing is enabled (tc_set_timing). */
@@ -202,6 +223,14 @@ tc_status tc_spmv(const tc_handle* h, const float* d_x, float* d_y, tc_stream_t 
 
 /* y := A x with x and y in the handle's internal ids (no permutation). */
 tc_status tc_spmv_internal(const tc_handle* h, const float* d_x, float* d_y, tc_stream_t stream);
+
+/* As tc_spmv_internal, but always one launch per tile in tile order (the
+ * paper's scheme of one kernel per tile, Section 3.1), also for a handle built
+ * with row panels, whose products otherwise run as one row-panel launch.  Both
+ * orders add each row's per-tile sums in the same order, so for a panel handle
+ * the two give the same bits; this call exists to check that.  Same arguments,
+ * ownership and errors as tc_spmv_internal. */
+tc_status tc_spmv_tiles(const tc_handle* h, const float* d_x, float* d_y, tc_stream_t stream);
 
 /* Y := A X for k right-hand sides: X is n_cols x k and Y n_rows x k, both
  * row-major, device, caller's index space; 1 <= k <= 256. */

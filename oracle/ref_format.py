@@ -48,10 +48,47 @@ def xcd_boundaries(clen_sorted: np.ndarray, W: int, groups: int) -> list:
     return bounds
 
 
+def panel_weights(n_rows: int, irow: np.ndarray, ctile: np.ndarray, csplit: Sequence[int]) -> np.ndarray:
+    """Entries of each internal row that stay with the row: the row's segment
+    in a column tile counts unless the tile's split length cuts it into chunks
+    (chunks are not tied to a panel)."""
+    if irow.size == 0:
+        return np.zeros(n_rows, np.int64)
+    key = ctile.astype(np.int64) * n_rows + irow
+    u, cnt = np.unique(key, return_counts=True)
+    t, r = u // n_rows, u % n_rows
+    sp = np.asarray(csplit, np.int64)[t]
+    keep = (sp == 0) | (cnt <= sp)
+    return np.bincount(r[keep], weights=cnt[keep], minlength=n_rows).astype(np.int64)
+
+
+def panel_bounds(weight: np.ndarray, panels: int, max_rows: int) -> list:
+    """Row panels: contiguous ranges of internal rows, panel p ending at the
+    first row where the running weight reaches ceil((p+1) total / panels),
+    each at least one row and at most max_rows; rows left after `panels`
+    panels go into further panels of max_rows."""
+    n = len(weight)
+    if max_rows <= 0:
+        raise ValueError("panel_rows must be positive")
+    pre = np.concatenate([[0], np.cumsum(weight, dtype=np.int64)])
+    total = int(pre[-1])
+    b = [0]
+    for p in range(panels):
+        if b[-1] >= n:
+            break
+        tgt = -(-((p + 1) * total) // panels)
+        lb = int(np.searchsorted(pre, tgt, side="left"))
+        b.append(min(max(lb, b[-1] + 1), b[-1] + max_rows, n))
+    while b[-1] < n:
+        b.append(min(b[-1] + max_rows, n))
+    return b
+
+
 def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S: int = 64,
           split_len: int = -1, camping_pad: bool = False, relabel: Optional[bool] = None,
           table: Optional[PerfTable] = None, max_act_warp: int = 8192, xcd_groups: int = 0,
-          coo: bool = False, bounds: Optional[Sequence[int]] = None) -> dict:
+          coo: bool = False, bounds: Optional[Sequence[int]] = None, panels: int = 0,
+          panel_rows: int = 0, panel_waves: int = 16) -> dict:
     n_rows, n_cols, rp, col, val = csr
     rp = np.asarray(rp, np.int64)
     col = np.asarray(col, np.int32)
@@ -99,6 +136,17 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
     row_of = np.repeat(np.arange(n_rows, dtype=np.int64), np.diff(rp))
     icol = cpos[col] if nnz else np.zeros(0, np.int64)
     tile_of = np.searchsorted(starts, icol, side="right") if nnz else np.zeros(0, np.int64)
+    NT = ntiles  # column tiles
+    ccount = np.bincount(tile_of, minlength=NT) if nnz else np.zeros(NT, np.int64)
+    csplit = [tile_split_len(split_len, int(ccount[t]), max_act_warp, S) for t in range(NT)]
+    pb = None
+    if panels > 0:
+        # row panels: tile g = panel * NT + column tile
+        pb = panel_bounds(panel_weights(n_rows, rmap[row_of], tile_of, csplit), panels, panel_rows)
+        prow = np.searchsorted(pb, rmap[row_of], side="right") - 1 if nnz else np.zeros(0, np.int64)
+        tile_of = prow * NT + tile_of
+        ranges = [ranges[g % NT] for g in range((len(pb) - 1) * NT)]
+        ntiles = len(ranges)
     order = np.argsort(tile_of, kind="stable")
     tcount = np.bincount(tile_of, minlength=ntiles) if nnz else np.zeros(ntiles, np.int64)
     tstart = np.concatenate([[0], np.cumsum(tcount)])
@@ -127,13 +175,14 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
         tile_row_off.append(tile_row_off[-1] + len(srow))
         seg_lists.append((tstart[t] + sstart, slen, srow))
         # a6: workload size and partition
-        kind = "dense" if t < T else "sparse"
-        split_t = tile_split_len(split_len, int(tcount[t]), max_act_warp, S)
+        kind = "dense" if t % NT < T else "sparse"
+        split_t = csplit[t % NT]
         split_used.append(split_t)
         if wl is not None:
             WLt = int(wl[t])
         elif table is not None:
-            WLt = choose_wl(slen.tolist(), int(tcount[t]), table, kind, max_act_warp, S, split_t)
+            WLt = choose_wl(slen.tolist(), int(tcount[t]), table, kind, panel_waves if pb is not None else max_act_warp,
+                            S, split_t)
         else:
             raise ValueError("give wl or a table")
         wl_used.append(WLt)
@@ -208,7 +257,8 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
         **extra,
         n_rows=n_rows, n_cols=n_cols, nnz=nnz, W=W, S=S, split_len=split_len, T=T, xcd_groups=xcd_groups, bounds=list(bounds) if bounds else None,
         tile_split=np.asarray(split_used, np.int64),
-        n_tiles_total=ntiles, relabel=bool(relabel),
+        n_tiles_total=ntiles, relabel=bool(relabel), n_col_tiles=NT,
+        panel_begin=None if pb is None else np.asarray(pb, np.int64), panel_rows=panel_rows, panel_waves=panel_waves,
         clen=clen, cperm=cperm.astype(np.int32), cpos=cpos.astype(np.int32),
         rowmap=rmap.astype(np.int32),
         tile_col_begin=np.asarray([r[0] for r in ranges], np.int64),

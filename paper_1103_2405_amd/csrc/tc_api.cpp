@@ -42,6 +42,10 @@ extern "C" tc_status tc_handle_info(const tc_handle* h, tc_info* info) {
   info->device_bytes = bytes;
   info->build_us = h->build_us;
   info->model_us = h->model_us;
+  info->n_panels = h->n_panels;
+  info->n_col_tiles = h->n_col_tiles;
+  info->panel_rows = h->panel_rows;
+  info->panel_waves = h->panel_waves;
   return TC_OK;
 }
 
@@ -92,6 +96,8 @@ extern "C" tc_status tc_export_format(const tc_handle* h, tc_format_view* v) {
     if (v->tile_wl) v->tile_wl[t] = h->tile_wl[t];
     if (v->tile_split) v->tile_split[t] = h->tile_split[t];
   }
+  if (v->panel_begin)
+    for (size_t p = 0; p < h->panel_begin.size(); ++p) v->panel_begin[p] = h->panel_begin[p];
   if (v->tile_row_off)
     for (int t = 0; t <= h->n_tiles; ++t) v->tile_row_off[t] = h->tile_row_off.empty() ? 0 : h->tile_row_off[t];
   for (int64_t j = 0; j < h->n_wl; ++j) {

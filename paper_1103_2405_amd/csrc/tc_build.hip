@@ -506,6 +506,50 @@ __global__ void k_first_touch(const int32_t* __restrict__ seg_tile, const int32_
   if (!(sp > 0 && (int64_t)seg_len[s] > sp)) atomicMin(&first[r], t);
 }
 
+// Row panels: entries of each row that stay with the row (segments no
+// longer than their column tile's split length; longer ones become chunks).
+__global__ void k_panel_weight(const int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_len,
+                               const int32_t* __restrict__ seg_row, int64_t nseg, const int64_t* __restrict__ split_t,
+                               int32_t* __restrict__ w) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  const int64_t sp = split_t[seg_tile[s]];
+  if (!(sp > 0 && (int64_t)seg_len[s] > sp)) atomicAdd(&w[seg_row[s]], seg_len[s]);
+}
+
+// first i in [0, n] with pre[i] >= tgt[p] (pre non-decreasing, n + 1 entries)
+__global__ void k_lower_bound_pre(const int64_t* __restrict__ pre, int64_t n, const int64_t* __restrict__ tgt, int P,
+                                  int64_t* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (pre[mid] < tgt[p]) lo = mid + 1; else hi = mid;
+  }
+  out[p] = lo;
+}
+
+// tile of a segment with row panels: panel of its row * column tiles + column tile
+__global__ void k_seg_panel(int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_row, int64_t nseg,
+                            const int32_t* __restrict__ pb, int32_t np, int32_t nct) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  const int32_t r = seg_row[s];
+  int32_t lo = 0, hi = np - 1;  // last panel with pb[p] <= r
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (pb[mid] <= r) lo = mid; else hi = mid - 1;
+  }
+  seg_tile[s] = lo * nct + seg_tile[s];
+}
+
+__global__ void k_tile_entries(const int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_len, int64_t nseg,
+                               unsigned long long* __restrict__ tnnz) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nseg) atomicAdd(&tnnz[seg_tile[s]], (unsigned long long)seg_len[s]);
+}
+
 __global__ void k_ne(const int32_t* __restrict__ a, int64_t n, int32_t v, int32_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a[i] != v;
@@ -1013,8 +1057,84 @@ void check_descriptors(const std::vector<Wl>& dwl, const std::vector<HostWl>& wl
   }
 }
 
+// compute units and LDS of the current device
+void device_limits(tc_handle* h) {
+  int dev = 0, cus = 0;
+  HIPX(hipGetDevice(&dev));
+  HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  h->n_cu = cus > 0 ? cus : 256;
+  // LDS a workgroup may use (the opt-in limit) and LDS per compute unit
+  int blk = 0, optin = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) blk = 65536;
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
+  if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+    per_cu = 0;
+  (void)hipGetLastError();
+  const int64_t wg = std::max(blk, optin);
+  h->lds_cu_bytes = per_cu > 0 ? per_cu : wg;
+  h->lds_floats = std::min<int64_t>(std::min<int64_t>(wg, h->lds_cu_bytes) / 4, kLdsMaxFloats);
+}
+
+// Row panels (MI355X reading of the row partition of Section 3.2, with the
+// workgroups of one GPU in place of GPUs).  Given the (column tile, row)
+// segments: each row's weight is its entries in segments that are not split
+// into chunks; panel p ends at the first row where the running weight reaches
+// ceil((p + 1) total / P), holding at least one and at most `rows` rows, and
+// rows left after P panels go into further panels of `rows`.  Segment tiles
+// become panel * n_col_tiles + column tile.  Returns the panel bounds.
+std::vector<int64_t> make_panels(int32_t* seg_tile, const int32_t* seg_row, const int32_t* seg_len, int64_t nseg,
+                                 int64_t n_rows, const int64_t* d_split_col, int32_t P, int64_t rows, int32_t nct,
+                                 Tmp& tmp, hipStream_t st) {
+  std::vector<int64_t> pb{0};
+  if (n_rows == 0) return pb;
+  int32_t* w = tmp.get<int32_t>(n_rows);
+  HIPX(hipMemsetAsync(w, 0, sizeof(int32_t) * n_rows, st));
+  if (nseg > 0) {
+    hipLaunchKernelGGL(k_panel_weight, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg,
+                       d_split_col, w);
+    HIPX(hipGetLastError());
+  }
+  int64_t* pre = tmp.get<int64_t>(n_rows + 1);
+  const int64_t total = excl_scan<int32_t, int64_t>(w, n_rows, pre, tmp, st);
+  HIPX(hipMemcpyAsync(pre + n_rows, &total, sizeof(int64_t), hipMemcpyHostToDevice, st));
+  std::vector<int64_t> tgt(P), lb(P);
+  for (int32_t p = 0; p < P; ++p) tgt[p] = ((int64_t)(p + 1) * total + P - 1) / P;
+  int64_t* d_tgt = tmp.get<int64_t>(P);
+  int64_t* d_lb = tmp.get<int64_t>(P);
+  HIPX(hipMemcpyAsync(d_tgt, tgt.data(), sizeof(int64_t) * P, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_lower_bound_pre, dim3(nblk(P, kB)), dim3(kB), 0, st, (const int64_t*)pre, n_rows,
+                     (const int64_t*)d_tgt, P, d_lb);
+  HIPX(hipGetLastError());
+  HIPX(hipMemcpyAsync(lb.data(), d_lb, sizeof(int64_t) * P, hipMemcpyDeviceToHost, st));
+  HIPX(hipStreamSynchronize(st));
+  for (int32_t p = 0; p < P && pb.back() < n_rows; ++p)
+    pb.push_back(std::min(std::min(std::max(lb[p], pb.back() + 1), pb.back() + rows), n_rows));
+  while (pb.back() < n_rows) pb.push_back(std::min(pb.back() + rows, n_rows));
+  const int32_t np = (int32_t)pb.size() - 1;
+  if ((int64_t)np * nct >= ((int64_t)1 << 24)) throw Fail{TC_EUNSUPPORTED, "too many (panel, column tile) tiles"};
+  std::vector<int32_t> pb32(pb.begin(), pb.end());
+  int32_t* d_pb = tmp.get<int32_t>(np + 1);
+  HIPX(hipMemcpyAsync(d_pb, pb32.data(), sizeof(int32_t) * (np + 1), hipMemcpyHostToDevice, st));
+  if (nseg > 0) {
+    hipLaunchKernelGGL(k_seg_panel, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_row, nseg,
+                       (const int32_t*)d_pb, np, nct);
+    HIPX(hipGetLastError());
+  }
+  HIPX(hipStreamSynchronize(st));
+  return pb;
+}
+
 void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h) {
   PhaseClock clk(st);
+  device_limits(h);
+  if (h->n_panels != 0) {
+    const int64_t wg_floats = h->lds_floats;
+    if (h->panel_rows == 0) h->panel_rows = (int32_t)std::min<int64_t>(wg_floats, h->lds_cu_bytes / 8);
+    if (h->panel_rows > wg_floats)
+      throw Fail{TC_EINVAL, "panel_rows exceeds the LDS of one workgroup (" + std::to_string(wg_floats) + " floats)"};
+    if (h->n_panels < 0)  // automatic: panels of about 4096 rows, at most two per compute unit
+      h->n_panels = (int32_t)std::max<int64_t>(1, std::min<int64_t>((A->n_rows + 4095) / 4096, 2 * (int64_t)h->n_cu));
+  }
   const int64_t n_rows = A->n_rows, n_cols = A->n_cols, nnz = A->nnz;
   Tmp tmp(st);
   h->stream = st;
@@ -1217,7 +1337,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   for (int t = 0; t < ntiles; ++t) h->tile_nnz[t] = tstart[t + 1] - tstart[t];
   h->tile_split.assign(ntiles, 0);
   for (int t = 0; t < ntiles; ++t) h->tile_split[t] = tile_split_len(h->split_len, h->tile_nnz[t], h->max_act_warp, h->S);
-  int64_t* d_split_t = tmp.get<int64_t>(ntiles);
+  int64_t* d_split_t = tmp.get<int64_t>(std::max(ntiles, 1));
   if (ntiles > 0)
     HIPX(hipMemcpyAsync(d_split_t, h->tile_split.data(), sizeof(int64_t) * ntiles, hipMemcpyHostToDevice, st));
   int32_t* first = tmp.get<int32_t>(n_rows);
@@ -1271,6 +1391,36 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       tmp.release(flags);
       tmp.release(pos);
     }
+    if (h->n_panels > 0) {
+      // row panels: every (panel, column tile) pair becomes a tile, panel-major
+      const int32_t nct = ntiles;
+      h->panel_begin = make_panels(seg_tile, seg_row, seg_len, nseg, n_rows, d_split_t, h->n_panels,
+                                   h->panel_rows, nct, tmp, st);
+      h->n_panels = (int32_t)h->panel_begin.size() - 1;
+      h->n_col_tiles = nct;
+      ntiles = h->n_panels * nct;
+      h->n_tiles = ntiles;
+      std::vector<int64_t> cb = h->tile_col_begin, ce = h->tile_col_end, csp = h->tile_split;
+      h->tile_col_begin.resize(ntiles);
+      h->tile_col_end.resize(ntiles);
+      h->tile_split.resize(ntiles);
+      for (int g = 0; g < ntiles; ++g) {
+        h->tile_col_begin[g] = cb[g % nct];
+        h->tile_col_end[g] = ce[g % nct];
+        h->tile_split[g] = csp[g % nct];
+      }
+      unsigned long long* d_tn = tmp.get<unsigned long long>(ntiles);
+      HIPX(hipMemsetAsync(d_tn, 0, sizeof(unsigned long long) * ntiles, st));
+      hipLaunchKernelGGL(k_tile_entries, dim3(nblk(nseg, kB)), dim3(kB), 0, st, (const int32_t*)seg_tile,
+                         (const int32_t*)seg_len, nseg, d_tn);
+      HIPX(hipGetLastError());
+      h->tile_nnz.assign(ntiles, 0);
+      HIPX(hipMemcpyAsync(h->tile_nnz.data(), d_tn, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, st));
+      d_split_t = tmp.get<int64_t>(ntiles);
+      HIPX(hipMemcpyAsync(d_split_t, h->tile_split.data(), sizeof(int64_t) * ntiles, hipMemcpyHostToDevice, st));
+      HIPX(hipStreamSynchronize(st));
+      trow.assign(ntiles + 1, 0);
+    }
     hipLaunchKernelGGL(k_first_touch, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg,
                        (const int64_t*)d_split_t, first, touched);
     HIPX(hipGetLastError());
@@ -1319,6 +1469,10 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipMemcpyAsync(run_len.data(), d_rl, sizeof(int32_t) * nruns, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
   }
+  if (nnz == 0 && h->n_panels > 0) {
+    h->n_panels = 0;
+    h->n_col_tiles = 0;
+  }
   h->d_rows_sorted = rows_sorted;
   h->d_rows_len = rows_len;
   h->n_rows_sorted = nseg;
@@ -1333,7 +1487,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   } else {
     default_perf_table(&table);
   }
-  PartitionParams pp{h->S, h->split_len, h->max_act_warp, h->camping_pad};
+  PartitionParams pp{h->S, h->split_len, h->n_panels > 0 ? (int64_t)h->panel_waves : h->max_act_warp,
+                     h->camping_pad};
   h->tile_wl.assign(ntiles, 0);
   h->tile_wl_begin.assign(ntiles + 1, 0);
   std::vector<HostWl>& wls = h->wls;
@@ -1348,6 +1503,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     }
     const int64_t split_t = h->tile_split[t];
     pp.split_len = (int32_t)split_t;
+    const bool sparse_t = (h->n_panels > 0 ? t % h->n_col_tiles : t) >= T;
     int64_t WLt;
     if (o->wl_policy == 1) {
       if (t >= o->n_wl_per_tile) throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
@@ -1355,11 +1511,11 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     } else if (o->wl_policy == 2) {
       WLt = o->wl_all;
     } else {
-      WLt = choose_wl(runs, h->tile_nnz[t], table, t >= T, pp);
+      WLt = choose_wl(runs, h->tile_nnz[t], table, sparse_t, pp);
     }
     if (WLt < 1) throw Fail{TC_EINVAL, "workload size must be >= 1"};
     h->tile_wl[t] = WLt;
-    if (!runs.empty()) h->model_us += model_time(runs, WLt, table, t >= T, pp);
+    if (!runs.empty()) h->model_us += model_time(runs, WLt, table, sparse_t, pp);
     h->tile_wl_begin[t] = (int64_t)wls.size();
     partition_tile(runs, WLt, t, trow[t], pp, &wls);
   }
@@ -1369,6 +1525,35 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
                       hipMemcpyHostToDevice, st));
   const int64_t nwl = (int64_t)wls.size();
   h->n_wl = nwl;
+  if (h->n_panels > 0) {
+    // panel pass metadata: each tile's leading chunk workloads run on any
+    // workgroup (their sums go to partial slots), listed per column tile
+    const int32_t nct = h->n_col_tiles;
+    std::vector<int64_t> ncb(ntiles), cbv(nct + 1, 0), chunks;
+    for (int g = 0; g < ntiles; ++g) {
+      int64_t j = h->tile_wl_begin[g];
+      while (j < h->tile_wl_begin[g + 1] && wls[j].chunk >= 0) ++j;
+      ncb[g] = j;
+    }
+    for (int t = 0; t < nct; ++t) {
+      cbv[t] = (int64_t)chunks.size();
+      for (int p = 0; p < h->n_panels; ++p)
+        for (int64_t j = h->tile_wl_begin[p * nct + t]; j < ncb[p * nct + t]; ++j) chunks.push_back(j);
+    }
+    cbv[nct] = (int64_t)chunks.size();
+    std::vector<int32_t> pb32(h->panel_begin.begin(), h->panel_begin.end());
+    h->d_panel_ncb = hold<int64_t>(h, std::max<int64_t>(ntiles, 1));
+    h->d_panel_cb = hold<int64_t>(h, nct + 1);
+    h->d_panel_chunks = hold<int64_t>(h, std::max<int64_t>((int64_t)chunks.size(), 1));
+    h->d_panel_begin = hold<int32_t>(h, h->n_panels + 1);
+    HIPX(hipMemcpyAsync(h->d_panel_ncb, ncb.data(), sizeof(int64_t) * ntiles, hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(h->d_panel_cb, cbv.data(), sizeof(int64_t) * (nct + 1), hipMemcpyHostToDevice, st));
+    if (!chunks.empty())
+      HIPX(hipMemcpyAsync(h->d_panel_chunks, chunks.data(), sizeof(int64_t) * chunks.size(), hipMemcpyHostToDevice,
+                          st));
+    HIPX(hipMemcpyAsync(h->d_panel_begin, pb32.data(), sizeof(int32_t) * pb32.size(), hipMemcpyHostToDevice, st));
+    HIPX(hipStreamSynchronize(st));  // host vectors above go out of scope
+  }
 
   // split rows: slots grouped by row, in (tile, chunk) order
   std::vector<int64_t> chunk_wl;
@@ -1523,22 +1708,6 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->d_ybuf = hold<float>(h, std::max(n_rows, n_cols));
   h->d_red = hold<double>(h, 4096);
   h->d_counters = hold<unsigned long long>(h, std::max<int64_t>(ntiles, 1));
-  {
-    int dev = 0, cus = 0;
-    HIPX(hipGetDevice(&dev));
-    HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    h->n_cu = cus > 0 ? cus : 256;
-    // LDS a workgroup may use (the opt-in limit) and LDS per compute unit
-    int blk = 0, optin = 0, per_cu = 0;
-    if (hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) blk = 65536;
-    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
-    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
-      per_cu = 0;
-    (void)hipGetLastError();
-    const int64_t wg = std::max(blk, optin);
-    h->lds_cu_bytes = per_cu > 0 ? per_cu : wg;
-    h->lds_floats = std::min<int64_t>(std::min<int64_t>(wg, h->lds_cu_bytes) / 4, kLdsMaxFloats);
-  }
   HIPX(hipStreamSynchronize(st));
   clk.mark("a7 pack + metadata");
 }
@@ -1603,7 +1772,9 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   }
   if (o->tile_width < 0 || o->wave < 0 || o->split_len < -1 || o->xcd_groups < 0 || o->xcd_groups > 64 || o->kernel < 0 || o->kernel > 1 || (o->kernel == 1 && o->xcd_groups > 0) || o->value_map < 0 || o->value_map > 1 || (o->value_map && o->kernel == 1) || o->max_act_warp < 0 || o->wl_policy < 0 ||
       !(o->slices == 0 || o->slices == 1 || o->slices == 2 || o->slices == 4 || o->slices == 8) ||
-      o->n_tile_bounds < 0 || o->lds_stage < -1 || o->lds_stage > 1 || (o->n_tile_bounds > 0 && (!o->tile_bounds || o->xcd_groups > 0)) ||
+      o->n_tile_bounds < 0 || o->lds_stage < -1 || o->lds_stage > 1 || o->panels < -1 || o->panel_rows < 0 ||
+      !(o->panel_waves == 0 || o->panel_waves == 4 || o->panel_waves == 8 || o->panel_waves == 16) ||
+      (o->panels != 0 && (o->xcd_groups > 0 || o->kernel == 1)) || (o->n_tile_bounds > 0 && (!o->tile_bounds || o->xcd_groups > 0)) ||
       o->wl_policy > 2 || (o->wl_policy == 1 && !o->wl_per_tile) || (o->relabel > 0 && A->n_rows != A->n_cols)) {
     set_error("tc_build_tiled: invalid option");
     return TC_EINVAL;
@@ -1633,6 +1804,9 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   h->kernel = o->kernel;
   h->slices = o->slices;
   h->lds_tiles = o->lds_stage + 1;  // 0 never, 1 automatic, 2 every tile that fits
+  h->n_panels = o->panels;
+  h->panel_rows = o->panels != 0 ? o->panel_rows : 0;
+  h->panel_waves = o->panels != 0 ? (o->panel_waves > 0 ? o->panel_waves : 16) : 0;
   h->alloc = o->alloc;
   h->dfree = o->free;
   h->alloc_ctx = o->alloc_ctx;

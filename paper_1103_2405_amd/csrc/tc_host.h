@@ -54,8 +54,9 @@ K pick_slices(int32_t s, K s1, K s2, K s4, K s8) {
 // caller adds them in its own pass); split rows are then added to y first.
 // skip_zero: y's empty rows are still zero from an earlier product into the
 // same y (nothing else writes them), so the zeroing launch can be left out.
+// tilewise: one launch per tile even for a handle with row panels.
 void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine = false,
-                   bool skip_zero = false);
+                   bool skip_zero = false, bool tilewise = false);
 // Y := A X for k right-hand sides in internal ids; epi: fused RWR restart.
 void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st, bool skip_empty = false,
                    const RwrEpi* epi = nullptr);

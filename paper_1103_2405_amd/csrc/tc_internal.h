@@ -149,6 +149,13 @@ struct tc_handle {
   int64_t lds_floats = 0;           // floats of x one workgroup can stage (device limit)
   int64_t lds_cu_bytes = 0;         // LDS bytes per compute unit
   int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
+  // row panels: tile g = panel g / n_col_tiles, column tile g % n_col_tiles
+  int32_t n_panels = 0, n_col_tiles = 0, panel_rows = 0, panel_waves = 0;
+  std::vector<int64_t> panel_begin;  // [n_panels + 1] internal rows
+  int32_t* d_panel_begin = nullptr;  // device copy (int32)
+  int64_t* d_panel_ncb = nullptr;    // [n_tiles] first workload of the tile that is not a split chunk
+  int64_t* d_panel_chunks = nullptr; // chunk workloads of every column tile, panel order
+  int64_t* d_panel_cb = nullptr;     // [n_col_tiles + 1] offsets into d_panel_chunks
   // value map (build option): the CSR entry of every padded slot, -1 for pads
   int32_t* d_vmap = nullptr;
   // TILE-COO (kernel == 1): every tile's entries in coordinate form

@@ -69,6 +69,102 @@ __global__ void __launch_bounds__(kLdsB) k_tile_lds(const Wl* __restrict__ wl, i
   }
 }
 
+// x of a row panel: gathers through the caches; the panel's rows of y sit in
+// LDS (ys[row - base]) and every tile adds its row sums there.  A panel row
+// is in at most one workload of a tile, and tiles are separated by barriers,
+// so each row's adds happen in tile order, as the first-touch product does
+// them (an add to the zeroed LDS row gives fl32(s), the first tile's store).
+struct PanelX {
+  const float* __restrict__ x;
+  float* ys;
+  int32_t base;
+  __device__ float operator()(int32_t i) const { return x[i]; }
+  __device__ void addy(float*, int32_t rid, double s) const {
+    float* q = ys + ((rid & ~kAddFlag) - base);
+    *q = (float)((double)*q + s);
+  }
+};
+
+// ... and column tile 0 of a panel handle with its x segment staged in LDS
+// (behind the panel's rows of y): its gathers are LDS reads.
+struct PanelLdsX {
+  const float* xs;
+  float* ys;
+  int32_t base;
+  __device__ float operator()(int32_t i) const { return xs[i]; }
+  __device__ void addy(float*, int32_t rid, double s) const {
+    float* q = ys + ((rid & ~kAddFlag) - base);
+    *q = (float)((double)*q + s);
+  }
+};
+
+// The workloads of column tile t for workgroup p: the tile's own workloads
+// that are not split chunks, then every np-th chunk workload of column tile t
+// over all panels (chunk sums go to partial slots, so any workgroup may run
+// them).
+template <int NW, class G>
+__device__ inline void panel_tile(const G& xg, int64_t g, int32_t t, int32_t p, int32_t np, int32_t wv, int lane,
+                                  const Wl* __restrict__ wl, const int64_t* __restrict__ wl_begin,
+                                  const int64_t* __restrict__ ncb, const int64_t* __restrict__ chunks,
+                                  const int64_t* __restrict__ cb, const int32_t* __restrict__ idx,
+                                  const float* __restrict__ val, const int32_t* __restrict__ rowid, float* y,
+                                  double* __restrict__ partial) {
+  const int64_t e = wl_begin[g + 1];
+  for (int64_t j = ncb[g] + wv; j < e; j += NW) run_workload<1>(wl[j], lane, idx, val, rowid, xg, y, partial);
+  const int64_t ce = cb[t + 1];
+  for (int64_t k = cb[t] + p + (int64_t)wv * np; k < ce; k += (int64_t)NW * np)
+    run_workload<1>(wl[chunks[k]], lane, idx, val, rowid, xg, y, partial);
+}
+
+// Row-panel pass (one launch per product).  Workgroup p owns internal rows
+// [pb[p], pb[p+1]) and keeps their y in LDS while it sweeps the column tiles
+// in order, a barrier after each.  All workgroups walk the column tiles in the
+// same order, so the x segment of the current tile is what the L2s hold; with
+// w0 > 0 column tile 0 (internal columns [0, w0), the hottest) is first copied
+// into LDS behind y (rows_cap floats in).  At the end the panel's y is stored
+// once, coalesced.
+template <int NW>
+__global__ void __launch_bounds__(NW * kWave) k_panel_spmv(const Wl* __restrict__ wl,
+                                                           const int64_t* __restrict__ wl_begin,
+                                                           const int64_t* __restrict__ ncb,
+                                                           const int64_t* __restrict__ chunks,
+                                                           const int64_t* __restrict__ cb, int32_t nct, int32_t np,
+                                                           const int32_t* __restrict__ pb, int32_t rows_cap,
+                                                           int32_t w0, const int32_t* __restrict__ idx,
+                                                           const float* __restrict__ val,
+                                                           const int32_t* __restrict__ rowid,
+                                                           const float* __restrict__ x, float* __restrict__ y,
+                                                           double* __restrict__ partial) {
+  extern __shared__ float ys[];
+  const int32_t p = blockIdx.x;
+  const int32_t r0 = pb[p], nr = pb[p + 1] - r0;
+  for (int32_t i = threadIdx.x; i < nr; i += NW * kWave) ys[i] = 0.0f;
+  float* xs = ys + rows_cap;  // rows_cap is a multiple of 4: 16-byte aligned
+  if (w0 > 0) {
+    const int32_t w4 = ((uintptr_t)x & 15) == 0 ? w0 & ~3 : 0;
+    for (int32_t k = 4 * (int32_t)threadIdx.x; k < w4; k += 4 * NW * kWave)
+      *(float4*)(xs + k) = *(const float4*)(x + k);
+    for (int32_t k = w4 + (int32_t)threadIdx.x; k < w0; k += NW * kWave) xs[k] = x[k];
+  }
+  __syncthreads();
+  const int lane = lane_id();
+  const int32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  int32_t t = 0;
+  if (w0 > 0 && nct > 0) {
+    panel_tile<NW>(PanelLdsX{xs, ys, r0}, (int64_t)p * nct, 0, p, np, wv, lane, wl, wl_begin, ncb, chunks, cb, idx,
+                   val, rowid, y, partial);
+    __syncthreads();
+    t = 1;
+  }
+  const PanelX xg{x, ys, r0};
+  for (; t < nct; ++t) {
+    panel_tile<NW>(xg, (int64_t)p * nct + t, t, p, np, wv, lane, wl, wl_begin, ncb, chunks, cb, idx, val, rowid, y,
+                   partial);
+    __syncthreads();
+  }
+  for (int32_t i = threadIdx.x; i < nr; i += NW * kWave) y[r0 + i] = ys[i];
+}
+
 // Concurrent pass over tiles 1..G of the XCD schedule.  Workgroups are
 // dispatched round-robin over the 8 XCDs, so block b runs on XCD b % 8: tile
 // 1 + (b % G) takes blocks b with that residue, and its x range stays in one
@@ -335,7 +431,42 @@ int64_t lds_tile_blocks(const tc_handle* h, int64_t lw) {
   return per_cu * h->n_cu;
 }
 
-void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine, bool skip_zero) {
+// Floats of x that the row-panel pass stages in LDS (column tile 0, when it
+// fits behind the panel's rows of y and staging is not turned off), else 0.
+int64_t panel_stage_width(const tc_handle* h) {
+  if (h->n_panels <= 0 || h->lds_tiles == 0 || h->n_col_tiles < 2) return 0;
+  const int64_t rows_cap = (h->panel_rows + 3) & ~3;
+  const int64_t w0 = h->tile_col_end[0] - h->tile_col_begin[0];
+  return rows_cap + w0 <= h->lds_floats ? w0 : 0;
+}
+
+// One launch of the row-panel pass: every row of y is stored by its panel.
+void panel_pass(tc_handle* h, const float* x, float* y, hipStream_t st) {
+  if (h->n_panels <= 0 || h->n_wl == 0) return;
+  const int64_t rows_cap = (h->panel_rows + 3) & ~3;
+  const int64_t w0 = panel_stage_width(h);
+  const uint32_t lds = (uint32_t)(4 * (rows_cap + w0));
+  auto kern = h->panel_waves == 4 ? k_panel_spmv<4> : h->panel_waves == 8 ? k_panel_spmv<8> : k_panel_spmv<16>;
+  if (lds > 65536) HIPC(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  launch_tile(h, kern, dim3((unsigned)h->n_panels), dim3((unsigned)(h->panel_waves * kWave)), lds, st,
+              (const Wl*)h->d_wl, (const int64_t*)h->d_tile_wl_begin, (const int64_t*)h->d_panel_ncb,
+              (const int64_t*)h->d_panel_chunks, (const int64_t*)h->d_panel_cb, (int32_t)h->n_col_tiles,
+              (int32_t)h->n_panels, (const int32_t*)h->d_panel_begin, (int32_t)rows_cap, (int32_t)w0,
+              (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, x, y, h->d_partial);
+}
+
+void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine, bool skip_zero,
+                   bool tilewise) {
+  if (h->n_panels > 0 && !tilewise) {
+    panel_pass(h, x, y, st);
+    if (h->n_split_rows > 0) {
+      hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
+                         h->n_split_rows, h->d_partial, y, 0);
+      HIPC(hipGetLastError());
+    }
+    h->spmv_calls++;
+    return;
+  }
   const bool xcd = h->xcd_groups > 0 && h->n_tiles > 1;
   const int64_t nzero = xcd ? h->n_zero0 : h->n_empty;
   const int64_t nz = std::max<int64_t>(nzero, h->n_tiles);
@@ -437,6 +568,15 @@ extern "C" tc_status tc_spmv_internal(const tc_handle* hc, const float* x, float
     if (!hc || (!x && hc->n_cols > 0) || (!y && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
     if ((const void*)x == (const void*)y && hc->n_rows > 0) throw Err{TC_EINVAL, "x and y must not alias"};
     spmv_internal(const_cast<tc_handle*>(hc), x, y, (hipStream_t)stream);
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_spmv_tiles(const tc_handle* hc, const float* x, float* y, tc_stream_t stream) {
+  return guarded("tc_spmv_tiles", [&]() -> tc_status {
+    if (!hc || (!x && hc->n_cols > 0) || (!y && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    if ((const void*)x == (const void*)y && hc->n_rows > 0) throw Err{TC_EINVAL, "x and y must not alias"};
+    spmv_internal(const_cast<tc_handle*>(hc), x, y, (hipStream_t)stream, false, false, true);
     return TC_OK;
   });
 }

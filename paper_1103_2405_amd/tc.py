@@ -45,7 +45,7 @@ class CBuildOpts(ctypes.Structure):
                 ("wl_per_tile", vp), ("n_wl_per_tile", i32), ("wave", i32), ("split_len", i32),
                 ("camping_pad", i32), ("relabel", i32), ("max_act_warp", i32), ("xcd_groups", i32), ("kernel", i32),
                 ("value_map", i32), ("slices", i32), ("tile_bounds", vp), ("n_tile_bounds", i32),
-                ("lds_stage", i32),
+                ("lds_stage", i32), ("panels", i32), ("panel_rows", i32), ("panel_waves", i32),
                 ("perf_table", ctypes.c_char_p), ("alloc", vp), ("free", vp), ("alloc_ctx", vp)]
 
 
@@ -55,7 +55,8 @@ class CInfo(ctypes.Structure):
                 ("xcd_groups", i32), ("kernel", i32), ("n_dense_tiles", i32), ("n_tiles", i32),
                 ("n_workloads", i64), ("nnz_pad", i64), ("n_rowid", i64), ("n_rows_sorted", i64),
                 ("n_split_rows", i64), ("n_partials", i64), ("n_dangling", i64), ("device_bytes", i64),
-                ("build_us", ctypes.c_double), ("model_us", ctypes.c_double)]
+                ("build_us", ctypes.c_double), ("model_us", ctypes.c_double),
+                ("n_panels", i32), ("n_col_tiles", i32), ("panel_rows", i32), ("panel_waves", i32)]
 
 
 _VIEW_FIELDS = [("cperm", np.int32, "n_cols"), ("rowmap", np.int32, "n_rows"),
@@ -72,7 +73,7 @@ _VIEW_FIELDS = [("cperm", np.int32, "n_cols"), ("rowmap", np.int32, "n_rows"),
                 ("wl_rowid_off", np.int64, "n_workloads"), ("idx", np.int32, "nnz_pad"),
                 ("val", np.float32, "nnz_pad"), ("rowid", np.int32, "n_rowid"),
                 ("coo_row", np.int32, "nnz_coo"), ("coo_col", np.int32, "nnz_coo"),
-                ("coo_val", np.float32, "nnz_coo")]
+                ("coo_val", np.float32, "nnz_coo"), ("panel_begin", np.int64, "n_panels+1")]
 
 
 class CFormatView(ctypes.Structure):
@@ -83,7 +84,7 @@ class CTiming(ctypes.Structure):
     _fields_ = [("tile_kernel_ms", ctypes.c_double), ("tile_launches", i64), ("spmv_calls", i64)]
 
 
-EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_internal", "tc_spmm",
+EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_internal", "tc_spmv_tiles", "tc_spmm",
             "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
             "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory",
             "tc_rwr_multi", "tc_csr_transpose", "tc_rwr_edge_weights", "tc_rwr_iterates", "tc_rwr_adjoint",
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.tc_build_tiled.argtypes = [P(CCsr), P(CBuildOpts), vp, P(vp)]
     lib.tc_spmv.argtypes = [vp, vp, vp, vp]
     lib.tc_spmv_internal.argtypes = [vp, vp, vp, vp]
+    lib.tc_spmv_tiles.argtypes = [vp, vp, vp, vp]
     lib.tc_spmm.argtypes = [vp, vp, vp, i32, vp]
     lib.tc_pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_float, i32, i32, vp, P(i32), P(ctypes.c_double), vp]
     lib.tc_hits.argtypes = [vp, ctypes.c_float, i32, i32, vp, vp, P(i32), P(ctypes.c_double), vp]
@@ -214,7 +216,8 @@ class TiledMatrix:
                  wave: int = 64, split_len: int = -1, camping_pad: bool = False, relabel: int = -1,
                  max_act_warp: int = 0, perf_table: Optional[str] = "default", xcd_groups: int = -1,
                  kernel: str = "composite", value_map: bool = False, slices: int = 0,
-                 tile_bounds: Optional[Sequence[int]] = None, lds_stage: int = 0, stream=None):
+                 tile_bounds: Optional[Sequence[int]] = None, lds_stage: int = 0, panels: int = 0,
+                 panel_rows: int = 0, panel_waves: int = 0, stream=None):
         lib = load_library()
         A = csr if isinstance(csr, DeviceCsr) else DeviceCsr(csr)
         self.n_rows, self.n_cols, self.nnz = A.n_rows, A.n_cols, A.nnz
@@ -230,6 +233,7 @@ class TiledMatrix:
         o.value_map = int(bool(value_map))
         o.slices = int(slices)
         o.lds_stage = int(lds_stage)
+        o.panels, o.panel_rows, o.panel_waves = int(panels), int(panel_rows), int(panel_waves)
         keep_b = None
         if tile_bounds is not None and len(tile_bounds) > 0:
             keep_b = (ctypes.c_int32 * len(tile_bounds))(*[int(v) for v in tile_bounds])
@@ -290,6 +294,7 @@ class TiledMatrix:
         sizes = dict(inf)
         sizes["n_tiles+1"] = inf["n_tiles"] + 1
         sizes["nnz_coo"] = inf["nnz"] if inf["kernel"] == 1 else 0
+        sizes["n_panels+1"] = inf["n_panels"] + 1 if inf["n_panels"] > 0 else 0
         arrays, view = {}, CFormatView()
         for name, dt, sz in _VIEW_FIELDS:
             if metadata_only and sz in ("nnz_pad", "n_rowid", "n_rows_sorted", "n_rows", "n_cols", "nnz_coo"):
@@ -303,7 +308,9 @@ class TiledMatrix:
         arrays.update(T=inf["n_dense_tiles"], n_tiles_total=inf["n_tiles"], nnz_pad=inf["nnz_pad"],
                       xcd_groups=inf["xcd_groups"], kernel=inf["kernel"],
                       W=inf["tile_width"], S=inf["wave"], split_len=inf["split_len"],
-                      relabel=bool(inf["relabel"]), n_rows=inf["n_rows"], n_cols=inf["n_cols"])
+                      relabel=bool(inf["relabel"]), n_rows=inf["n_rows"], n_cols=inf["n_cols"],
+                      n_panels=inf["n_panels"], n_col_tiles=inf["n_col_tiles"], panel_rows=inf["panel_rows"],
+                      panel_waves=inf["panel_waves"])
         return arrays
 
     # -- products
@@ -327,6 +334,13 @@ class TiledMatrix:
         _need(x, (self.n_cols,), "x")
         _need(y, (self.n_rows,), "y")
         _check(load_library().tc_spmv_internal(self.handle, _ptr(x), _ptr(y), _stream(stream)), "tc_spmv_internal")
+        return y
+
+    def spmv_tiles(self, x: torch.Tensor, y: torch.Tensor, stream=None) -> torch.Tensor:
+        """As spmv_internal, one launch per tile (also for row-panel handles)."""
+        _need(x, (self.n_cols,), "x")
+        _need(y, (self.n_rows,), "y")
+        _check(load_library().tc_spmv_tiles(self.handle, _ptr(x), _ptr(y), _stream(stream)), "tc_spmv_tiles")
         return y
 
     def spmm(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
