@@ -159,6 +159,7 @@ def rwr_batched(c: float = 0.85, tol: float = 1e-6, ks=(1, 8, 32, 64, 128)):
     b = out["k32"]["queries_per_s"]
     out.update(tiled_loop_queries_per_s=round(tiled_seq, 2),
                torch_csr_loop_queries_per_s=None if torch_seq is None else round(torch_seq, 2),
+               torch_csr_note="PyTorch sparse CSR (the ROCm sparse library): context only, not a target",
                speedup_k32_vs_tiled_loop=round(b / tiled_seq, 2),
                speedup_k32_vs_torch_csr_loop=None if torch_seq is None else round(b / torch_seq, 2))
     tm.close()
@@ -330,27 +331,27 @@ def kernel_compare(A_cl23=None, reps: int = 20):
 
 
 def attainable_bandwidth(dev, gib: int = 2, reps: int = 10):
-    """What plain streaming reaches on this GPU, next to the nominal HBM peak:
-    a read-only reduction and a device copy over `gib` GiB (torch's own
-    kernels), GB/s from CUDA events on the current stream, median of reps."""
+    """The streaming-read rate the product kernels can reach on this GPU, next
+    to the nominal HBM peak: the library's own read kernel (tc_stream_read:
+    16-byte non-temporal loads, four in flight per thread) over `gib` GiB,
+    timed with events on the launch stream; median of reps."""
     import torch
+    from paper_1103_2405_amd.tc import STREAM_SINK_FLOATS, stream_read
     n = (gib << 30) // 4
     a = torch.rand(n, device=dev)
-    b = torch.empty_like(a)
-    res = {}
-    for name, fn, nbytes in (("read", lambda: a.sum(), 4 * n), ("copy", lambda: b.copy_(a), 8 * n)):
-        fn()
-        ts = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            fn()
-            e1.record()
-            e1.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        res[name + "_gbps"] = round(nbytes / (float(np.median(ts)) / 1e3) / 1e9, 1)
-    res["bytes"] = 4 * n
-    del a, b
+    sink = torch.empty(STREAM_SINK_FLOATS, device=dev)
+    stream_read(a, sink)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        stream_read(a, sink)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    res = {"read_gbps": round(4 * n / (float(np.median(ts)) / 1e3) / 1e9, 1), "bytes": 4 * n,
+           "kernel": "k_stream_read (tc_stream_read)"}
+    del a, sink
     torch.cuda.empty_cache()
     return res
 
@@ -364,6 +365,8 @@ def main():
     ap.add_argument("--workload", default="cl23")
     ap.add_argument("--tile-width", type=int, default=0)
     ap.add_argument("--split-len", type=int, default=-1)
+    ap.add_argument("--panels", type=int, default=-1,
+                    help="row panels: -1 automatic (default), 0 none (one launch per tile), P > 0 that many")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-timing", action="store_true", help="skip the per-launch kernel timing")
@@ -392,7 +395,8 @@ def main():
     perf_table = "default"
 
     def step(timing: bool):
-        tm = TiledMatrix(A, tile_width=args.tile_width, split_len=args.split_len, perf_table=perf_table)
+        tm = TiledMatrix(A, tile_width=args.tile_width, split_len=args.split_len, perf_table=perf_table,
+                         panels=args.panels)
         if timing:
             tm.set_timing(True)
         tm.pagerank(0.85, 0.0, args.iters, out=p_out)
@@ -429,16 +433,19 @@ def main():
         avg_ms = tot_ms / max(launches, 1)
         achieved = per_launch_bytes / (avg_ms / 1e3) / 1e9
         from paper_1103_2405_amd.profsum import read_traffic
-        traffic = read_traffic(os.path.join(ROOT, "profiles", "k_tile_spmv_%s_pagerank_counters.txt" % args.workload))
+        kname = "k_panel_spmv" if info["n_panels"] > 0 else "k_tile_spmv"
+        traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pagerank_counters.txt" % (kname, args.workload)))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "k_tile_spmv_pr",  # the product with the fused update; k_tile_spmv on the last iteration
+                    # the row-panel pass (one launch per product), or the tile kernel with the fused update
+                    "kernel": kname if info["n_panels"] > 0 else "k_tile_spmv_pr",
                     "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches_per_spmv": round(launches / max(calls, 1), 2),
                     "bytes_per_launch": int(per_launch_bytes)}
 
     # separate measurements (not part of value): PageRank alone and the plain CSR baseline
-    tm = TiledMatrix(A, tile_width=args.tile_width, split_len=args.split_len, perf_table=perf_table)
+    tm = TiledMatrix(A, tile_width=args.tile_width, split_len=args.split_len, perf_table=perf_table,
+                     panels=args.panels)
     tm.pagerank(0.85, 0.0, 5, out=p_out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -490,7 +497,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, step="build_tiled + %d PageRank iterations + destroy" % args.iters,
-                       tile_width=info["tile_width"], n_tiles=info["n_tiles"],
+                       tile_width=info["tile_width"], n_tiles=info["n_tiles"], n_panels=info["n_panels"],
+                       n_col_tiles=info["n_col_tiles"], panel_rows=info["panel_rows"],
                        n_workloads=info["n_workloads"], nnz_pad=info["nnz_pad"]),
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
         "step_ms": {"min": round(float(per_step.min()), 3), "median": round(float(np.median(per_step)), 3),

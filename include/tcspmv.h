@@ -113,9 +113,17 @@ typedef struct {
                                  are LDS reads; 1: every tile that fits is staged; -1: every
                                  tile gathers x through the caches */
   int32_t panels;             /* row panels (MI355X reading of Section 3.2's row partition, applied
-                                 to the workgroups of one GPU): 0 (default) = none; -1 = about
-                                 4096 rows per panel, at most two panels per compute unit; P > 0 =
-                                 P panels.  Internal rows are cut into contiguous panels of at
+                                 to the workgroups of one GPU): 0 (default) = none; P > 0 = P
+                                 panels; -1 = automatic: min(compute units, ceil(n_rows / 2048))
+                                 panels of up to 9/8 of an even share of rows (rounded up to 64)
+                                 unless panel_rows is given, and, unless tile_bounds is given, a
+                                 head tile of the columns that fit in the LDS left behind y (a
+                                 multiple of 1024, staged in LDS), then tiles of tile_width
+                                 (default 2^19) columns by Algorithm 1's rule, then the sparse
+                                 tile; with wl_policy 0 and split_len -1 the panel tiles then
+                                 take workloads of 512 entries and split rows longer than 1024
+                                 (measured best here: the panel's wavefronts meet at a barrier
+                                 after every tile, an imbalance Eq. 1-5 do not charge).  Internal rows are cut into contiguous panels of at
                                  most panel_rows rows holding about equal numbers of the entries
                                  that stay with their row (a segment longer than its column
                                  tile's split length is chunked and belongs to no panel); every
@@ -125,7 +133,8 @@ typedef struct {
   int32_t panel_rows;         /* most rows of a panel; 0 = half the LDS of a compute unit, in
                                  floats (20480 on gfx950); at most one workgroup's LDS */
   int32_t panel_waves;        /* wavefronts of a panel's workgroup (4, 8 or 16; 0 = 16), also the
-                                 resident-wavefront count of the model (Eq. 1) for panel tiles */
+                                 resident wavefronts of Eq. 1 when Algorithm 2 sizes the
+                                 workloads of a panel's tile */
   const char* perf_table;     /* path of a throughput table for the model; NULL = built-in */
   /* optional device allocator for the handle's buffers; NULL = hipMalloc / hipFree */
   void* (*alloc)(size_t bytes, void* ctx);
@@ -344,6 +353,16 @@ tc_status tc_rwr_theta_grad(int64_t n_cols, int64_t nnz, const int64_t* d_rpT, i
 /* Plain CSR SpMV (one thread per row, Appendix B's CSR kernel), the baseline
  * the tiled kernels are compared with: y := A x, caller's ids, no handle. */
 tc_status tc_csr_spmv(const tc_csr* A, const float* d_x, float* d_y, tc_stream_t stream);
+
+/* Measurement of the streaming-read rate the product kernels can reach (the
+ * attainable side of the roofline, next to the nominal HBM peak): reads the n
+ * floats of d_buf once, 16 bytes per load with the non-temporal loads of the
+ * tile kernels, four loads in flight per thread, 8192 workgroups of 256
+ * threads; each thread's sum is written to d_sink, which must hold
+ * 8192 * 256 floats (device).  n must be a multiple of 4 and d_buf 16-byte
+ * aligned (TC_EINVAL otherwise).  Asynchronous on `stream`; the caller times
+ * it with events on that stream. */
+tc_status tc_stream_read(const float* d_buf, int64_t n, float* d_sink, tc_stream_t stream);
 
 /* Sizes and parameters of a handle (host, no GPU work). */
 tc_status tc_handle_info(const tc_handle* h, tc_info* info);

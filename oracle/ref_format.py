@@ -174,6 +174,8 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
         rows_len.append(slen)
         tile_row_off.append(tile_row_off[-1] + len(srow))
         seg_lists.append((tstart[t] + sstart, slen, srow))
+    for t in range(ntiles):
+        slen = seg_lists[t][1]
         # a6: workload size and partition
         kind = "dense" if t % NT < T else "sparse"
         split_t = csplit[t % NT]
@@ -181,6 +183,7 @@ def build(csr, W: int, n_tiles: int = -1, wl: Optional[Sequence[int]] = None, S:
         if wl is not None:
             WLt = int(wl[t])
         elif table is not None:
+            # with row panels a panel's tile is tuned for the wavefronts of its workgroup
             WLt = choose_wl(slen.tolist(), int(tcount[t]), table, kind, panel_waves if pb is not None else max_act_warp,
                             S, split_t)
         else:

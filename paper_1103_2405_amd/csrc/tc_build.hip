@@ -13,6 +13,8 @@
 // Every sort is a chain of stable counting-sort passes, so the format is a
 // pure function of the input and the options.
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -544,10 +546,10 @@ __global__ void k_seg_panel(int32_t* __restrict__ seg_tile, const int32_t* __res
   seg_tile[s] = lo * nct + seg_tile[s];
 }
 
-__global__ void k_tile_entries(const int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_len, int64_t nseg,
-                               unsigned long long* __restrict__ tnnz) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < nseg) atomicAdd(&tnnz[seg_tile[s]], (unsigned long long)seg_len[s]);
+__global__ void k_tile_entries(const int64_t* __restrict__ pre, const int64_t* __restrict__ off, int32_t ntiles,
+                               int64_t* __restrict__ tnnz) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < ntiles) tnnz[g] = pre[off[g + 1]] - pre[off[g]];
 }
 
 __global__ void k_ne(const int32_t* __restrict__ a, int64_t n, int32_t v, int32_t* __restrict__ out) {
@@ -1057,6 +1059,9 @@ void check_descriptors(const std::vector<Wl>& dwl, const std::vector<HostWl>& wl
   }
 }
 
+// Workload size of the automatic row panels (see tc_build_tiled).
+constexpr int64_t kPanelWl = 512;
+
 // compute units and LDS of the current device
 void device_limits(tc_handle* h) {
   int dev = 0, cus = 0;
@@ -1127,13 +1132,29 @@ std::vector<int64_t> make_panels(int32_t* seg_tile, const int32_t* seg_row, cons
 void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h) {
   PhaseClock clk(st);
   device_limits(h);
+  int64_t panel_head = 0;  // automatic panels: width of the LDS-staged head tile
   if (h->n_panels != 0) {
     const int64_t wg_floats = h->lds_floats;
-    if (h->panel_rows == 0) h->panel_rows = (int32_t)std::min<int64_t>(wg_floats, h->lds_cu_bytes / 8);
     if (h->panel_rows > wg_floats)
       throw Fail{TC_EINVAL, "panel_rows exceeds the LDS of one workgroup (" + std::to_string(wg_floats) + " floats)"};
-    if (h->n_panels < 0)  // automatic: panels of about 4096 rows, at most two per compute unit
-      h->n_panels = (int32_t)std::max<int64_t>(1, std::min<int64_t>((A->n_rows + 4095) / 4096, 2 * (int64_t)h->n_cu));
+    if (h->n_panels < 0) {
+      // automatic: one 16-wavefront workgroup per compute unit (fewer for
+      // matrices of under 2048 rows per compute unit), each panel sized for
+      // an eighth more rows than an even share; the LDS left behind y holds
+      // the head tile (a multiple of 1024 columns, at least 1024).  More
+      // panels than compute units only when the rows do not fit.
+      int64_t P = std::max<int64_t>(1, std::min<int64_t>(h->n_cu, (A->n_rows + 2047) / 2048));
+      int64_t R = ((9 * ((A->n_rows + P - 1) / P) + 7) / 8 + 63) / 64 * 64;
+      if (R > wg_floats - 1024) {
+        R = (wg_floats - 1024) / 64 * 64;
+        P = (9 * A->n_rows / 8 + R - 1) / R;
+      }
+      h->n_panels = (int32_t)std::max<int64_t>(1, P);
+      if (h->panel_rows == 0) h->panel_rows = (int32_t)std::max<int64_t>(64, R);
+      const int64_t head = (wg_floats - ((h->panel_rows + 3) & ~3)) / 1024 * 1024;
+      panel_head = head >= 1024 && o->n_tile_bounds == 0 ? std::min<int64_t>(head, A->n_cols) : 0;
+    }
+    if (h->panel_rows == 0) h->panel_rows = (int32_t)std::min<int64_t>(wg_floats, h->lds_cu_bytes / 8);
   }
   const int64_t n_rows = A->n_rows, n_cols = A->n_cols, nnz = A->nnz;
   Tmp tmp(st);
@@ -1240,7 +1261,31 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     for (int g = 1; g < G; ++g) starts.push_back((int32_t)std::max<int64_t>(head + hcut[g], starts.back()));
     T = 1;
     ntiles = 1 + G;
+  } else if (panel_head > 0) {
+    // automatic row panels: the head tile [0, head) staged in LDS, then tiles
+    // of W columns while the first column of the next one holds at least two
+    // entries (Algorithm 1's rule), then the sparse tile
+    T = 1;
+    if (panel_head < n_cols) {
+      starts.push_back((int32_t)panel_head);
+      const int64_t NTr = (n_cols - panel_head + W - 1) / W;
+      int32_t* samp = tmp.get<int32_t>(NTr);
+      hipLaunchKernelGGL(k_strided, dim3(nblk(NTr, kB)), dim3(kB), 0, st, clen_sorted + panel_head, (int64_t)W, NTr,
+                         samp);
+      HIPX(hipGetLastError());
+      std::vector<int32_t> hs(NTr);
+      HIPX(hipMemcpyAsync(hs.data(), samp, sizeof(int32_t) * NTr, hipMemcpyDeviceToHost, st));
+      HIPX(hipStreamSynchronize(st));
+      int64_t k = 0;
+      while (k < NTr && hs[k] >= 2) {
+        ++k;
+        if (panel_head + k * W < n_cols) starts.push_back((int32_t)(panel_head + k * W));
+      }
+      T = (int32_t)(1 + k);
+    }
+    ntiles = (int32_t)starts.size() + 1;
   } else if (o->n_tile_bounds > 0) {
+
     // given tile boundaries: dense tiles up to the last bound, then the
     // sparse tile if columns remain
     for (int i = 0; i < o->n_tile_bounds; ++i)
@@ -1271,7 +1316,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     h->tile_col_end[t] = t + 1 < ntiles ? starts[t] : n_cols;
   }
   TileMap tmap{W, T, nullptr, 0};
-  if ((h->xcd_groups > 0 || o->n_tile_bounds > 0) && ntiles > 1) {
+  if ((h->xcd_groups > 0 || o->n_tile_bounds > 0 || panel_head > 0) && ntiles > 1) {
     int32_t* d_starts = tmp.get<int32_t>(ntiles - 1);
     HIPX(hipMemcpyAsync(d_starts, starts.data(), sizeof(int32_t) * (ntiles - 1), hipMemcpyHostToDevice, st));
     tmap = TileMap{W, T, d_starts, ntiles - 1};
@@ -1409,18 +1454,13 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
         h->tile_col_end[g] = ce[g % nct];
         h->tile_split[g] = csp[g % nct];
       }
-      unsigned long long* d_tn = tmp.get<unsigned long long>(ntiles);
-      HIPX(hipMemsetAsync(d_tn, 0, sizeof(unsigned long long) * ntiles, st));
-      hipLaunchKernelGGL(k_tile_entries, dim3(nblk(nseg, kB)), dim3(kB), 0, st, (const int32_t*)seg_tile,
-                         (const int32_t*)seg_len, nseg, d_tn);
-      HIPX(hipGetLastError());
-      h->tile_nnz.assign(ntiles, 0);
-      HIPX(hipMemcpyAsync(h->tile_nnz.data(), d_tn, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, st));
+      h->tile_nnz.assign(ntiles, 0);  // from the sorted segments below
       d_split_t = tmp.get<int64_t>(ntiles);
       HIPX(hipMemcpyAsync(d_split_t, h->tile_split.data(), sizeof(int64_t) * ntiles, hipMemcpyHostToDevice, st));
       HIPX(hipStreamSynchronize(st));
       trow.assign(ntiles + 1, 0);
     }
+    clk.mark("a5 segments formed");
     hipLaunchKernelGGL(k_first_touch, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg,
                        (const int64_t*)d_split_t, first, touched);
     HIPX(hipGetLastError());
@@ -1443,6 +1483,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       std::swap(k0, k1);
       std::swap(v0, v1);
     }
+    clk.mark("a5 segments sorted");
     rows_sorted = hold<int32_t>(h, nseg);
     rows_len = hold<int32_t>(h, nseg);
     srt_start = tmp.get<int32_t>(nseg);
@@ -1453,6 +1494,17 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     hipLaunchKernelGGL(k_key_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, k0, nseg, lb + rb, ntiles, d_off);
     HIPX(hipGetLastError());
     HIPX(hipMemcpyAsync(trow.data(), d_off, sizeof(int64_t) * (ntiles + 1), hipMemcpyDeviceToHost, st));
+    if (h->n_panels > 0) {
+      // entries of every (panel, column tile) tile: sums of its sorted rows' lengths
+      int64_t* pre = tmp.get<int64_t>(nseg + 1);
+      const int64_t tot = excl_scan<int32_t, int64_t>(rows_len, nseg, pre, tmp, st);
+      HIPX(hipMemcpyAsync(pre + nseg, &tot, sizeof(int64_t), hipMemcpyHostToDevice, st));
+      int64_t* d_tn = tmp.get<int64_t>(ntiles);
+      hipLaunchKernelGGL(k_tile_entries, dim3(nblk(ntiles, kB)), dim3(kB), 0, st, (const int64_t*)pre,
+                         (const int64_t*)d_off, ntiles, d_tn);
+      HIPX(hipGetLastError());
+      HIPX(hipMemcpyAsync(h->tile_nnz.data(), d_tn, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, st));
+    }
     // length runs
     int32_t* rflags = tmp.get<int32_t>(nseg);
     int32_t* rpos = tmp.get<int32_t>(nseg);
@@ -1493,33 +1545,65 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->tile_wl_begin.assign(ntiles + 1, 0);
   std::vector<HostWl>& wls = h->wls;
   wls.clear();
+  // Runs of each tile, then Algorithm 2 and the partition tile by tile; the
+  // tiles are independent, so with many tiles (row panels) they are spread
+  // over host threads, each writing its own tiles' workload lists.
+  std::vector<std::vector<LenRun>> truns(ntiles);
   size_t ri = 0;
   for (int t = 0; t < ntiles; ++t) {
-    std::vector<LenRun> runs;
     while (ri < run_pos.size() && run_pos[ri] < trow[t + 1]) {
       const int64_t end = ri + 1 < run_pos.size() ? std::min(run_pos[ri + 1], trow[t + 1]) : trow[t + 1];
-      runs.push_back(LenRun{run_len[ri], end - run_pos[ri]});
+      truns[t].push_back(LenRun{run_len[ri], end - run_pos[ri]});
       ++ri;
     }
-    const int64_t split_t = h->tile_split[t];
-    pp.split_len = (int32_t)split_t;
+  }
+  if (o->wl_policy == 1 && o->n_wl_per_tile < ntiles)
+    throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
+  std::vector<std::vector<HostWl>> twls(ntiles);
+  std::vector<double> tmodel(ntiles, 0.0);
+  std::vector<int> tbad(ntiles, 0);
+  auto tile_job = [&](int t) {
+    const std::vector<LenRun>& runs = truns[t];
+    PartitionParams pt = pp;
+    pt.split_len = (int32_t)h->tile_split[t];
     const bool sparse_t = (h->n_panels > 0 ? t % h->n_col_tiles : t) >= T;
     int64_t WLt;
-    if (o->wl_policy == 1) {
-      if (t >= o->n_wl_per_tile) throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
+    if (o->wl_policy == 1)
       WLt = o->wl_per_tile[t];
-    } else if (o->wl_policy == 2) {
+    else if (o->wl_policy == 2)
       WLt = o->wl_all;
-    } else {
-      WLt = choose_wl(runs, h->tile_nnz[t], table, sparse_t, pp);
+    else if (o->panels < 0)
+      WLt = kPanelWl;
+    else
+      WLt = choose_wl(runs, h->tile_nnz[t], table, sparse_t, pt);
+    if (WLt < 1) {
+      tbad[t] = 1;
+      return;
     }
-    if (WLt < 1) throw Fail{TC_EINVAL, "workload size must be >= 1"};
     h->tile_wl[t] = WLt;
-    if (!runs.empty()) h->model_us += model_time(runs, WLt, table, sparse_t, pp);
+    if (!runs.empty()) tmodel[t] = model_time(runs, WLt, table, sparse_t, pt);
+    partition_tile(runs, WLt, t, trow[t], pt, &twls[t]);
+  };
+  const int nthr = ntiles >= 64 ? (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency())) : 1;
+  if (nthr > 1) {
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    for (int i = 0; i < nthr; ++i)
+      pool.emplace_back([&]() {
+        for (int t; (t = next.fetch_add(1)) < ntiles;) tile_job(t);
+      });
+    for (auto& th : pool) th.join();
+  } else {
+    for (int t = 0; t < ntiles; ++t) tile_job(t);
+  }
+  for (int t = 0; t < ntiles; ++t) {
+    if (tbad[t]) throw Fail{TC_EINVAL, "workload size must be >= 1"};
+    h->model_us += tmodel[t];
     h->tile_wl_begin[t] = (int64_t)wls.size();
-    partition_tile(runs, WLt, t, trow[t], pp, &wls);
+    wls.insert(wls.end(), twls[t].begin(), twls[t].end());
   }
   h->tile_wl_begin[ntiles] = (int64_t)wls.size();
+  clk.mark("a6 sizes and partition");
   h->d_tile_wl_begin = hold<int64_t>(h, ntiles + 1);
   HIPX(hipMemcpyAsync(h->d_tile_wl_begin, h->tile_wl_begin.data(), sizeof(int64_t) * (ntiles + 1),
                       hipMemcpyHostToDevice, st));
@@ -1704,6 +1788,20 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->d_partial = hold<double>(h, std::max<int64_t>(h->n_slots, 1) * 256);
   if (!srows.empty())
     HIPX(hipMemcpyAsync(h->d_split, srows.data(), sizeof(SplitRow) * srows.size(), hipMemcpyHostToDevice, st));
+  std::vector<int64_t> psb;
+  if (h->n_panels > 0) {
+    // split rows of each panel (srows is in increasing row): [psb[p], psb[p+1])
+    psb.assign(h->n_panels + 1, 0);
+    size_t q = 0;
+    for (int p = 0; p <= h->n_panels; ++p) {
+      const int64_t lo = h->panel_begin[p];
+      while (q < srows.size() && srows[q].row < lo) ++q;
+      psb[p] = p == h->n_panels ? (int64_t)srows.size() : (int64_t)q;
+    }
+    h->d_panel_split_begin = hold<int64_t>(h, h->n_panels + 1);
+    h->d_panel_yraw = hold<float>(h, std::max<int64_t>((int64_t)srows.size(), 1));
+    HIPX(hipMemcpyAsync(h->d_panel_split_begin, psb.data(), sizeof(int64_t) * psb.size(), hipMemcpyHostToDevice, st));
+  }
   h->d_xbuf = hold<float>(h, std::max(n_rows, n_cols));
   h->d_ybuf = hold<float>(h, std::max(n_rows, n_cols));
   h->d_red = hold<double>(h, 4096);
@@ -1794,9 +1892,14 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   h->n_rows = A->n_rows;
   h->n_cols = A->n_cols;
   h->nnz = A->nnz;
-  h->W = o->tile_width > 0 ? o->tile_width : (1 << 23);
+  h->W = o->tile_width > 0 ? o->tile_width : (o->panels < 0 ? (1 << 19) : (1 << 23));
   h->S = o->wave > 0 ? o->wave : 64;
   h->split_len = o->split_len < 0 ? -1 : o->split_len;
+  // automatic row panels with automatic sizes: workloads of kPanelWl entries
+  // and rows split into chunks of twice that (measured best on MI355X; the
+  // panel's wavefronts meet at a barrier after every tile, and Eq. 1-5 do not
+  // charge the imbalance there)
+  if (o->panels < 0 && o->split_len < 0) h->split_len = 2 * kPanelWl;
   h->camping_pad = o->camping_pad != 0;
   h->relabel = o->relabel < 0 ? (A->n_rows == A->n_cols) : (o->relabel != 0);
   h->max_act_warp = o->max_act_warp > 0 ? o->max_act_warp : 8192;

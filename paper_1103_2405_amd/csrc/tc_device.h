@@ -25,6 +25,19 @@ struct RwrEpi {
   const int32_t* seeds;  // internal ids, one per right-hand side
 };
 
+// PageRank update fused into the row-panel pass (Eq. 6): every row is
+// written as p' = fl32(c (fl32(y) + d/n) + (1 - c)/n), the separate update's
+// rounding; a split row's sum over its unsplit segments also goes to yraw (in
+// the order of the split-row list), for the pass that adds its chunks.
+struct PanelPr {
+  double c;
+  const double* dmass;    // dangling mass of the iterate the product reads
+  int64_t n;
+  const int64_t* psb;     // [panels + 1] split rows of each panel
+  const SplitRow* split;  // split rows, increasing row
+  float* yraw;
+};
+
 __device__ inline float rwr_restart(double c, float y, bool is_seed) {
   return (float)(c * (double)y + (is_seed ? 1.0 - c : 0.0));
 }

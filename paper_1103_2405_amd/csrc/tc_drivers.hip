@@ -125,6 +125,20 @@ __global__ void k_pr_split_empty(const SplitRow* __restrict__ sr, int64_t n_spli
   }
 }
 
+// Fused PageRank step with row panels, the split rows: their unsplit
+// segments' sum (yraw, from the panel pass) plus their chunks, then the same
+// formula as the panel pass; the rows without entries were written by it.
+__global__ void k_pr_split_panel(const SplitRow* __restrict__ sr, int64_t n_split, const double* __restrict__ partial,
+                                 const float* __restrict__ yraw, float* __restrict__ pn, double c,
+                                 const double* __restrict__ dmass, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_split) return;
+  const double dn = *dmass / (double)n, tele = (1.0 - c) / (double)n;
+  const SplitRow s = sr[t];
+  const float yv = (float)((double)yraw[t] + sum_slots(partial + s.slot_begin, s.n_slots));
+  pn[s.row] = (float)(c * ((double)yv + dn) + tele);
+}
+
 // Fused one-query RWR step, the rows the tile kernel does not write: split
 // rows (their chunks' sums) and, when `empty` is given, rows without entries
 // (y = 0), same formula as RwrX.
@@ -255,6 +269,7 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
       // dangling mass comes from a pass over the dangling range alone.  The
       // others run the product into the other buffer, then the update in place.
       const bool fuse = !xcd && h->n_tiles == 1 && h->kernel == 0;
+      const bool fuse_panel = h->n_panels > 0 && h->kernel == 0;
       float* buf[2] = {p, y};
       bool zero_rows[2] = {false, false};  // the buffer's rows without entries hold 0
       int cur = 0;
@@ -262,7 +277,26 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
         const bool need_res = it + 1 == max_iter || (tol > 0.0f && (it + 1) % check_every == 0);
         float* pc = buf[cur];
         float* pn = buf[1 - cur];
-        if (fuse && !need_res) {
+        if (fuse_panel && !need_res) {
+          const PanelPr pr{(double)c, (const double*)(res + 1), n, (const int64_t*)h->d_panel_split_begin,
+                           (const SplitRow*)h->d_split, h->d_panel_yraw};
+          panel_pass(h, pc, pn, st, &pr);
+          if (h->n_split_rows > 0) {
+            hipLaunchKernelGGL(k_pr_split_panel, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
+                               h->n_split_rows, (const double*)h->d_partial, (const float*)h->d_panel_yraw, pn,
+                               (double)c, (const double*)(res + 1), n);
+            HIPC(hipGetLastError());
+          }
+          hipLaunchKernelGGL(k_dang_sum, dim3(kRedBlocks), dim3(kB), 0, st, (const float*)pn, n, n - h->n_dangling,
+                             parts + kRedBlocks);
+          HIPC(hipGetLastError());
+          hipLaunchKernelGGL(k_finish, dim3(1), dim3(kB), 0, st, (const double*)(parts + kRedBlocks), kRedBlocks, 1,
+                             res + 1);
+          HIPC(hipGetLastError());
+          h->spmv_calls++;
+          zero_rows[1 - cur] = false;
+          cur = 1 - cur;
+        } else if (fuse && !need_res) {
           const int64_t b = h->tile_wl_begin[0], e = h->tile_wl_begin[1];
           if (e > b)
             launch_tile(h,

@@ -54,6 +54,10 @@ K pick_slices(int32_t s, K s1, K s2, K s4, K s8) {
 // caller adds them in its own pass); split rows are then added to y first.
 // skip_zero: y's empty rows are still zero from an earlier product into the
 // same y (nothing else writes them), so the zeroing launch can be left out.
+// One launch of the row-panel pass y := A x (a handle with row panels); with
+// pr, the pass writes the fused PageRank update of y instead (split rows are
+// finished by the caller from pr->yraw and their chunks).
+void panel_pass(tc_handle* h, const float* x, float* y, hipStream_t st, const PanelPr* pr);
 // tilewise: one launch per tile even for a handle with row panels.
 void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine = false,
                    bool skip_zero = false, bool tilewise = false);

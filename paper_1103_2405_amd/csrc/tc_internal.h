@@ -156,6 +156,8 @@ struct tc_handle {
   int64_t* d_panel_ncb = nullptr;    // [n_tiles] first workload of the tile that is not a split chunk
   int64_t* d_panel_chunks = nullptr; // chunk workloads of every column tile, panel order
   int64_t* d_panel_cb = nullptr;     // [n_col_tiles + 1] offsets into d_panel_chunks
+  int64_t* d_panel_split_begin = nullptr;  // [n_panels + 1] first split row (d_split) of each panel
+  float* d_panel_yraw = nullptr;     // [n_split_rows] a split row's sum over its unsplit segments (fused update)
   // value map (build option): the CSR entry of every padded slot, -1 for pads
   int32_t* d_vmap = nullptr;
   // TILE-COO (kernel == 1): every tile's entries in coordinate form

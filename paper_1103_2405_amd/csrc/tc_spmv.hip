@@ -122,8 +122,8 @@ __device__ inline void panel_tile(const G& xg, int64_t g, int32_t t, int32_t p, 
 // same order, so the x segment of the current tile is what the L2s hold; with
 // w0 > 0 column tile 0 (internal columns [0, w0), the hottest) is first copied
 // into LDS behind y (rows_cap floats in).  At the end the panel's y is stored
-// once, coalesced.
-template <int NW>
+// once, coalesced (PR: as the PageRank update of it).
+template <int NW, bool PR = false>
 __global__ void __launch_bounds__(NW * kWave) k_panel_spmv(const Wl* __restrict__ wl,
                                                            const int64_t* __restrict__ wl_begin,
                                                            const int64_t* __restrict__ ncb,
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(NW * kWave) k_panel_spmv(const Wl* __restrict_
                                                            const float* __restrict__ val,
                                                            const int32_t* __restrict__ rowid,
                                                            const float* __restrict__ x, float* __restrict__ y,
-                                                           double* __restrict__ partial) {
+                                                           double* __restrict__ partial, PanelPr pr) {
   extern __shared__ float ys[];
   const int32_t p = blockIdx.x;
   const int32_t r0 = pb[p], nr = pb[p + 1] - r0;
@@ -162,7 +162,14 @@ __global__ void __launch_bounds__(NW * kWave) k_panel_spmv(const Wl* __restrict_
                    partial);
     __syncthreads();
   }
-  for (int32_t i = threadIdx.x; i < nr; i += NW * kWave) y[r0 + i] = ys[i];
+  if (PR) {
+    const double dn = *pr.dmass / (double)pr.n, tele = (1.0 - pr.c) / (double)pr.n;
+    for (int32_t i = threadIdx.x; i < nr; i += NW * kWave) y[r0 + i] = (float)(pr.c * ((double)ys[i] + dn) + tele);
+    const int64_t se = pr.psb[p + 1];
+    for (int64_t q = pr.psb[p] + threadIdx.x; q < se; q += NW * kWave) pr.yraw[q] = ys[pr.split[q].row - r0];
+  } else {
+    for (int32_t i = threadIdx.x; i < nr; i += NW * kWave) y[r0 + i] = ys[i];
+  }
 }
 
 // Concurrent pass over tiles 1..G of the XCD schedule.  Workgroups are
@@ -214,6 +221,28 @@ __global__ void k_begin_spmv(float* __restrict__ y, const int32_t* __restrict__ 
   if (i < n_empty) y[empty[i]] = 0.0f;
   if (i < nt) counters[i] = 0ull;
 }
+
+// ---- streaming read (measurement): every 16-byte word of the buffer read
+// once with the tile kernels' non-temporal loads, four per thread in flight;
+// the per-thread sums go to sink so the loads cannot be dropped.
+__global__ void __launch_bounds__(kB) k_stream_read(const v4f* __restrict__ a, int64_t n4, float* __restrict__ sink) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const int64_t T = (int64_t)gridDim.x * kB;
+  float s = 0.0f;
+  int64_t i = t;
+  for (; i + 3 * T < n4; i += 4 * T) {
+    const v4f v0 = __builtin_nontemporal_load(a + i), v1 = __builtin_nontemporal_load(a + i + T);
+    const v4f v2 = __builtin_nontemporal_load(a + i + 2 * T), v3 = __builtin_nontemporal_load(a + i + 3 * T);
+    s += ((v0.x + v0.y) + (v0.z + v0.w)) + ((v1.x + v1.y) + (v1.z + v1.w)) + ((v2.x + v2.y) + (v2.z + v2.w)) +
+         ((v3.x + v3.y) + (v3.z + v3.w));
+  }
+  for (; i < n4; i += T) {
+    const v4f v = __builtin_nontemporal_load(a + i);
+    s += (v.x + v.y) + (v.z + v.w);
+  }
+  sink[t] = s;
+}
+constexpr int kStreamBlocks = 8192;
 
 // ---- plain CSR baseline: one thread per row (FP64 accumulation)
 __global__ void k_csr_scalar(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -434,31 +463,36 @@ int64_t lds_tile_blocks(const tc_handle* h, int64_t lw) {
 // Floats of x that the row-panel pass stages in LDS (column tile 0, when it
 // fits behind the panel's rows of y and staging is not turned off), else 0.
 int64_t panel_stage_width(const tc_handle* h) {
-  if (h->n_panels <= 0 || h->lds_tiles == 0 || h->n_col_tiles < 2) return 0;
+  if (h->n_panels <= 0 || h->lds_tiles == 0 || h->n_col_tiles < 1) return 0;
   const int64_t rows_cap = (h->panel_rows + 3) & ~3;
   const int64_t w0 = h->tile_col_end[0] - h->tile_col_begin[0];
   return rows_cap + w0 <= h->lds_floats ? w0 : 0;
 }
 
-// One launch of the row-panel pass: every row of y is stored by its panel.
-void panel_pass(tc_handle* h, const float* x, float* y, hipStream_t st) {
+// One launch of the row-panel pass: every row of y is stored by its panel
+// (with pr: the fused PageRank update of it).
+void panel_pass(tc_handle* h, const float* x, float* y, hipStream_t st, const PanelPr* pr) {
   if (h->n_panels <= 0 || h->n_wl == 0) return;
   const int64_t rows_cap = (h->panel_rows + 3) & ~3;
   const int64_t w0 = panel_stage_width(h);
   const uint32_t lds = (uint32_t)(4 * (rows_cap + w0));
-  auto kern = h->panel_waves == 4 ? k_panel_spmv<4> : h->panel_waves == 8 ? k_panel_spmv<8> : k_panel_spmv<16>;
+  auto kern = pr ? (h->panel_waves == 4 ? k_panel_spmv<4, true>
+                    : h->panel_waves == 8 ? k_panel_spmv<8, true> : k_panel_spmv<16, true>)
+                 : (h->panel_waves == 4 ? k_panel_spmv<4> : h->panel_waves == 8 ? k_panel_spmv<8> : k_panel_spmv<16>);
+  const PanelPr none{0.0, nullptr, 0, nullptr, nullptr, nullptr};
   if (lds > 65536) HIPC(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   launch_tile(h, kern, dim3((unsigned)h->n_panels), dim3((unsigned)(h->panel_waves * kWave)), lds, st,
               (const Wl*)h->d_wl, (const int64_t*)h->d_tile_wl_begin, (const int64_t*)h->d_panel_ncb,
               (const int64_t*)h->d_panel_chunks, (const int64_t*)h->d_panel_cb, (int32_t)h->n_col_tiles,
               (int32_t)h->n_panels, (const int32_t*)h->d_panel_begin, (int32_t)rows_cap, (int32_t)w0,
-              (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, x, y, h->d_partial);
+              (const int32_t*)h->d_idx, (const float*)h->d_val, (const int32_t*)h->d_rowid, x, y, h->d_partial,
+              pr ? *pr : none);
 }
 
 void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine, bool skip_zero,
                    bool tilewise) {
   if (h->n_panels > 0 && !tilewise) {
-    panel_pass(h, x, y, st);
+    panel_pass(h, x, y, st, nullptr);
     if (h->n_split_rows > 0) {
       hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
                          h->n_split_rows, h->d_partial, y, 0);
@@ -609,6 +643,17 @@ extern "C" tc_status tc_csr_spmv(const tc_csr* A, const float* x, float* y, tc_s
                          A->col_idx, A->val, A->n_rows, x, y);
       HIPC(hipGetLastError());
     }
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_stream_read(const float* d_buf, int64_t n, float* d_sink, tc_stream_t stream) {
+  return guarded("tc_stream_read", [&]() -> tc_status {
+    if ((!d_buf && n > 0) || !d_sink) throw Err{TC_EINVAL, "NULL argument"};
+    if (n < 0 || (n & 3) || ((uintptr_t)d_buf & 15)) throw Err{TC_EINVAL, "n must be a multiple of 4 and the buffer 16-byte aligned"};
+    hipLaunchKernelGGL(k_stream_read, dim3(kStreamBlocks), dim3(kB), 0, (hipStream_t)stream, (const v4f*)d_buf, n / 4,
+                       d_sink);
+    HIPC(hipGetLastError());
     return TC_OK;
   });
 }

@@ -88,7 +88,7 @@ EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_inter
             "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
             "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory",
             "tc_rwr_multi", "tc_csr_transpose", "tc_rwr_edge_weights", "tc_rwr_iterates", "tc_rwr_adjoint",
-            "tc_rwr_theta_grad", "tc_gather_rows", "tc_refresh_values"]
+            "tc_rwr_theta_grad", "tc_gather_rows", "tc_refresh_values", "tc_stream_read"]
 
 _lib = None
 
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.tc_spmv.argtypes = [vp, vp, vp, vp]
     lib.tc_spmv_internal.argtypes = [vp, vp, vp, vp]
     lib.tc_spmv_tiles.argtypes = [vp, vp, vp, vp]
+    lib.tc_stream_read.argtypes = [vp, i64, vp, vp]
     lib.tc_spmm.argtypes = [vp, vp, vp, i32, vp]
     lib.tc_pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_float, i32, i32, vp, P(i32), P(ctypes.c_double), vp]
     lib.tc_hits.argtypes = [vp, ctypes.c_float, i32, i32, vp, vp, P(i32), P(ctypes.c_double), vp]
@@ -414,6 +415,18 @@ def rwr_multi(mats, seeds, c: float = 0.85, tol: float = 0.0, max_iter: int = 30
                                        ctypes.cast(res, vp), _stream(stream)),
            "tc_rwr_multi")
     return outs, it.value, np.array(res[:n])
+
+
+STREAM_SINK_FLOATS = 8192 * 256
+
+
+def stream_read(buf: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """One streaming read of buf (float32, contiguous, numel a multiple of 4)
+    by the library's measurement kernel; sink holds STREAM_SINK_FLOATS floats."""
+    if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.dtype == torch.float32 and buf.is_contiguous()):
+        raise ValueError("buf must be a contiguous float32 CUDA tensor")
+    _need(sink, (STREAM_SINK_FLOATS,), "sink")
+    _check(load_library().tc_stream_read(_ptr(buf), buf.numel(), _ptr(sink), _stream(stream)), "tc_stream_read")
 
 
 def release_cached_memory() -> int:

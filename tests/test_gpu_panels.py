@@ -135,12 +135,37 @@ def test_panel_waves_give_the_same_bits():
     assert torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2])
 
 
-def test_panel_pagerank_and_automatic_panels():
-    csr = gg.pagerank_matrix(gg.rmat(14, 16, seed=14))
-    gm = TiledMatrix(csr, tile_width=2048, panels=-1)
+def reference_of(gm, csr, table, P):
+    """The reference builder with the panel count asked for and the parameters
+    a handle reports (automatic panels: head tile, column tiles, panel size)."""
+    inf = gm.info()
+    f = gm.export_format(metadata_only=True)
+    T = inf["n_dense_tiles"]
+    # automatic panels: workloads of 512 entries, rows split beyond 1024
+    return rf.build(csr, W=inf["tile_width"], bounds=[int(v) for v in f["tile_col_end"][:T]],
+                    wl=[512] * inf["n_tiles"], split_len=1024, panels=P, panel_rows=inf["panel_rows"],
+                    panel_waves=inf["panel_waves"])
+
+
+@pytest.mark.parametrize("scale", [12, 14])
+def test_panel_automatic_format_and_pagerank(scale):
+    from paper_1103_2405_amd.tc import DEFAULT_PERF_TABLE
+    csr = gg.pagerank_matrix(gg.rmat(scale, 16, seed=scale))
+    gm = TiledMatrix(csr, panels=-1, tile_width=1024)
     inf = gm.info()
     say(inf)
-    assert inf["n_panels"] >= 1 and inf["n_col_tiles"] > 1 and inf["panel_rows"] > 0
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    P = min(n_cu, -(-csr[0] // 2048))
+    R = ((9 * (-(-csr[0] // P)) + 7) // 8 + 63) // 64 * 64
+    # P panels are asked for; the row cap can leave rows for further panels
+    assert inf["n_panels"] >= P and inf["panel_rows"] == max(64, R) and inf["panel_waves"] == 16
+    assert inf["split_len"] == 1024 and set(gm.export_format(metadata_only=True)["tile_wl"]) == {512}
+    assert (np.diff(gm.export_format(metadata_only=True)["panel_begin"]) <= inf["panel_rows"]).all()
+    f = gm.export_format()
+    head = f["tile_col_end"][0]
+    assert head % 1024 == 0 or head == csr[1]
+    same_format(f, reference_of(gm, csr, DEFAULT_PERF_TABLE, P))
+    check_products(gm, csr, gg.uniform_f32(csr[0], 3))
     p, it, res = gm.pagerank(0.85, 0.0, 50)
     pref, _, _ = oracle.pagerank(csr, 0.85, 0.0, 50)
     assert np.abs(p.cpu().numpy().astype(np.float64) - pref).sum() <= 1e-6
@@ -182,3 +207,22 @@ def test_panel_lds_staged_first_tile(bounds, R):
     gm.spmv_internal(x, ya)
     off.spmv_internal(x, yb)
     assert torch.equal(ya.view(torch.int32), yb.view(torch.int32))
+
+
+@pytest.mark.parametrize("split,bounds", [(-1, None), (64, [512, 2048]), (16, [1024])])
+def test_panel_pagerank_fused_update_equals_separate_update(split, bounds):
+    """With the change read every iteration no step is fused; with a fixed
+    count every step but the last runs the update inside the panel pass: the
+    iterates agree bit for bit (split rows with and without unsplit segments,
+    rows without entries and dangling columns included)."""
+    csr = gg.pagerank_matrix(gg.rmat(13, 8, seed=21))
+    assert np.any(np.diff(csr[2]) == 0) and np.any(np.bincount(csr[3], minlength=csr[1]) == 0)
+    gm = TiledMatrix(csr, tile_width=1024, split_len=split, tile_bounds=bounds, panels=11, panel_rows=1024)
+    inf = gm.info()
+    assert inf["n_panels"] >= 11 and (split < 0 or inf["n_split_rows"] > 0)
+    a, it, ra = gm.pagerank(0.85, 1e-7, 300, check_every=1)
+    b, it2, rb = gm.pagerank(0.85, 0.0, it)
+    assert it2 == it and ra == rb
+    assert torch.equal(a, b)
+    pref, _, _ = oracle.pagerank(csr, 0.85, 0.0, it)
+    assert np.abs(b.cpu().numpy() - pref).sum() <= 1e-6
