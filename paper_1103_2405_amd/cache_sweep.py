@@ -30,6 +30,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--graph", default="cl23")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--panels", type=int, default=0,
+                    help="build with row panels (-1 automatic) instead of one tile")
+    ap.add_argument("--widths", default="", help="comma-separated widths (default: 1K .. n_cols by powers of two)")
     a = ap.parse_args(argv)
     assert torch.cuda.is_available(), "runs on the GPU"
     import graphgen as gg
@@ -41,9 +44,15 @@ def main(argv=None):
     A = DeviceCsr(csr)
     col_d = A.col.clone()
     res = []
-    for wm in [w for w in WIDTHS if w <= n_cols]:
+    widths = [int(v) for v in a.widths.split(",")] if a.widths else [w for w in WIDTHS if w <= n_cols]
+    for wm in widths:
         A.col.copy_(torch.remainder(col_d, wm))
-        tm = TiledMatrix(A, tile_width=n_cols, n_tiles=1, relabel=0)
+        if a.panels:
+            # the benchmark's format (row panels, column tiles by Algorithm 1)
+            # on the modded matrix
+            tm = TiledMatrix(A, panels=a.panels)
+        else:
+            tm = TiledMatrix(A, tile_width=n_cols, n_tiles=1, relabel=0)
         x = torch.rand(n_cols, device="cuda")
         y = torch.empty(n_rows, device="cuda")
         for _ in range(2):
@@ -52,9 +61,12 @@ def main(argv=None):
         for _ in range(a.reps):
             tm.spmv_internal(x, y)
         t = tm.get_timing()
-        tm.close()
         res.append((wm, t["tile_kernel_ms"] * 1e3 / max(t["spmv_calls"], 1)))
+        if a.panels:
+            inf = tm.info()
+            print("   panels %d, column tiles %d" % (inf["n_panels"], inf["n_col_tiles"]), file=sys.stderr, flush=True)
         print("width %8d (%8.1f KB of x): %8.1f us" % (wm, wm * 4 / 1024, res[-1][1]), file=sys.stderr, flush=True)
+        tm.close()
     base = res[0][1]
     knee = max(w for w, us in res if us <= 1.1 * base)
     print(json.dumps({"graph": a.graph, "nnz": int(A.nnz), "widths": [w for w, _ in res],

@@ -1062,6 +1062,24 @@ void check_descriptors(const std::vector<Wl>& dwl, const std::vector<HostWl>& wl
 // Workload size of the automatic row panels (see tc_build_tiled).
 constexpr int64_t kPanelWl = 512;
 
+// f(i) for i in [0, n) on up to 16 host threads when there are at least
+// `min_par` items (each i touches only its own outputs).
+template <class F>
+void parallel_for(int64_t n, int64_t min_par, F&& f) {
+  const int nthr = n >= min_par ? (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency())) : 1;
+  if (nthr <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> pool;
+  for (int k = 0; k < nthr; ++k)
+    pool.emplace_back([&]() {
+      for (int64_t i; (i = next.fetch_add(1)) < n;) f(i);
+    });
+  for (auto& th : pool) th.join();
+}
+
 // compute units and LDS of the current device
 void device_limits(tc_handle* h) {
   int dev = 0, cus = 0;
@@ -1562,7 +1580,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   std::vector<std::vector<HostWl>> twls(ntiles);
   std::vector<double> tmodel(ntiles, 0.0);
   std::vector<int> tbad(ntiles, 0);
-  auto tile_job = [&](int t) {
+  auto tile_job = [&](int64_t t) {
     const std::vector<LenRun>& runs = truns[t];
     PartitionParams pt = pp;
     pt.split_len = (int32_t)h->tile_split[t];
@@ -1584,25 +1602,27 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     if (!runs.empty()) tmodel[t] = model_time(runs, WLt, table, sparse_t, pt);
     partition_tile(runs, WLt, t, trow[t], pt, &twls[t]);
   };
-  const int nthr = ntiles >= 64 ? (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency())) : 1;
-  if (nthr > 1) {
-    std::atomic<int> next{0};
-    std::vector<std::thread> pool;
-    for (int i = 0; i < nthr; ++i)
-      pool.emplace_back([&]() {
-        for (int t; (t = next.fetch_add(1)) < ntiles;) tile_job(t);
-      });
-    for (auto& th : pool) th.join();
-  } else {
-    for (int t = 0; t < ntiles; ++t) tile_job(t);
-  }
+  parallel_for(ntiles, 64, tile_job);
+  // workload, element and row-id offsets of every tile, then the tiles'
+  // workloads copied into place in parallel
+  std::vector<int64_t> tdoff(ntiles + 1, 0), troff(ntiles + 1, 0);
   for (int t = 0; t < ntiles; ++t) {
     if (tbad[t]) throw Fail{TC_EINVAL, "workload size must be >= 1"};
     h->model_us += tmodel[t];
-    h->tile_wl_begin[t] = (int64_t)wls.size();
-    wls.insert(wls.end(), twls[t].begin(), twls[t].end());
+    h->tile_wl_begin[t + 1] = h->tile_wl_begin[t] + (int64_t)twls[t].size();
+    int64_t a = 0, r = 0;
+    for (const HostWl& w : twls[t]) {
+      const int64_t area = (int64_t)w.w_pad * w.h_pad;
+      a += area + ((h->camping_pad && area % 512 == 0) ? 64 : 0);
+      r += w.h_pad;
+    }
+    tdoff[t + 1] = tdoff[t] + a;
+    troff[t + 1] = troff[t] + r;
   }
-  h->tile_wl_begin[ntiles] = (int64_t)wls.size();
+  wls.resize((size_t)h->tile_wl_begin[ntiles]);
+  parallel_for(ntiles, 64, [&](int64_t t) {
+    std::copy(twls[t].begin(), twls[t].end(), wls.begin() + h->tile_wl_begin[t]);
+  });
   clk.mark("a6 sizes and partition");
   h->d_tile_wl_begin = hold<int64_t>(h, ntiles + 1);
   HIPX(hipMemcpyAsync(h->d_tile_wl_begin, h->tile_wl_begin.data(), sizeof(int64_t) * (ntiles + 1),
@@ -1682,26 +1702,27 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->n_slots = (int64_t)chunk_wl.size();
   h->n_split_rows = (int64_t)srows.size();
 
-  // offsets
-  int64_t doff = 0, roff = 0;
+  // offsets (per tile in parallel from the tile prefix sums); chunk slots after
+  const int64_t doff = tdoff[ntiles], roff = troff[ntiles];
   std::vector<Wl> dwl(nwl);
   std::vector<PackWl> pwl(nwl);
-  size_t cq = 0;
-  for (int64_t j = 0; j < nwl; ++j) {
-    HostWl& w = wls[j];
-    const int64_t area = (int64_t)w.w_pad * w.h_pad;
-    const int32_t extra = (h->camping_pad && area % 512 == 0) ? 64 : 0;
-    w.data_off = doff;
-    w.rowid_off = roff;
-    int32_t info = w.layout;
-    if (w.chunk >= 0) info = kChunk | (slot_of[cq++] << 2);
-    dwl[j] = Wl{doff, roff, w.w_pad, w.h_pad, w.n_rows, info};
-    const int32_t coff = w.chunk >= 0 ? (int32_t)(w.chunk * h->tile_split[w.tile]) : -1;
-    pwl[j] = PackWl{doff, roff, w.w_pad, w.h_pad, w.n_rows, w.layout, w.row_begin, coff, w.w,
-                    (int32_t)h->tile_col_begin[w.tile], extra, w.tile};
-    doff += area + extra;
-    roff += w.h_pad;
-  }
+  parallel_for(ntiles, 64, [&](int64_t t) {
+    int64_t d = tdoff[t], r = troff[t];
+    for (int64_t j = h->tile_wl_begin[t]; j < h->tile_wl_begin[t + 1]; ++j) {
+      HostWl& w = wls[j];
+      const int64_t area = (int64_t)w.w_pad * w.h_pad;
+      const int32_t extra = (h->camping_pad && area % 512 == 0) ? 64 : 0;
+      w.data_off = d;
+      w.rowid_off = r;
+      dwl[j] = Wl{d, r, w.w_pad, w.h_pad, w.n_rows, w.layout};
+      const int32_t coff = w.chunk >= 0 ? (int32_t)(w.chunk * h->tile_split[w.tile]) : -1;
+      pwl[j] = PackWl{d, r, w.w_pad, w.h_pad, w.n_rows, w.layout, w.row_begin, coff, w.w,
+                      (int32_t)h->tile_col_begin[w.tile], extra, w.tile};
+      d += area + extra;
+      r += w.h_pad;
+    }
+  });
+  for (size_t q = 0; q < chunk_wl.size(); ++q) dwl[chunk_wl[q]].info = kChunk | (slot_of[q] << 2);
   h->nnz_pad = doff;
   h->n_rowid = roff;
   if (doff >= ((int64_t)1 << 40)) throw Fail{TC_EUNSUPPORTED, "padded format too large"};

@@ -100,6 +100,61 @@ def test_full_size_pagerank_100_iterations(cl23, cl23_handle):
 
 
 @pytest.fixture(scope="module")
+def cl23_panels(cl23):
+    # the configuration bench.py times: automatic row panels
+    tm = TiledMatrix(DeviceCsr(cl23), panels=-1)
+    yield tm
+    tm.close()
+
+
+def test_full_size_panels_spmv_all_rows_and_tile_order(cl23, cl23_panels):
+    inf = cl23_panels.info()
+    say("panels", inf["n_panels"], "column tiles", inf["n_col_tiles"], "rows", inf["panel_rows"])
+    assert inf["n_panels"] > 1 and inf["n_col_tiles"] > 1
+    n = cl23[0]
+    x = gg.uniform_f32(n, 101)
+    assert_spmv_all_rows(cl23_panels, cl23, x)
+    # the one-launch panel pass gives the bits of the tile-by-tile launches
+    xt = torch.from_numpy(x).cuda()
+    ya, yb = torch.empty(n, device="cuda"), torch.empty(n, device="cuda")
+    cl23_panels.spmv_internal(xt, ya)
+    cl23_panels.spmv_tiles(xt, yb)
+    assert torch.equal(ya.view(torch.int32), yb.view(torch.int32))
+
+
+def test_full_size_panels_pagerank_100_iterations(cl23, cl23_panels):
+    # 99 iterations with the update fused into the panel pass, the last one separate
+    p, it, _ = cl23_panels.pagerank(0.85, 0.0, 100)
+    ref, _, _ = oracle.pagerank(cl23, 0.85, 0.0, 100)
+    p = p.cpu().numpy().astype(np.float64)
+    assert it == 100
+    assert np.abs(p - ref).sum() <= 1e-6
+    assert abs(p.sum() - 1.0) <= 1e-5
+
+
+def test_rmat20_panels_format_bit_exact(rmat20):
+    # automatic row panels on R-MAT 20: every array against the reference
+    # builder given the parameters the handle reports
+    csr = gg.pagerank_matrix(rmat20)
+    with TiledMatrix(DeviceCsr(csr), panels=-1) as tm:
+        inf = tm.info()
+        f = tm.export_format()
+        T = inf["n_dense_tiles"]
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        P = min(n_cu, -(-csr[0] // 2048))
+        say("rmat20 panels", inf["n_panels"], "col tiles", inf["n_col_tiles"], "reference build ...")
+        ref = rf.build(csr, W=inf["tile_width"], bounds=[int(v) for v in f["tile_col_end"][:T]],
+                       wl=[512] * inf["n_tiles"], split_len=1024, panels=P, panel_rows=inf["panel_rows"],
+                       panel_waves=inf["panel_waves"])
+        assert f["n_tiles_total"] == ref["n_tiles_total"] and f["nnz_pad"] == ref["nnz_pad"]
+        for k in FMT_KEYS + ["panel_begin"]:
+            a, b = np.asarray(f[k]), np.asarray(ref[k])
+            assert a.shape == b.shape and np.array_equal(a.astype(np.int64), b.astype(np.int64)), k
+        assert np.array_equal(f["val"].view(np.uint32), ref["val"].view(np.uint32))
+        assert_spmv_all_rows(tm, csr, gg.uniform_f32(rmat20.n, 7))
+
+
+@pytest.fixture(scope="module")
 def rmat20_rwr():
     g = gg.rmat(20, 16, seed=20)
     W = gg.rwr_matrix(g)
