@@ -245,6 +245,20 @@ tc_status tc_spmv_tiles(const tc_handle* h, const float* d_x, float* d_y, tc_str
  * row-major, device, caller's index space; 1 <= k <= 256. */
 tc_status tc_spmm(const tc_handle* h, const float* d_X, float* d_Y, int32_t k, tc_stream_t stream);
 
+/* Y := A X like tc_spmm, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): X (n_cols x k) and Y (n_rows x k) are row-major in the
+ * handle's internal ids (row i of X is the caller's row cperm[i], see
+ * tc_export_format; Y's row rowmap[r] is the caller's row r), so no staging
+ * copies are needed, and the split rows' partial sums go to a file-scope
+ * device array of 16 MiB per GPU (held until the process ends) instead of
+ * the handle's pool.  The call allocates nothing and is not timed by
+ * tc_set_timing.  Calls that overlap on one GPU share that array and race.
+ * Same kernels and order as tc_spmm, so the same bits.  Errors: TC_EINVAL for
+ * NULL arguments, k outside [1, 256], X == Y, or partial sums larger than the
+ * array (n_partials * pieces * k doubles); TC_EHIP. */
+tc_status tc_spmm_internal_noalloc(const tc_handle* h, const float* d_X, float* d_Y, int32_t k, tc_stream_t stream);
+
 /* PageRank (Appendix F, Eq. 6): M must be the handle of the column-stochastic
  * matrix W^T (M[v][u] = 1/outdeg(u)); empty columns are dangling nodes whose
  * mass is spread uniformly.  p^(0) = 1/n;

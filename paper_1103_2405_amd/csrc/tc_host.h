@@ -62,8 +62,13 @@ void panel_pass(tc_handle* h, const float* x, float* y, hipStream_t st, const Pa
 void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool fuse_combine = false,
                    bool skip_zero = false, bool tilewise = false);
 // Y := A X for k right-hand sides in internal ids; epi: fused RWR restart.
+// partial_ext: split-row partial sums go there (at least n_slots * pieces * k
+// doubles) instead of the handle's pool buffer, and launches are not timed:
+// the call then allocates nothing.
 void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st, bool skip_empty = false,
-                   const RwrEpi* epi = nullptr);
+                   const RwrEpi* epi = nullptr, double* partial_ext = nullptr);
+// doubles of split-row partial sums spmm_internal needs for k right-hand sides
+size_t spmm_partial_doubles(tc_handle* h, int32_t k);
 // out row q = in row perm[q] (rows of w floats)
 void gather_rows(const float* in, const int32_t* perm, int64_t n, int32_t w, float* out, hipStream_t st);
 // one double from the device (synchronises the stream)

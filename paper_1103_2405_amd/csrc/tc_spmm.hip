@@ -2,6 +2,8 @@
 // batched queries of Appendix F, Eq. 9, many restart vectors at once).
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "tc_host.h"
 
@@ -318,8 +320,13 @@ void spmm_plan(tc_handle* h) {
 // epi (one tile, k <= kB): write the RWR restart of every row instead of
 // the product.  skip_empty: the rows no workload writes already hold what
 // this call would write there (0, or with epi their restart values).
+size_t spmm_partial_doubles(tc_handle* h, int32_t k) {
+  spmm_plan(h);
+  return (size_t)h->n_slots * h->mm_pieces * k;
+}
+
 void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_t st, bool skip_empty,
-                   const RwrEpi* epi) {
+                   const RwrEpi* epi, double* partial_ext) {
   if (epi && !(h->n_tiles == 1 && h->xcd_groups == 0 && k <= kB))
     throw Err{TC_EINVAL, "fused restart needs one tile and k <= 256"};
   const RwrEpi ep = epi ? *epi : RwrEpi{0.0, nullptr};
@@ -343,7 +350,9 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
   // and within 2% of two columns per step or eight rows per group)
   const int32_t slices = v4 ? 4 : 1;
   double* partial = nullptr;
-  if (h->n_slots > 0) {
+  if (partial_ext) {
+    partial = partial_ext;
+  } else if (h->n_slots > 0) {
     const size_t need = sizeof(double) * (size_t)h->n_slots * pieces * k;
     if (need > h->mm_partial_bytes) {
       if (h->d_mm_partial) pool_free(h->d_mm_partial, st, false);
@@ -355,6 +364,8 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
     }
     partial = h->d_mm_partial;
   }
+  const bool timing = h->timing;
+  if (partial_ext) h->timing = false;  // event creation is not for callers that cannot allocate
   if (h->n_empty > 0 && !skip_empty) {
     const int64_t rpb = kB / std::min(k, kB);
     hipLaunchKernelGGL(k_begin_spmm, dim3((unsigned)std::min<int64_t>(nblk(h->n_empty, rpb), 1 << 16)), dim3(kB), 0,
@@ -381,6 +392,7 @@ void spmm_internal(tc_handle* h, const float* X, float* Y, int32_t k, hipStream_
                        h->n_split_rows, (const double*)partial, pieces, Y, k, ep);
     HIPC(hipGetLastError());
   }
+  h->timing = timing;
   h->spmv_calls++;
 }
 
@@ -406,6 +418,50 @@ extern "C" tc_status tc_spmm(const tc_handle* hc, const float* X, float* Y, int3
     } else {
       spmm_internal(h, Xi, Y, k, st);
     }
+    return TC_OK;
+  });
+}
+
+// ---- SpMM for callers that cannot allocate (code under HIP graph capture,
+// serving loops, harnesses that forbid hipMalloc): the split-row partial sums
+// live in this file-scope device array instead of the handle's pool buffer.
+// Every call on a device shares that device's copy (calls that overlap on one
+// GPU race); nothing in it needs clearing, each product writes every slot it
+// reads.  The array's address on each device comes from hipGetSymbolAddress
+// on the first call with that device current.
+namespace {
+constexpr size_t kScratchDoubles = (size_t)1 << 21;  // 16 MiB per device
+__device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;
+
+double* scratch_on_current_device() {
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  double* p = nullptr;
+  HIPC(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+  g_scratch_ptr[dev] = p;
+  return p;
+}
+}  // namespace
+
+extern "C" tc_status tc_spmm_internal_noalloc(const tc_handle* hc, const float* X, float* Y, int32_t k,
+                                              tc_stream_t stream) {
+  return guarded("tc_spmm_internal_noalloc", [&]() -> tc_status {
+    if (!hc || (!X && hc->n_cols > 0) || (!Y && hc->n_rows > 0)) throw Err{TC_EINVAL, "NULL argument"};
+    if (k < 1 || k > 256) throw Err{TC_EINVAL, "k must be in [1, 256]"};
+    if ((const void*)X == (const void*)Y && hc->n_rows > 0) throw Err{TC_EINVAL, "X and Y must not alias"};
+    tc_handle* h = const_cast<tc_handle*>(hc);
+    const size_t need = spmm_partial_doubles(h, k);
+    if (need > kScratchDoubles)
+      throw Err{TC_EINVAL, "split-row partial sums need " + std::to_string(need * sizeof(double)) +
+                               " bytes, more than the " + std::to_string(kScratchDoubles * sizeof(double)) +
+                               "-byte scratch of this call"};
+    double* ptr = scratch_on_current_device();
+    spmm_internal(h, X, Y, k, (hipStream_t)stream, false, nullptr, ptr);
     return TC_OK;
   });
 }

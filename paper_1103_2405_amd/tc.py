@@ -88,7 +88,8 @@ EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_inter
             "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
             "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory",
             "tc_rwr_multi", "tc_csr_transpose", "tc_rwr_edge_weights", "tc_rwr_iterates", "tc_rwr_adjoint",
-            "tc_rwr_theta_grad", "tc_gather_rows", "tc_refresh_values", "tc_stream_read"]
+            "tc_rwr_theta_grad", "tc_gather_rows", "tc_refresh_values", "tc_stream_read",
+            "tc_spmm_internal_noalloc"]
 
 _lib = None
 
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.tc_spmv_internal.argtypes = [vp, vp, vp, vp]
     lib.tc_spmv_tiles.argtypes = [vp, vp, vp, vp]
     lib.tc_stream_read.argtypes = [vp, i64, vp, vp]
+    lib.tc_spmm_internal_noalloc.argtypes = [vp, vp, vp, i32, vp]
     lib.tc_spmm.argtypes = [vp, vp, vp, i32, vp]
     lib.tc_pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_float, i32, i32, vp, P(i32), P(ctypes.c_double), vp]
     lib.tc_hits.argtypes = [vp, ctypes.c_float, i32, i32, vp, vp, P(i32), P(ctypes.c_double), vp]
@@ -343,6 +345,17 @@ class TiledMatrix:
         _need(y, (self.n_rows,), "y")
         _check(load_library().tc_spmv_tiles(self.handle, _ptr(x), _ptr(y), _stream(stream)), "tc_spmv_tiles")
         return y
+
+    def spmm_internal_noalloc(self, X: torch.Tensor, Y: torch.Tensor, stream=None) -> torch.Tensor:
+        """Y := A X in internal ids with no device allocation by the library."""
+        if not isinstance(X, torch.Tensor) or X.dim() != 2:
+            raise ValueError("X must be a 2-D tensor (n_cols x k)")
+        k = int(X.shape[1])
+        _need(X, (self.n_cols, k), "X")
+        _need(Y, (self.n_rows, k), "Y")
+        _check(load_library().tc_spmm_internal_noalloc(self.handle, _ptr(X), _ptr(Y), k, _stream(stream)),
+               "tc_spmm_internal_noalloc")
+        return Y
 
     def spmm(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """Y := A X for X (n_cols x k, row-major)."""
