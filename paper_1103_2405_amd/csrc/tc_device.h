@@ -130,6 +130,9 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
     for (int q = 2 * sl; q < nchunk; q += 2 * S) {
       const int ra = q * rpc + my, rb = (q + 1) * rpc + my;
       const bool oka = ra < nr, okb = rb < nr;
+      // row ids read with the matrix loads (clamped to a valid entry; chunks have none to write)
+      const int32_t ida = chunk ? 0 : ld_nt(rowid + d.rowid_off + (oka ? ra : 0));
+      const int32_t idb = chunk ? 0 : ld_nt(rowid + d.rowid_off + (okb ? rb : 0));
       double sa = 0.0, sb = 0.0;
       v4i ia, ib;
       v4f va, vb;
@@ -154,8 +157,8 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
         if (chunk) {
           if (oka) partial[d.info >> 2] = sa;
         } else {
-          if (oka) x.addy(y, ld_nt(rowid + d.rowid_off + ra), sa);
-          if (okb) x.addy(y, ld_nt(rowid + d.rowid_off + rb), sb);
+          if (oka) x.addy(y, ida, sa);
+          if (okb) x.addy(y, idb, sb);
         }
       }
     }
@@ -163,6 +166,7 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
   }
   for (int32_t r = sl; r < nr; r += S) {
     const int64_t base = off + (int64_t)r * wp;
+    const int32_t idr = chunk ? 0 : ld_nt(rowid + d.rowid_off + r);
     double acc = 0.0;
     int32_t c = 4 * lane;
     for (; c + 256 < wp; c += 512) {
@@ -176,7 +180,7 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
       if (chunk)
         partial[d.info >> 2] = acc;
       else
-        x.addy(y, ld_nt(rowid + d.rowid_off + r), acc);
+        x.addy(y, idr, acc);
     }
   }
 }
@@ -197,11 +201,16 @@ __device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict_
   for (int32_t r0 = sl * kWave; r0 < nr; r0 += U * S * kWave) {
     double acc[U];
     bool ok[U];
+    int32_t rid[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       acc[u] = 0.0;
       ok[u] = r0 + u * S * kWave + lane < nr;
     }
+    // the rows' ids go out with the first matrix loads (a lane past the last
+    // row reads the workload's first id and never uses it)
+#pragma unroll
+    for (int u = 0; u < U; ++u) rid[u] = ld_nt(rowid + d.rowid_off + (ok[u] ? r0 + u * S * kWave + lane : 0));
     int32_t c = 0;
     for (; c + C <= w; c += C) {
       int32_t ii[U][C];
@@ -243,7 +252,7 @@ __device__ inline void cm_rows(const Wl& d, int lane, const int32_t* __restrict_
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (ok[u]) x.addy(y, ld_nt(rowid + d.rowid_off + r0 + u * S * kWave + lane), acc[u]);
+      if (ok[u]) x.addy(y, rid[u], acc[u]);
   }
 }
 
@@ -357,13 +366,19 @@ __device__ __attribute__((always_inline)) inline void run_workload(const Wl& d, 
   }
 }
 
-// S wavefronts per workload of the tile (row slices; grid = workloads * S / 4).
-
-// p[0] + p[s] + ... + p[(n-1) s], added in that order; eight loads go out
-// together (a split row can have dozens of chunks, summed by one thread)
+// p[0] + p[s] + ... + p[(n-1) s], added in that order; 32 loads go out
+// together, then 8 (a split row can have hundreds of chunks, summed by one
+// thread: the loads in flight set its time)
 __device__ inline double sum_slots(const double* __restrict__ p, int64_t n, int64_t s = 1) {
   double acc = 0.0;
   int64_t q = 0;
+  for (; q + 32 <= n; q += 32) {
+    double t[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) t[u] = p[(q + u) * s];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc += t[u];
+  }
   for (; q + 8 <= n; q += 8) {
     double t[8];
 #pragma unroll

@@ -109,11 +109,33 @@ __device__ inline void panel_tile(const G& xg, int64_t g, int32_t t, int32_t p, 
                                   const int64_t* __restrict__ cb, const int32_t* __restrict__ idx,
                                   const float* __restrict__ val, const int32_t* __restrict__ rowid, float* y,
                                   double* __restrict__ partial) {
+  // each wavefront's next descriptor is read while it runs the current one
   const int64_t e = wl_begin[g + 1];
-  for (int64_t j = ncb[g] + wv; j < e; j += NW) run_workload<1>(wl[j], lane, idx, val, rowid, xg, y, partial);
+  int64_t j = ncb[g] + wv;
+  if (j < e) {
+    Wl d = wl[j];
+    for (;;) {
+      const int64_t jn = j + NW;
+      const Wl dn = wl[jn < e ? jn : j];
+      run_workload<1>(d, lane, idx, val, rowid, xg, y, partial);
+      if (jn >= e) break;
+      d = dn;
+      j = jn;
+    }
+  }
   const int64_t ce = cb[t + 1];
-  for (int64_t k = cb[t] + p + (int64_t)wv * np; k < ce; k += (int64_t)NW * np)
-    run_workload<1>(wl[chunks[k]], lane, idx, val, rowid, xg, y, partial);
+  int64_t k = cb[t] + p + (int64_t)wv * np;
+  if (k < ce) {
+    Wl d = wl[chunks[k]];
+    for (;;) {
+      const int64_t kn = k + (int64_t)NW * np;
+      const Wl dn = wl[chunks[kn < ce ? kn : k]];
+      run_workload<1>(d, lane, idx, val, rowid, xg, y, partial);
+      if (kn >= ce) break;
+      d = dn;
+      k = kn;
+    }
+  }
 }
 
 // Row-panel pass (one launch per product).  Workgroup p owns internal rows
