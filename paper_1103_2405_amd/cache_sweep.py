@@ -4,10 +4,12 @@ The paper finds the tile width by taking the column indices modulo a width
 Wm, so that every x access falls in the first Wm entries, and sweeping Wm:
 the SpMV time stays flat while the segment fits the cache and rises beyond
 (the knee).  Here the matrix is the Chung-Lu PageRank matrix (or R-MAT 20),
-each modded matrix is built as one tile, and the tile-kernel time per product
-comes from HIP events around every launch.
+each modded matrix is built as one tile (or, with --panels, in row panels
+with column tiles), and the kernel time per product comes from HIP events
+around every launch.
 
     python -m paper_1103_2405_amd.cache_sweep [--graph cl23|rmat20] [--reps 10]
+        [--panels -1] [--widths 1024,8388608]
 
 Prints one JSON line: the widths, the microseconds per product, and the
 knee (the largest width within 10% of the time at the smallest width).

@@ -1390,6 +1390,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       b_row = (int32_t*)cr;
       b_val = cv;
     }
+    clk.mark("a4 bucket passes");
     int64_t* d_ts = tmp.get<int64_t>(ntiles + 1);
     hipLaunchKernelGGL(k_tile_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, b_icol, nnz, tmap, ntiles, d_ts);
     HIPX(hipGetLastError());
@@ -1454,6 +1455,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       tmp.release(flags);
       tmp.release(pos);
     }
+    clk.mark("a5 segment emission");
     if (h->n_panels > 0) {
       // row panels: every (panel, column tile) pair becomes a tile, panel-major
       const int32_t nct = ntiles;
@@ -1575,6 +1577,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       ++ri;
     }
   }
+  clk.mark("a6 runs");
   if (o->wl_policy == 1 && o->n_wl_per_tile < ntiles)
     throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
   std::vector<std::vector<HostWl>> twls(ntiles);
@@ -1603,6 +1606,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     partition_tile(runs, WLt, t, trow[t], pt, &twls[t]);
   };
   parallel_for(ntiles, 64, tile_job);
+  clk.mark("a6 tile partitions");
   // workload, element and row-id offsets of every tile, then the tiles'
   // workloads copied into place in parallel
   std::vector<int64_t> tdoff(ntiles + 1, 0), troff(ntiles + 1, 0);
@@ -1659,6 +1663,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipStreamSynchronize(st));  // host vectors above go out of scope
   }
 
+  clk.mark("a6 panel lists");
   // split rows: slots grouped by row, in (tile, chunk) order
   std::vector<int64_t> chunk_wl;
   for (int64_t j = 0; j < nwl; ++j)
@@ -1702,6 +1707,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->n_slots = (int64_t)chunk_wl.size();
   h->n_split_rows = (int64_t)srows.size();
 
+  clk.mark("a6 split rows");
   // offsets (per tile in parallel from the tile prefix sums); chunk slots after
   const int64_t doff = tdoff[ntiles], roff = troff[ntiles];
   std::vector<Wl> dwl(nwl);
@@ -1726,6 +1732,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->nnz_pad = doff;
   h->n_rowid = roff;
   if (doff >= ((int64_t)1 << 40)) throw Fail{TC_EUNSUPPORTED, "padded format too large"};
+  clk.mark("a6 descriptors");
   check_descriptors(dwl, wls, h->tile_row_off, h->n_slots, doff, roff);
 
   clk.mark("a6 partition");
