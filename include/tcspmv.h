@@ -404,9 +404,12 @@ tc_status tc_get_timing(tc_handle* h, tc_timing* t);
 void tc_destroy(tc_handle* h);
 
 /* Return every block cached in the library's device pool to HIP (all
- * devices; synchronous).  Handles still alive keep their memory.  Returns the
- * number of bytes released.  Setting TC_POOL=0 in the environment before the
- * first call disables the pool (every release then goes straight to hipFree). */
+ * devices; synchronous), and free the host blocks the builder keeps for reuse
+ * (page-locked transfer buffers, workload lists of destroyed handles).
+ * Handles still alive keep their memory.  Returns the number of bytes
+ * released, device and host together.  Setting TC_POOL=0 in the environment
+ * before the first call disables both pools (every release then goes straight
+ * to hipFree or free). */
 size_t tc_release_cached_memory(void);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -172,4 +172,4 @@ extern "C" void tc_destroy(tc_handle* h) {
   delete h;
 }
 
-extern "C" size_t tc_release_cached_memory(void) { return tc::pool_release_cached(); }
+extern "C" size_t tc_release_cached_memory(void) { return tc::pool_release_cached() + tc::host_release_cached(); }

@@ -14,8 +14,12 @@
 // pure function of the input and the options.
 #include <algorithm>
 #include <atomic>
-#include <thread>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -354,12 +358,6 @@ __global__ void k_expand_rows(const int64_t* __restrict__ rp, int64_t n_rows, in
   }
 }
 
-__global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __restrict__ at, int64_t n,
-                             int32_t* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = src[at[i]];
-}
-
 __global__ void k_icol(const int32_t* __restrict__ col, const int32_t* __restrict__ cpos, int64_t nnz,
                        int32_t* __restrict__ icol) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,13 +394,19 @@ __global__ void k_tile_bounds(const int32_t* __restrict__ b_icol, int64_t nnz, T
   tstart[t] = lo;
 }
 
-// a5: segment heads = first entry of each (tile, row) pair
-__global__ void k_seg_flags(const int32_t* __restrict__ b_icol, const int32_t* __restrict__ b_row, int64_t nnz,
-                            TileMap tm, int32_t* __restrict__ flags) {
+// a5: segment heads = first entry of each (tile, row) pair.  The entries are
+// bucketed by tile, so a head is a row change (this pass) or the first entry
+// of a tile (k_tile_heads, run after it).
+__global__ void k_seg_flags(const int32_t* __restrict__ b_row, int64_t nnz, int32_t* __restrict__ flags) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
-  int f = k == 0 || b_row[k] != b_row[k - 1] || tm(b_icol[k]) != tm(b_icol[k - 1]);
-  flags[k] = f;
+  flags[k] = k == 0 || b_row[k] != b_row[k - 1];
+}
+
+__global__ void k_tile_heads(const int64_t* __restrict__ tstart, int32_t ntiles, int64_t nnz,
+                             int32_t* __restrict__ flags) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntiles && tstart[t] < nnz) flags[tstart[t]] = 1;
 }
 
 __global__ void k_seg_emit(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos,
@@ -447,24 +451,24 @@ __global__ void k_seg_len(const int32_t* __restrict__ seg_start, int64_t nseg, i
 }
 
 __global__ void k_seg_keys(const int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_len,
-                           const int32_t* __restrict__ seg_row, int64_t nseg, int32_t maxlen, int lb, int rb,
-                           uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                           const int32_t* __restrict__ seg_row, const int32_t* __restrict__ seg_start, int64_t nseg,
+                           int32_t maxlen, int lb, int rb, uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nseg) return;
   keys[s] = ((uint64_t)seg_tile[s] << (lb + rb)) | ((uint64_t)(maxlen - seg_len[s]) << rb) | (uint64_t)seg_row[s];
-  vals[s] = (int32_t)s;
+  vals[s] = seg_start[s];
 }
 
-__global__ void k_seg_gather(const int32_t* __restrict__ perm, const int32_t* __restrict__ seg_row,
-                             const int32_t* __restrict__ seg_len, const int32_t* __restrict__ seg_start, int64_t nseg,
-                             int32_t* __restrict__ rows_sorted, int32_t* __restrict__ rows_len,
-                             int32_t* __restrict__ srt_start) {
+// sorted segments: row and length back from the key, start from the value
+__global__ void k_seg_decode(const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals, int64_t nseg,
+                             int32_t maxlen, int lb, int rb, int32_t* __restrict__ rows_sorted,
+                             int32_t* __restrict__ rows_len, int32_t* __restrict__ srt_start) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nseg) return;
-  int32_t s = perm[i];
-  rows_sorted[i] = seg_row[s];
-  rows_len[i] = seg_len[s];
-  srt_start[i] = seg_start[s];
+  const uint64_t k = keys[i];
+  rows_sorted[i] = (int32_t)(k & (((uint64_t)1 << rb) - 1));
+  rows_len[i] = maxlen - (int32_t)((k >> rb) & (((uint64_t)1 << lb) - 1));
+  srt_start[i] = vals[i];
 }
 
 // start of each tile in the sorted segment keys (tile in the top bits)
@@ -494,6 +498,17 @@ __global__ void k_run_emit(const int32_t* __restrict__ flags, const int32_t* __r
     run_pos[pos[i]] = i;
     run_len[pos[i]] = rows_len[i];
   }
+}
+
+// rows of the split rows' chunks (sorted-row positions at) and each row's first tile
+__global__ void k_chunk_rows(const int32_t* __restrict__ rows_sorted, const int32_t* __restrict__ first,
+                             const int32_t* __restrict__ at, int64_t nc, int32_t* __restrict__ row,
+                             int32_t* __restrict__ row_first) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  const int32_t r = rows_sorted[at[q]];
+  row[q] = r;
+  row_first[q] = first[r];
 }
 
 // first tile in which each row sits in a workload that is not a split chunk
@@ -1038,10 +1053,10 @@ struct PhaseClock {
 // within [0, n_slots), and its rows within its tile's sorted rows.  The
 // offsets come from a running sum, so a violation is a bug in the partition;
 // it is reported instead of handing a kernel an address outside a buffer.
-void check_descriptors(const std::vector<Wl>& dwl, const std::vector<HostWl>& wls,
+void check_descriptors(const Wl* dwl, const HostArray<HostWl>& wls,
                        const std::vector<int64_t>& tile_row_off, int64_t n_slots, int64_t nnz_pad, int64_t n_rowid) {
   const int64_t ntiles = (int64_t)tile_row_off.size() - 1;
-  for (size_t j = 0; j < dwl.size(); ++j) {
+  for (size_t j = 0; j < wls.size(); ++j) {
     const Wl& d = dwl[j];
     const HostWl& w = wls[j];
     const int layout = d.info & 3;
@@ -1062,23 +1077,97 @@ void check_descriptors(const std::vector<Wl>& dwl, const std::vector<HostWl>& wl
 // Workload size of the automatic row panels (see tc_build_tiled).
 constexpr int64_t kPanelWl = 512;
 
-// f(i) for i in [0, n) on up to 16 host threads when there are at least
-// `min_par` items (each i touches only its own outputs).
+// Host threads for the builder's per-tile loops: started on first use and
+// kept for the life of the process, so a build pays no thread start-up.  One
+// loop runs on them at a time; a loop issued while another runs (builds on two
+// host threads at once) runs on its calling thread alone.
+class HostPool {
+ public:
+  static HostPool& get() {
+    static HostPool* p = new HostPool();  // never destroyed: idle threads end with the process
+    return *p;
+  }
+  // f(i) for i in [0, n) on the pool and the calling thread; false if the
+  // pool is busy or empty (nothing was run)
+  bool run(int64_t n, const std::function<void(int64_t)>& f) {
+    std::unique_lock<std::mutex> busy(busy_, std::try_to_lock);
+    if (!busy.owns_lock() || th_.empty()) return false;
+    {
+      std::lock_guard<std::mutex> g(m_);
+      f_ = &f;
+      n_ = n;
+      next_.store(0);
+      pending_ = (int)th_.size();
+      ++gen_;
+    }
+    wake_.notify_all();
+    work();
+    std::unique_lock<std::mutex> g(m_);
+    done_.wait(g, [&] { return pending_ == 0; });
+    f_ = nullptr;
+    return true;
+  }
+
+ private:
+  HostPool() {
+    const int k = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency())) - 1;
+    for (int i = 0; i < k; ++i) th_.emplace_back([this] { loop(); });
+  }
+  void work() {
+    for (int64_t i; (i = next_.fetch_add(1)) < n_;) (*f_)(i);
+  }
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> g(m_);
+    for (;;) {
+      wake_.wait(g, [&] { return gen_ != seen; });
+      seen = gen_;
+      g.unlock();
+      work();
+      g.lock();
+      if (--pending_ == 0) done_.notify_one();
+    }
+  }
+  std::mutex busy_, m_;
+  std::condition_variable wake_, done_;
+  const std::function<void(int64_t)>* f_ = nullptr;
+  int64_t n_ = 0;
+  std::atomic<int64_t> next_{0};
+  int pending_ = 0;
+  uint64_t gen_ = 0;
+  std::vector<std::thread> th_;
+};
+
+// f(i) for i in [0, n) on the host pool when there are at least `min_par`
+// items (each i touches only its own outputs), else on this thread.
 template <class F>
 void parallel_for(int64_t n, int64_t min_par, F&& f) {
-  const int nthr = n >= min_par ? (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency())) : 1;
-  if (nthr <= 1) {
-    for (int64_t i = 0; i < n; ++i) f(i);
-    return;
+  if (n >= min_par) {
+    const std::function<void(int64_t)> fn = [&](int64_t i) { f(i); };
+    if (HostPool::get().run(n, fn)) return;
   }
-  std::atomic<int64_t> next{0};
-  std::vector<std::thread> pool;
-  for (int k = 0; k < nthr; ++k)
-    pool.emplace_back([&]() {
-      for (int64_t i; (i = next.fetch_add(1)) < n;) f(i);
-    });
-  for (auto& th : pool) th.join();
+  for (int64_t i = 0; i < n; ++i) f(i);
 }
+
+// n items of T in a page-locked host block from the library's host pool, for
+// the life of one build step.  The block goes back to the pool when its
+// holder ends, after the build stream has finished every copy that may still
+// read or write it.
+template <class T>
+struct Staged {
+  HostBlock b;
+  hipStream_t st;
+  T* p;
+  Staged(int64_t n, hipStream_t s)
+      : b(host_take(sizeof(T) * (size_t)std::max<int64_t>(n, 1), true)), st(s), p((T*)b.p) {}
+  ~Staged() {
+    (void)hipStreamSynchronize(st);
+    host_give(b);
+  }
+  Staged(const Staged&) = delete;
+  Staged& operator=(const Staged&) = delete;
+  T& operator[](int64_t i) { return p[i]; }
+};
 
 // compute units and LDS of the current device
 void device_limits(tc_handle* h) {
@@ -1348,6 +1437,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   int32_t *b_icol = nullptr, *b_row = nullptr;
   const float* b_val = nullptr;
   std::vector<int64_t> tstart(ntiles + 1, 0);
+  int64_t* d_ts = nullptr;  // tstart on the device
   // value map: entry indices stand in for the values through a4-a7
   const float* vsrc = A->val;
   if (o->value_map && nnz > 0) {
@@ -1391,7 +1481,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       b_val = cv;
     }
     clk.mark("a4 bucket passes");
-    int64_t* d_ts = tmp.get<int64_t>(ntiles + 1);
+    d_ts = tmp.get<int64_t>(ntiles + 1);
     hipLaunchKernelGGL(k_tile_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, b_icol, nnz, tmap, ntiles, d_ts);
     HIPX(hipGetLastError());
     HIPX(hipMemcpyAsync(tstart.data(), d_ts, sizeof(int64_t) * (ntiles + 1), hipMemcpyDeviceToHost, st));
@@ -1417,8 +1507,9 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   int64_t nseg = 0;
   int32_t *rows_sorted = nullptr, *rows_len = nullptr, *srt_start = nullptr;
   std::vector<int64_t> trow(ntiles + 1, 0);
-  std::vector<int64_t> run_pos;
-  std::vector<int32_t> run_len;
+  std::unique_ptr<Staged<int64_t>> run_pos;  // start and length of every (tile, length) run
+  std::unique_ptr<Staged<int32_t>> run_len;
+  int64_t nruns = 0;
   if (nnz > 0) {
     int32_t *seg_start, *seg_row, *seg_tile, *seg_len;
     if (one_tile) {
@@ -1440,7 +1531,9 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     } else {
       int32_t* flags = tmp.get<int32_t>(nnz);
       int32_t* pos = tmp.get<int32_t>(nnz);
-      hipLaunchKernelGGL(k_seg_flags, dim3(nblk(nnz, kB)), dim3(kB), 0, st, b_icol, b_row, nnz, tmap, flags);
+      hipLaunchKernelGGL(k_seg_flags, dim3(nblk(nnz, kB)), dim3(kB), 0, st, b_row, nnz, flags);
+      hipLaunchKernelGGL(k_tile_heads, dim3(nblk(ntiles, kB)), dim3(kB), 0, st, (const int64_t*)d_ts, ntiles, nnz,
+                         flags);
       HIPX(hipGetLastError());
       nseg = excl_scan<int32_t, int32_t>(flags, nnz, pos, tmp, st);
       seg_start = tmp.get<int32_t>(nseg);
@@ -1493,8 +1586,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     uint64_t* k1 = tmp.get<uint64_t>(nseg);
     int32_t* v0 = tmp.get<int32_t>(nseg);
     int32_t* v1 = tmp.get<int32_t>(nseg);
-    hipLaunchKernelGGL(k_seg_keys, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg, maxlen, lb,
-                       rb, k0, v0);
+    hipLaunchKernelGGL(k_seg_keys, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, seg_start, nseg,
+                       maxlen, lb, rb, k0, v0);
     HIPX(hipGetLastError());
     // one tile: the segments already come in increasing row (the key's low
     // rb bits), so the stable passes over the length bits finish the order
@@ -1507,8 +1600,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     rows_sorted = hold<int32_t>(h, nseg);
     rows_len = hold<int32_t>(h, nseg);
     srt_start = tmp.get<int32_t>(nseg);
-    hipLaunchKernelGGL(k_seg_gather, dim3(nblk(nseg, kB)), dim3(kB), 0, st, v0, seg_row, seg_len, seg_start, nseg,
-                       rows_sorted, rows_len, srt_start);
+    hipLaunchKernelGGL(k_seg_decode, dim3(nblk(nseg, kB)), dim3(kB), 0, st, (const uint64_t*)k0, (const int32_t*)v0,
+                       nseg, maxlen, lb, rb, rows_sorted, rows_len, srt_start);
     HIPX(hipGetLastError());
     int64_t* d_off = tmp.get<int64_t>(ntiles + 1);
     hipLaunchKernelGGL(k_key_bounds, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, k0, nseg, lb + rb, ntiles, d_off);
@@ -1530,15 +1623,15 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     int32_t* rpos = tmp.get<int32_t>(nseg);
     hipLaunchKernelGGL(k_run_flags, dim3(nblk(nseg, kB)), dim3(kB), 0, st, k0, nseg, rb, rflags);
     HIPX(hipGetLastError());
-    const int64_t nruns = excl_scan<int32_t, int32_t>(rflags, nseg, rpos, tmp, st);
+    nruns = excl_scan<int32_t, int32_t>(rflags, nseg, rpos, tmp, st);
     int64_t* d_rp = tmp.get<int64_t>(nruns);
     int32_t* d_rl = tmp.get<int32_t>(nruns);
     hipLaunchKernelGGL(k_run_emit, dim3(nblk(nseg, kB)), dim3(kB), 0, st, rflags, rpos, rows_len, nseg, d_rp, d_rl);
     HIPX(hipGetLastError());
-    run_pos.resize(nruns);
-    run_len.resize(nruns);
-    HIPX(hipMemcpyAsync(run_pos.data(), d_rp, sizeof(int64_t) * nruns, hipMemcpyDeviceToHost, st));
-    HIPX(hipMemcpyAsync(run_len.data(), d_rl, sizeof(int32_t) * nruns, hipMemcpyDeviceToHost, st));
+    run_pos.reset(new Staged<int64_t>(nruns, st));
+    run_len.reset(new Staged<int32_t>(nruns, st));
+    HIPX(hipMemcpyAsync(run_pos->p, d_rp, sizeof(int64_t) * nruns, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(run_len->p, d_rl, sizeof(int32_t) * nruns, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
   }
   if (nnz == 0 && h->n_panels > 0) {
@@ -1563,19 +1656,22 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
                      h->camping_pad};
   h->tile_wl.assign(ntiles, 0);
   h->tile_wl_begin.assign(ntiles + 1, 0);
-  std::vector<HostWl>& wls = h->wls;
-  wls.clear();
+  HostArray<HostWl>& wls = h->wls;
+  wls.release();
   // Runs of each tile, then Algorithm 2 and the partition tile by tile; the
   // tiles are independent, so with many tiles (row panels) they are spread
   // over host threads, each writing its own tiles' workload lists.
+  // (every run lies in one tile: the tile is in the key's top bits)
   std::vector<std::vector<LenRun>> truns(ntiles);
-  size_t ri = 0;
-  for (int t = 0; t < ntiles; ++t) {
-    while (ri < run_pos.size() && run_pos[ri] < trow[t + 1]) {
-      const int64_t end = ri + 1 < run_pos.size() ? std::min(run_pos[ri + 1], trow[t + 1]) : trow[t + 1];
-      truns[t].push_back(LenRun{run_len[ri], end - run_pos[ri]});
-      ++ri;
-    }
+  if (nruns > 0) {
+    const int64_t* rp = run_pos->p;
+    const int32_t* rl = run_len->p;
+    parallel_for(ntiles, 64, [&](int64_t t) {
+      for (int64_t ri = std::lower_bound(rp, rp + nruns, trow[t]) - rp; ri < nruns && rp[ri] < trow[t + 1]; ++ri) {
+        const int64_t end = ri + 1 < nruns ? std::min(rp[ri + 1], trow[t + 1]) : trow[t + 1];
+        truns[t].push_back(LenRun{rl[ri], end - rp[ri]});
+      }
+    });
   }
   clk.mark("a6 runs");
   if (o->wl_policy == 1 && o->n_wl_per_tile < ntiles)
@@ -1583,6 +1679,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   std::vector<std::vector<HostWl>> twls(ntiles);
   std::vector<double> tmodel(ntiles, 0.0);
   std::vector<int> tbad(ntiles, 0);
+  // per tile: padded elements and stored row ids of its workloads
+  std::vector<int64_t> tdoff(ntiles + 1, 0), troff(ntiles + 1, 0);
   auto tile_job = [&](int64_t t) {
     const std::vector<LenRun>& runs = truns[t];
     PartitionParams pt = pp;
@@ -1604,28 +1702,29 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     h->tile_wl[t] = WLt;
     if (!runs.empty()) tmodel[t] = model_time(runs, WLt, table, sparse_t, pt);
     partition_tile(runs, WLt, t, trow[t], pt, &twls[t]);
-  };
-  parallel_for(ntiles, 64, tile_job);
-  clk.mark("a6 tile partitions");
-  // workload, element and row-id offsets of every tile, then the tiles'
-  // workloads copied into place in parallel
-  std::vector<int64_t> tdoff(ntiles + 1, 0), troff(ntiles + 1, 0);
-  for (int t = 0; t < ntiles; ++t) {
-    if (tbad[t]) throw Fail{TC_EINVAL, "workload size must be >= 1"};
-    h->model_us += tmodel[t];
-    h->tile_wl_begin[t + 1] = h->tile_wl_begin[t] + (int64_t)twls[t].size();
     int64_t a = 0, r = 0;
     for (const HostWl& w : twls[t]) {
       const int64_t area = (int64_t)w.w_pad * w.h_pad;
       a += area + ((h->camping_pad && area % 512 == 0) ? 64 : 0);
       r += w.h_pad;
     }
-    tdoff[t + 1] = tdoff[t] + a;
-    troff[t + 1] = troff[t] + r;
+    tdoff[t + 1] = a;
+    troff[t + 1] = r;
+  };
+  parallel_for(ntiles, 64, tile_job);
+  clk.mark("a6 tile partitions");
+  // workload, element and row-id offsets of every tile, then the tiles'
+  // workloads copied into place in parallel
+  for (int t = 0; t < ntiles; ++t) {
+    if (tbad[t]) throw Fail{TC_EINVAL, "workload size must be >= 1"};
+    h->model_us += tmodel[t];
+    h->tile_wl_begin[t + 1] = h->tile_wl_begin[t] + (int64_t)twls[t].size();
+    tdoff[t + 1] += tdoff[t];
+    troff[t + 1] += troff[t];
   }
-  wls.resize((size_t)h->tile_wl_begin[ntiles]);
+  wls.reset(h->tile_wl_begin[ntiles]);
   parallel_for(ntiles, 64, [&](int64_t t) {
-    std::copy(twls[t].begin(), twls[t].end(), wls.begin() + h->tile_wl_begin[t]);
+    std::copy(twls[t].begin(), twls[t].end(), wls.data() + h->tile_wl_begin[t]);
   });
   clk.mark("a6 sizes and partition");
   h->d_tile_wl_begin = hold<int64_t>(h, ntiles + 1);
@@ -1668,29 +1767,22 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   std::vector<int64_t> chunk_wl;
   for (int64_t j = 0; j < nwl; ++j)
     if (wls[j].chunk >= 0) chunk_wl.push_back(j);
-  std::vector<int32_t> chunk_row(chunk_wl.size());
+  std::vector<int32_t> chunk_row(chunk_wl.size()), chunk_first(chunk_wl.size());
   if (!chunk_wl.empty()) {
-    // row ids of split rows (they sit at the start of their tile's sorted rows)
+    // row ids of split rows (they sit at the start of their tile's sorted
+    // rows) and the first tile that writes each
     const int64_t nc = (int64_t)chunk_wl.size();
     std::vector<int32_t> at(nc);
     for (int64_t q = 0; q < nc; ++q) at[q] = wls[chunk_wl[q]].row_begin;
     int32_t* d_at = tmp.get<int32_t>(nc);
     int32_t* d_r = tmp.get<int32_t>(nc);
+    int32_t* d_f = tmp.get<int32_t>(nc);
     HIPX(hipMemcpyAsync(d_at, at.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_gather_i32, dim3(nblk(nc, kB)), dim3(kB), 0, st, rows_sorted, d_at, nc, d_r);
+    hipLaunchKernelGGL(k_chunk_rows, dim3(nblk(nc, kB)), dim3(kB), 0, st, (const int32_t*)rows_sorted,
+                       (const int32_t*)first, (const int32_t*)d_at, nc, d_r, d_f);
     HIPX(hipGetLastError());
     HIPX(hipMemcpyAsync(chunk_row.data(), d_r, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st));
-    HIPX(hipStreamSynchronize(st));
-  }
-  std::vector<int32_t> chunk_first(chunk_wl.size());
-  if (!chunk_wl.empty()) {
-    const int64_t nc = (int64_t)chunk_wl.size();
-    int32_t* d_at = tmp.get<int32_t>(nc);
-    int32_t* d_r = tmp.get<int32_t>(nc);
-    HIPX(hipMemcpyAsync(d_at, chunk_row.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_gather_i32, dim3(nblk(nc, kB)), dim3(kB), 0, st, first, d_at, nc, d_r);
-    HIPX(hipGetLastError());
-    HIPX(hipMemcpyAsync(chunk_first.data(), d_r, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(chunk_first.data(), d_f, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
   }
   std::vector<size_t> ord(chunk_wl.size());
@@ -1710,8 +1802,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   clk.mark("a6 split rows");
   // offsets (per tile in parallel from the tile prefix sums); chunk slots after
   const int64_t doff = tdoff[ntiles], roff = troff[ntiles];
-  std::vector<Wl> dwl(nwl);
-  std::vector<PackWl> pwl(nwl);
+  Staged<Wl> dwl(nwl, st);
+  Staged<PackWl> pwl(nwl, st);
   parallel_for(ntiles, 64, [&](int64_t t) {
     int64_t d = tdoff[t], r = troff[t];
     for (int64_t j = h->tile_wl_begin[t]; j < h->tile_wl_begin[t + 1]; ++j) {
@@ -1733,7 +1825,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->n_rowid = roff;
   if (doff >= ((int64_t)1 << 40)) throw Fail{TC_EUNSUPPORTED, "padded format too large"};
   clk.mark("a6 descriptors");
-  check_descriptors(dwl, wls, h->tile_row_off, h->n_slots, doff, roff);
+  check_descriptors(dwl.p, wls, h->tile_row_off, h->n_slots, doff, roff);
 
   clk.mark("a6 partition");
   // ---- a7: pack
@@ -1743,8 +1835,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->d_wl = hold<Wl>(h, nwl);
   if (nwl > 0) {
     PackWl* d_pwl = tmp.get<PackWl>(nwl);
-    HIPX(hipMemcpyAsync(d_pwl, pwl.data(), sizeof(PackWl) * nwl, hipMemcpyHostToDevice, st));
-    HIPX(hipMemcpyAsync(h->d_wl, dwl.data(), sizeof(Wl) * nwl, hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(d_pwl, pwl.p, sizeof(PackWl) * nwl, hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(h->d_wl, dwl.p, sizeof(Wl) * nwl, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_pack, dim3(nblk(nwl * kPackSlices, kB / kWave)), dim3(kB), 0, st, d_pwl, nwl, srt_start, rows_len,
                        rows_sorted, b_icol, b_val, (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid,
                        o->value_map ? pad_minus_one() : 0.0f);

@@ -98,6 +98,42 @@ void pool_free(void* p, hipStream_t st, bool idle);       // idle: no queued wor
 size_t pool_release_cached();
 size_t pool_cached_bytes();
 
+// host blocks kept for reuse (tc_mem.cpp): page-locked ones for the build's
+// transfers, plain ones for a handle's host arrays.  A reused block is already
+// mapped, so a build does not fault in fresh pages every time.
+struct HostBlock {
+  void* p = nullptr;
+  size_t cap = 0;
+  bool pinned = false;
+};
+HostBlock host_take(size_t bytes, bool pinned);  // throws std::bad_alloc when out of memory
+void host_give(const HostBlock& b);
+size_t host_release_cached();
+
+// n items of a plain type in a reusable host block (contents uninitialised)
+template <class T>
+struct HostArray {
+  HostBlock b;
+  int64_t n = 0;
+  HostArray() = default;
+  HostArray(const HostArray&) = delete;
+  HostArray& operator=(const HostArray&) = delete;
+  ~HostArray() { release(); }
+  void reset(int64_t count) {
+    release();
+    b = host_take(sizeof(T) * (size_t)(count > 0 ? count : 1), false);
+    n = count;
+  }
+  void release() {
+    if (b.p) host_give(b);
+    b = HostBlock{};
+    n = 0;
+  }
+  T* data() const { return (T*)b.p; }
+  size_t size() const { return (size_t)n; }
+  T& operator[](int64_t i) const { return data()[i]; }
+};
+
 }  // namespace tc
 
 // The handle: every device buffer of one built matrix.
@@ -115,7 +151,7 @@ struct tc_handle {
   // host copies of small metadata
   std::vector<int64_t> tile_col_begin, tile_col_end, tile_nnz, tile_wl, tile_split, tile_row_off;
   std::vector<int64_t> tile_wl_begin;  // workloads of tile t: [tile_wl_begin[t], tile_wl_begin[t+1])
-  std::vector<tc::HostWl> wls;
+  tc::HostArray<tc::HostWl> wls;   // every workload, in descriptor order
 
   // device buffers (owned)
   int32_t* d_cperm = nullptr;       // internal column -> original column

@@ -13,9 +13,14 @@
 //
 // A failed hipMalloc first returns every cached block of the device to HIP and
 // tries again.  TC_POOL=0 in the environment turns caching off.
+//
+// Host blocks (the build's page-locked transfer buffers, a handle's workload
+// list) are kept the same way, so repeated builds neither page-lock nor fault
+// in fresh host memory.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <new>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -161,6 +166,86 @@ size_t pool_cached_bytes() {
   Pool& P = pool();
   std::lock_guard<std::mutex> lk(P.mu);
   return P.cached_bytes;
+}
+
+namespace {
+bool pool_enabled() {
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (P.enabled < 0) {
+    const char* e = std::getenv("TC_POOL");
+    P.enabled = (e && e[0] == '0') ? 0 : 1;
+  }
+  return P.enabled != 0;
+}
+
+struct HostPoolState {
+  std::mutex mu;
+  std::vector<HostBlock> free_blocks;
+};
+HostPoolState& host_pool() {
+  static HostPoolState* p = new HostPoolState();  // never destroyed, like the device pool
+  return *p;
+}
+void host_free_block(const HostBlock& b) {
+  if (b.pinned)
+    (void)hipHostFree(b.p);
+  else
+    std::free(b.p);
+}
+}  // namespace
+
+HostBlock host_take(size_t bytes, bool pinned) {
+  HostPoolState& P = host_pool();
+  if (pool_enabled()) {
+    std::lock_guard<std::mutex> lk(P.mu);
+    size_t best = P.free_blocks.size();
+    for (size_t i = 0; i < P.free_blocks.size(); ++i) {
+      const HostBlock& c = P.free_blocks[i];
+      // best fit, but not a block much larger than the request
+      if (c.pinned == pinned && c.cap >= bytes && c.cap <= bytes + bytes / 4 + ((size_t)2 << 20) &&
+          (best == P.free_blocks.size() || c.cap < P.free_blocks[best].cap))
+        best = i;
+    }
+    if (best < P.free_blocks.size()) {
+      const HostBlock b = P.free_blocks[best];
+      P.free_blocks.erase(P.free_blocks.begin() + (std::ptrdiff_t)best);
+      return b;
+    }
+  }
+  HostBlock b;
+  b.cap = round_size(bytes);
+  if (pinned && hipHostMalloc(&b.p, b.cap, hipHostMallocDefault) == hipSuccess) {
+    b.pinned = true;
+    return b;
+  }
+  if (pinned) (void)hipGetLastError();  // pageable memory stands in
+  b.p = std::malloc(b.cap);
+  if (!b.p) throw std::bad_alloc();
+  return b;
+}
+
+void host_give(const HostBlock& b) {
+  if (!b.p) return;
+  if (!pool_enabled()) {
+    host_free_block(b);
+    return;
+  }
+  HostPoolState& P = host_pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.free_blocks.push_back(b);
+}
+
+size_t host_release_cached() {
+  HostPoolState& P = host_pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  size_t freed = 0;
+  for (const HostBlock& b : P.free_blocks) {
+    freed += b.cap;
+    host_free_block(b);
+  }
+  P.free_blocks.clear();
+  return freed;
 }
 
 }  // namespace tc
