@@ -456,6 +456,33 @@ def test_rwr_multi_tolerance_and_empty(one_tile, every):
         rwr_multi(mats[:2], [seeds[0], -1], 0.85, 0.0, 5, 1)
 
 
+def test_rwr_multi_with_a_graph_larger_than_lds():
+    # every graph one tile (the fused restart), one of them with more columns
+    # than an LDS holds and one with split rows: the same bits as the
+    # single-graph driver, within the FP32 bound of the oracle
+    from paper_1103_2405_amd import rwr_multi
+    mats, csrs, seeds = [], [], []
+    for gi, (sc, ef) in enumerate([(16, 8), (9, 6), (12, 20), (10, 3)]):
+        g = gg.rmat(sc, ef, seed=900 + gi)
+        csr = gg.rwr_matrix(g)
+        mats.append(TiledMatrix(csr, split_len=64 if gi == 2 else -1))
+        csrs.append(csr)
+        seeds.append(int(gg.rwr_seeds(g, 1, 950 + gi)[0]))
+    assert mats[0].info()["n_tiles"] == 1 and csrs[0][1] > 40960
+    for graph in (False, True):
+        out, it, _ = rwr_multi(mats, seeds, 0.85, 0.0, 20, 5, graph=graph)
+        assert it == 20
+        for m, csr, s, r in zip(mats, csrs, seeds, out):
+            one, _, _ = m.rwr([s], 0.85, 0.0, 20)
+            assert torch.equal(one[:, 0], r)
+            ref, _, _ = oracle.rwr(csr, [s], 0.85, 0.0, 20)
+            d = np.abs(r.cpu().numpy() - ref[:, 0]).sum()
+            say("lds multi rwr n", csr[0], "L1 diff", d)
+            assert d <= 1e-5
+    for m in mats:
+        m.close()
+
+
 @pytest.mark.parametrize("W,split", [(0, -1), (0, 64), (1024, 64)])
 def test_refresh_values_equals_fresh_build(W, split):
     # a handle built with the value map and then given new values holds
