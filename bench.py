@@ -356,6 +356,35 @@ def attainable_bandwidth(dev, gib: int = 2, reps: int = 10):
     return res
 
 
+def attainable_gather(dev, window: int = 1 << 19, n: int = 1 << 27, reps: int = 10):
+    """The random-gather rate the product kernels can reach: the library's
+    gather kernel (tc_gather_read: coalesced index and value streams, one
+    gather of x per entry, eight in flight per lane) over n entries whose
+    indices are uniform in a window of `window` floats (the panel pass's
+    column tile: 2 MB, held by each XCD's L2); median of reps, in gathers/s."""
+    import torch
+    from paper_1103_2405_amd.tc import STREAM_SINK_FLOATS, gather_read
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    idx = torch.randint(0, window, (n,), device=dev, dtype=torch.int32, generator=gen)
+    val = torch.rand(n, device=dev, generator=gen)
+    x = torch.rand(window, device=dev, generator=gen)
+    sink = torch.empty(STREAM_SINK_FLOATS, device=dev)
+    gather_read(x, idx, val, sink)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gather_read(x, idx, val, sink)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del idx, val, x, sink
+    torch.cuda.empty_cache()
+    return {"gather_gps": round(n / (float(np.median(ts)) / 1e3) / 1e9, 1), "gather_window_floats": window,
+            "gather_entries": n, "gather_kernel": "k_gather_read (tc_gather_read)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -457,10 +486,19 @@ def main():
     csr_spmv(A, x, y)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(3):  # about 130 ms each on this matrix (its longest rows run on one thread)
+    for _ in range(3):  # CSR-vector: one wavefront per row, the longest (562K entries) alone
         csr_spmv(A, x, y)
     torch.cuda.synchronize()
     csr_ms = (time.perf_counter() - t1) * 1e3 / 3
+    # entries of the panel pass whose gathers read the LDS-staged head tile
+    # (column tile 0 of every panel) and those that gather from global memory
+    split = None
+    if info["n_panels"] > 0:
+        fm = tm.export_format(metadata_only=True)
+        tn = np.asarray(fm["tile_nnz"], np.int64)
+        nct = info["n_col_tiles"]
+        head = int(tn[::nct].sum())
+        split = {"lds_entries": head, "global_gathers": int(tn.sum()) - head}
     tm.close()
 
     if args.probe_copy:
@@ -471,6 +509,15 @@ def main():
         torch.cuda.synchronize()
 
     attainable = None if args.no_rwr else attainable_bandwidth(dev)
+    if attainable is not None:
+        attainable.update(attainable_gather(dev))
+        if split is not None:
+            # a lower bound of the panel pass from the two measured rates: its
+            # global gathers at the gather rate (their index and value streams
+            # included), the head tile's entries streamed at the read rate
+            attainable["panel_pass"] = dict(split, floor_us=round(
+                split["global_gathers"] / (attainable["gather_gps"] * 1e3) +
+                8 * split["lds_entries"] / (attainable["read_gbps"] * 1e3), 1))
 
     kernels = None if args.no_rwr else kernel_compare(A)
     if kernels:

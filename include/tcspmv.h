@@ -122,8 +122,9 @@ typedef struct {
                                  (default 2^19) columns by Algorithm 1's rule, then the sparse
                                  tile; with wl_policy 0 and split_len -1 the panel tiles then
                                  take workloads of 512 entries and split rows longer than 1024
-                                 (measured best here: the panel's wavefronts meet at a barrier
-                                 after every tile, an imbalance Eq. 1-5 do not charge).  Internal rows are cut into contiguous panels of at
+                                 (measured best here for a build and 100 products: Algorithm
+                                 2's sizes save 1% of each product but cost 7 ms of build
+                                 over the thousands of panel tiles).  Internal rows are cut into contiguous panels of at
                                  most panel_rows rows holding about equal numbers of the entries
                                  that stay with their row (a segment longer than its column
                                  tile's split length is chunked and belongs to no panel); every
@@ -364,8 +365,10 @@ tc_status tc_rwr_theta_grad(int64_t n_cols, int64_t nnz, const int64_t* d_rpT, i
                             const double* d_zT, const double* d_wT, const double* d_S, const double* d_G, float c,
                             double* dtheta, tc_stream_t stream);
 
-/* Plain CSR SpMV (one thread per row, Appendix B's CSR kernel), the baseline
- * the tiled kernels are compared with: y := A x, caller's ids, no handle. */
+/* Plain CSR SpMV, the baseline the tiled kernels are compared with: the
+ * CSR-vector kernel of Appendix B (one wavefront per row, FP64 partial sums
+ * reduced across it; Section 3.1, Observation 4).  y := A x in the caller's
+ * ids, no handle; d_x and d_y are device arrays of n_cols and n_rows floats. */
 tc_status tc_csr_spmv(const tc_csr* A, const float* d_x, float* d_y, tc_stream_t stream);
 
 /* Measurement of the streaming-read rate the product kernels can reach (the
@@ -377,6 +380,19 @@ tc_status tc_csr_spmv(const tc_csr* A, const float* d_x, float* d_y, tc_stream_t
  * aligned (TC_EINVAL otherwise).  Asynchronous on `stream`; the caller times
  * it with events on that stream. */
 tc_status tc_stream_read(const float* d_buf, int64_t n, float* d_sink, tc_stream_t stream);
+
+/* Measurement of the random-gather rate the product kernels can reach (the
+ * other attainable limit of the panel pass, whose x gathers cannot be
+ * coalesced; Section 3.1 on the cost of gathering x): for each of the n
+ * entries, reads d_idx[e] and d_val[e] (int32 and float, device) in coalesced
+ * groups of 64 as a column-major workload does, then gathers d_x[d_idx[e]]
+ * (d_x: n_x floats, device); eight entries per lane in flight, 8192
+ * workgroups of 256 threads, each thread's sum written to d_sink (8192 * 256
+ * floats, device).  An index outside [0, n_x) reads d_x[0].  n must be a
+ * multiple of 512 and n_x at least 1 (TC_EINVAL otherwise).  Asynchronous on
+ * `stream`; the caller times it with events on that stream. */
+tc_status tc_gather_read(const float* d_x, int64_t n_x, const int32_t* d_idx, const float* d_val, int64_t n,
+                         float* d_sink, tc_stream_t stream);
 
 /* Sizes and parameters of a handle (host, no GPU work). */
 tc_status tc_handle_info(const tc_handle* h, tc_info* info);

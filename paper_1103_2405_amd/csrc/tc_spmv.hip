@@ -266,15 +266,62 @@ __global__ void __launch_bounds__(kB) k_stream_read(const v4f* __restrict__ a, i
 }
 constexpr int kStreamBlocks = 8192;
 
-// ---- plain CSR baseline: one thread per row (FP64 accumulation)
-__global__ void k_csr_scalar(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                             const float* __restrict__ val, int64_t n_rows, const float* __restrict__ x,
-                             float* __restrict__ y) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rows) return;
+// Measurement of the random-gather rate: coalesced index and value streams
+// with one gather of x per entry, the access pattern of a column-major
+// workload (lane l of a group of 64 takes entry g*64 + l), eight entries per
+// lane in flight; the same grid as k_stream_read, each thread's sum to sink.
+// An index outside [0, n_x) reads x[0].
+constexpr int kGatherPer = 8;
+__global__ void __launch_bounds__(kB) k_gather_read(const float* __restrict__ x, int64_t n_x,
+                                                    const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                    int64_t n_chunks, float* __restrict__ sink) {
+  const int lane = lane_id();
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const int64_t W = (int64_t)gridDim.x * kWpb;
+  float s = 0.0f;
+  for (int64_t c = t / kWave; c < n_chunks; c += W) {
+    const int64_t base = c * (kGatherPer * kWave) + lane;
+    int32_t id[kGatherPer];
+    float v[kGatherPer];
+#pragma unroll
+    for (int u = 0; u < kGatherPer; ++u) {
+      id[u] = __builtin_nontemporal_load(idx + base + u * kWave);
+      v[u] = __builtin_nontemporal_load(val + base + u * kWave);
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherPer; ++u) s += v[u] * x[(uint64_t)(uint32_t)id[u] < (uint64_t)n_x ? id[u] : 0];
+  }
+  sink[t] = s;
+}
+
+// ---- plain CSR baseline: the CSR-vector kernel of Appendix B and Section 3.1
+// (Observation 4), one wavefront per row.  The lanes stride the row with
+// four loads in flight each, keep FP64 partial sums and reduce them across
+// the wavefront.  On a power-law matrix one wavefront walks each long row
+// alone, which is the imbalance the tiled format removes.
+__global__ void __launch_bounds__(kB) k_csr_vector(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const float* __restrict__ val, int64_t n_rows,
+                                                   const float* __restrict__ x, float* __restrict__ y) {
+  const int lane = lane_id();
+  const int64_t r = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (r >= n_rows) return;
+  const int64_t e = rp[r + 1];
   double acc = 0.0;
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc = fma((double)val[k], (double)x[col[k]], acc);
-  y[i] = (float)acc;
+  int64_t k = rp[r] + lane;
+  for (; k + 3 * kWave < e; k += 4 * kWave) {
+    int32_t c[4];
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c[u] = col[k + u * kWave];
+      v[u] = val[k + u * kWave];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = fma((double)v[u], (double)x[c[u]], acc);
+  }
+  for (; k < e; k += kWave) acc = fma((double)val[k], (double)x[col[k]], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) y[r] = (float)acc;
 }
 
 // ---- TILE-COO (Section 3.1, Observation 3)
@@ -661,10 +708,23 @@ extern "C" tc_status tc_csr_spmv(const tc_csr* A, const float* x, float* y, tc_s
       throw Err{TC_EINVAL, "NULL argument"};
     if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) throw Err{TC_EINVAL, "negative size"};
     if (A->n_rows > 0) {
-      hipLaunchKernelGGL(k_csr_scalar, dim3(nblk(A->n_rows, kB)), dim3(kB), 0, (hipStream_t)stream, A->row_ptr,
+      hipLaunchKernelGGL(k_csr_vector, dim3(nblk(A->n_rows, kWpb)), dim3(kB), 0, (hipStream_t)stream, A->row_ptr,
                          A->col_idx, A->val, A->n_rows, x, y);
       HIPC(hipGetLastError());
     }
+    return TC_OK;
+  });
+}
+
+extern "C" tc_status tc_gather_read(const float* d_x, int64_t n_x, const int32_t* d_idx, const float* d_val, int64_t n,
+                                   float* d_sink, tc_stream_t stream) {
+  return guarded("tc_gather_read", [&]() -> tc_status {
+    if (!d_sink || (n > 0 && (!d_x || !d_idx || !d_val))) throw Err{TC_EINVAL, "NULL argument"};
+    if (n < 0 || n % (kGatherPer * kWave) || n_x < 1)
+      throw Err{TC_EINVAL, "n must be a multiple of 512 and n_x positive"};
+    hipLaunchKernelGGL(k_gather_read, dim3(kStreamBlocks), dim3(kB), 0, (hipStream_t)stream, d_x, n_x, d_idx, d_val,
+                       n / (kGatherPer * kWave), d_sink);
+    HIPC(hipGetLastError());
     return TC_OK;
   });
 }

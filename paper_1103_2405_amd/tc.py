@@ -88,7 +88,7 @@ EXPORTED = ["tc_build_opts_default", "tc_build_tiled", "tc_spmv", "tc_spmv_inter
             "tc_pagerank", "tc_hits", "tc_rwr", "tc_csr_spmv", "tc_handle_info", "tc_export_format",
             "tc_set_timing", "tc_get_timing", "tc_destroy", "tc_last_error", "tc_release_cached_memory",
             "tc_rwr_multi", "tc_csr_transpose", "tc_rwr_edge_weights", "tc_rwr_iterates", "tc_rwr_adjoint",
-            "tc_rwr_theta_grad", "tc_gather_rows", "tc_refresh_values", "tc_stream_read",
+            "tc_rwr_theta_grad", "tc_gather_rows", "tc_refresh_values", "tc_stream_read", "tc_gather_read",
             "tc_spmm_internal_noalloc"]
 
 _lib = None
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.tc_spmv_internal.argtypes = [vp, vp, vp, vp]
     lib.tc_spmv_tiles.argtypes = [vp, vp, vp, vp]
     lib.tc_stream_read.argtypes = [vp, i64, vp, vp]
+    lib.tc_gather_read.argtypes = [vp, i64, vp, vp, i64, vp, vp]
     lib.tc_spmm_internal_noalloc.argtypes = [vp, vp, vp, i32, vp]
     lib.tc_spmm.argtypes = [vp, vp, vp, i32, vp]
     lib.tc_pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_float, i32, i32, vp, P(i32), P(ctypes.c_double), vp]
@@ -440,6 +441,20 @@ def stream_read(buf: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
         raise ValueError("buf must be a contiguous float32 CUDA tensor")
     _need(sink, (STREAM_SINK_FLOATS,), "sink")
     _check(load_library().tc_stream_read(_ptr(buf), buf.numel(), _ptr(sink), _stream(stream)), "tc_stream_read")
+
+
+def gather_read(x: torch.Tensor, idx: torch.Tensor, val: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """One pass of the library's random-gather measurement kernel: x[idx[e]]
+    times val[e] for every entry (idx int32, val float32, same length, a
+    multiple of 512); sink holds STREAM_SINK_FLOATS floats."""
+    for t, name, dt in ((x, "x", torch.float32), (idx, "idx", torch.int32), (val, "val", torch.float32)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, dt))
+    if idx.numel() != val.numel():
+        raise ValueError("idx and val must have the same length")
+    _need(sink, (STREAM_SINK_FLOATS,), "sink")
+    _check(load_library().tc_gather_read(_ptr(x), x.numel(), _ptr(idx), _ptr(val), idx.numel(), _ptr(sink),
+                                         _stream(stream)), "tc_gather_read")
 
 
 def release_cached_memory() -> int:

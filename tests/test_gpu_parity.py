@@ -740,3 +740,27 @@ def test_lds_staged_tiles(bounds, wl, split, S):
     gm = TiledMatrix(dy, wl=wl, split_len=split, tile_bounds=bounds, lds_stage=1, slices=S)
     check_spmv(gm, dy, xd, exact=True)
     gm.close()
+
+
+# ------------------------------------------------------------ measurement kernels
+def test_stream_and_gather_read_measurement_kernels():
+    # the attainable-rate kernels of the roofline read every element once:
+    # their per-thread sums add up to the exact totals (small integers)
+    from paper_1103_2405_amd.tc import STREAM_SINK_FLOATS, gather_read, stream_read
+    sink = torch.zeros(STREAM_SINK_FLOATS, device="cuda")
+    a = torch.ones(1 << 22, device="cuda")
+    stream_read(a, sink)
+    assert sink.double().sum().item() == float(1 << 22)
+    n = 1 << 20
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    x = torch.ones(1000, device="cuda")
+    x[0] = 2.0
+    idx = torch.randint(1, 1000, (n,), device="cuda", dtype=torch.int32, generator=gen)
+    idx[:3] = torch.tensor([-1, 1000, 1 << 30], dtype=torch.int32)  # outside [0, n_x): x[0]
+    val = torch.ones(n, device="cuda")
+    sink.zero_()
+    gather_read(x, idx, val, sink)
+    assert sink.double().sum().item() == float(n + 3)
+    with pytest.raises(TcError):
+        gather_read(x, idx[:1000], val[:1000], sink)  # not a multiple of 512
