@@ -390,6 +390,37 @@ __device__ inline double sum_slots(const double* __restrict__ p, int64_t n, int6
   return acc;
 }
 
+// The same sum as sum_slots (left to right from 0.0, so the same bits) by a
+// whole wavefront: each round the lanes copy 256 slots at once into the
+// wavefront's LDS buffer `buf` (256 doubles), then lane 0 adds them in slot
+// order from LDS.  A row of hundreds of chunks then costs a few global load
+// latencies instead of one per 32 slots.  The sum is valid in lane 0.
+__device__ inline double sum_slots_wave(const double* __restrict__ p, int64_t n, int lane, double* buf) {
+  double acc = 0.0;
+  for (int64_t q = 0; q < n; q += 4 * kWave) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = q + u * kWave + lane;
+      buf[u * kWave + lane] = i < n ? p[i] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int m = (int)(n - q < 4 * kWave ? n - q : 4 * kWave);
+    if (lane == 0) {
+      int k = 0;
+      for (; k + 8 <= m; k += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = buf[k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += t[u];
+      }
+      for (; k < m; ++k) acc += buf[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return acc;
+}
+
 // ---- vector kernels
 __global__ void k_fill_f32(float* __restrict__ a, int64_t n, float v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -128,15 +128,22 @@ __global__ void k_pr_split_empty(const SplitRow* __restrict__ sr, int64_t n_spli
 // Fused PageRank step with row panels, the split rows: their unsplit
 // segments' sum (yraw, from the panel pass) plus their chunks, then the same
 // formula as the panel pass; the rows without entries were written by it.
-__global__ void k_pr_split_panel(const SplitRow* __restrict__ sr, int64_t n_split, const double* __restrict__ partial,
-                                 const float* __restrict__ yraw, float* __restrict__ pn, double c,
-                                 const double* __restrict__ dmass, int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kB) k_pr_split_panel(const SplitRow* __restrict__ sr, int64_t n_split,
+                                                        const double* __restrict__ partial,
+                                                        const float* __restrict__ yraw, float* __restrict__ pn,
+                                                        double c, const double* __restrict__ dmass, int64_t n) {
+  // one wavefront per split row
+  const int lane = lane_id();
+  const int64_t t = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (t >= n_split) return;
-  const double dn = *dmass / (double)n, tele = (1.0 - c) / (double)n;
+  __shared__ double buf[kWpb][4 * kWave];
   const SplitRow s = sr[t];
-  const float yv = (float)((double)yraw[t] + sum_slots(partial + s.slot_begin, s.n_slots));
-  pn[s.row] = (float)(c * ((double)yv + dn) + tele);
+  const double acc = sum_slots_wave(partial + s.slot_begin, s.n_slots, lane, buf[threadIdx.x / kWave]);
+  if (lane == 0) {
+    const double dn = *dmass / (double)n, tele = (1.0 - c) / (double)n;
+    const float yv = (float)((double)yraw[t] + acc);
+    pn[s.row] = (float)(c * ((double)yv + dn) + tele);
+  }
 }
 
 // Fused one-query RWR step, the rows the tile kernel does not write: split
@@ -282,7 +289,7 @@ extern "C" tc_status tc_pagerank(const tc_handle* hc, float c, float tol, int32_
                            (const SplitRow*)h->d_split, h->d_panel_yraw};
           panel_pass(h, pc, pn, st, &pr);
           if (h->n_split_rows > 0) {
-            hipLaunchKernelGGL(k_pr_split_panel, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
+            hipLaunchKernelGGL(k_pr_split_panel, dim3(nblk(h->n_split_rows, kWpb)), dim3(kB), 0, st, h->d_split,
                                h->n_split_rows, (const double*)h->d_partial, (const float*)h->d_panel_yraw, pn,
                                (double)c, (const double*)(res + 1), n);
             HIPC(hipGetLastError());

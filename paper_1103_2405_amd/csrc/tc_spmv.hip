@@ -223,13 +223,17 @@ __global__ void k_combine_priv(float* __restrict__ y, const float* __restrict__ 
 }
 
 // Sum of every split row's chunks in (tile, chunk) order, added to y (or
-// stored when no tile wrote the row).
-__global__ void k_split_combine(const SplitRow* __restrict__ sr, int64_t n, const double* __restrict__ partial,
-                                float* __restrict__ y, int force_add) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// stored when no tile wrote the row); one wavefront per split row.
+__global__ void __launch_bounds__(kB) k_split_combine(const SplitRow* __restrict__ sr, int64_t n,
+                                                      const double* __restrict__ partial, float* __restrict__ y,
+                                                      int force_add) {
+  const int lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * kWpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (i >= n) return;
+  __shared__ double buf[kWpb][4 * kWave];
   const SplitRow s = sr[i];
-  const double acc = sum_slots(partial + s.slot_begin, s.n_slots);
+  const double acc = sum_slots_wave(partial + s.slot_begin, s.n_slots, lane, buf[threadIdx.x / kWave]);
+  if (lane != 0) return;
   if (s.store && !force_add)
     y[s.row] = (float)acc;
   else
@@ -563,7 +567,7 @@ void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool 
   if (h->n_panels > 0 && !tilewise) {
     panel_pass(h, x, y, st, nullptr);
     if (h->n_split_rows > 0) {
-      hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
+      hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kWpb)), dim3(kB), 0, st, h->d_split,
                          h->n_split_rows, h->d_partial, y, 0);
       HIPC(hipGetLastError());
     }
@@ -636,7 +640,7 @@ void spmv_internal(tc_handle* h, const float* x, float* y, hipStream_t st, bool 
     }
   }
   if (h->n_split_rows > 0) {
-    hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kB)), dim3(kB), 0, st, h->d_split,
+    hipLaunchKernelGGL(k_split_combine, dim3(nblk(h->n_split_rows, kWpb)), dim3(kB), 0, st, h->d_split,
                        h->n_split_rows, h->d_partial, y, xcd ? 1 : 0);
     HIPC(hipGetLastError());
   }
