@@ -370,8 +370,17 @@ struct TileMap {
   int32_t W, T;
   const int32_t* starts;  // NULL for fixed width
   int32_t ns;
+  // starts[i] = s0 + i * W for every i (the automatic panels' head tile, then
+  // tiles of W columns): the tile is arithmetic, with a shift when W is a
+  // power of two (wshift >= 0), instead of a search over the starts
+  int32_t uniform = 0, s0 = 0, wshift = -1;
   __device__ int32_t operator()(int32_t icol) const {
     if (!starts) return min(icol / W, T);
+    if (uniform) {
+      if (icol < s0) return 0;
+      const int32_t q = wshift >= 0 ? (icol - s0) >> wshift : (icol - s0) / W;
+      return min(1 + q, ns);
+    }
     int32_t lo = 0, hi = ns;  // number of starts <= icol
     while (lo < hi) {
       const int32_t mid = (lo + hi) >> 1;
@@ -394,32 +403,70 @@ __global__ void k_tile_bounds(const int32_t* __restrict__ b_icol, int64_t nnz, T
   tstart[t] = lo;
 }
 
-// a5: segment heads = first entry of each (tile, row) pair.  The entries are
-// bucketed by tile, so a head is a row change (this pass) or the first entry
-// of a tile (k_tile_heads, run after it).
-__global__ void k_seg_flags(const int32_t* __restrict__ b_row, int64_t nnz, int32_t* __restrict__ flags) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nnz) return;
-  flags[k] = k == 0 || b_row[k] != b_row[k - 1];
+// a5: segment heads, the first entry of each (tile, row) pair.  The entries
+// are bucketed by tile, so a head is the first entry, a row change, or the
+// first entry of a tile (tstart: the ntiles tile starts).  Bit i of the
+// result: entry base + i is a head, for the kScanPer entries of one thread
+// in the scan layout; rows receives their rows.
+__device__ inline uint32_t seg_head_bits(const int32_t* __restrict__ b_row, int64_t nnz,
+                                         const int64_t* __restrict__ tstart, int32_t ntiles, int64_t base,
+                                         int32_t* rows) {
+  int32_t prev = base > 0 && base <= nnz ? b_row[base - 1] : -1;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) rows[i] = b_row[min(base + i, nnz - 1)];
+  int32_t lo = 0, hi = ntiles;  // first tile starting at or after base
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (tstart[mid] < base) lo = mid + 1; else hi = mid;
+  }
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    const int64_t k = base + i;
+    bool h = k == 0 || rows[i] != prev;
+    while (lo < ntiles && tstart[lo] < k) ++lo;
+    if (lo < ntiles && tstart[lo] == k) h = true;
+    if (k < nnz && h) m |= 1u << i;
+    prev = rows[i];
+  }
+  return m;
 }
 
-__global__ void k_tile_heads(const int64_t* __restrict__ tstart, int32_t ntiles, int64_t nnz,
-                             int32_t* __restrict__ flags) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < ntiles && tstart[t] < nnz) flags[tstart[t]] = 1;
+// heads per scan block (block_sums[b]), for the scan of their positions
+__global__ void __launch_bounds__(kScanBlock) k_seghead_count(const int32_t* __restrict__ b_row, int64_t nnz,
+                                                              const int64_t* __restrict__ tstart, int32_t ntiles,
+                                                              int64_t* __restrict__ block_sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  int32_t rows[kScanPer];
+  const uint32_t m = seg_head_bits(b_row, nnz, tstart, ntiles, base, rows);
+  int64_t tot;
+  block_excl_scan<int64_t>((int64_t)__popc(m), &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-__global__ void k_seg_emit(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos,
-                           const int32_t* __restrict__ b_icol, const int32_t* __restrict__ b_row,
-                           const int32_t* __restrict__ rowmap, int64_t nnz, TileMap tm,
-                           int32_t* __restrict__ seg_start, int32_t* __restrict__ seg_row,
-                           int32_t* __restrict__ seg_tile) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nnz || !flags[k]) return;
-  int32_t s = pos[k];
-  seg_start[s] = (int32_t)k;
-  seg_row[s] = rowmap[b_row[k]];
-  seg_tile[s] = tm(b_icol[k]);
+// every head's segment at its position: start entry, internal row, tile
+__global__ void __launch_bounds__(kScanBlock) k_seghead_emit(const int32_t* __restrict__ b_row,
+                                                             const int32_t* __restrict__ b_icol,
+                                                             const int32_t* __restrict__ rowmap, int64_t nnz,
+                                                             const int64_t* __restrict__ tstart, int32_t ntiles,
+                                                             TileMap tm, const int64_t* __restrict__ block_off,
+                                                             int32_t* __restrict__ seg_start,
+                                                             int32_t* __restrict__ seg_row,
+                                                             int32_t* __restrict__ seg_tile) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  int32_t rows[kScanPer];
+  const uint32_t m = seg_head_bits(b_row, nnz, tstart, ntiles, base, rows);
+  int64_t tot;
+  int64_t off = block_excl_scan<int64_t>((int64_t)__popc(m), &tot) + block_off[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (!((m >> i) & 1u)) continue;
+    const int64_t k = base + i;
+    seg_start[off] = (int32_t)k;
+    seg_row[off] = rowmap[rows[i]];
+    seg_tile[off] = tm(b_icol[k]);
+    ++off;
+  }
 }
 
 // a5 with one tile: internal row i is a segment if its original row is non-empty
@@ -1427,6 +1474,13 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     int32_t* d_starts = tmp.get<int32_t>(ntiles - 1);
     HIPX(hipMemcpyAsync(d_starts, starts.data(), sizeof(int32_t) * (ntiles - 1), hipMemcpyHostToDevice, st));
     tmap = TileMap{W, T, d_starts, ntiles - 1};
+    bool uni = W > 0;
+    for (int i = 0; i < ntiles - 1 && uni; ++i) uni = (int64_t)starts[i] == (int64_t)starts[0] + (int64_t)i * W;
+    if (uni) {
+      tmap.uniform = 1;
+      tmap.s0 = starts[0];
+      if ((W & (W - 1)) == 0) tmap.wshift = bits_for((uint64_t)W) - 1;
+    }
   }
 
   clk.mark("a3 tiles");
@@ -1529,24 +1583,27 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       tmp.release(flags);
       tmp.release(pos);
     } else {
-      int32_t* flags = tmp.get<int32_t>(nnz);
-      int32_t* pos = tmp.get<int32_t>(nnz);
-      hipLaunchKernelGGL(k_seg_flags, dim3(nblk(nnz, kB)), dim3(kB), 0, st, b_row, nnz, flags);
-      hipLaunchKernelGGL(k_tile_heads, dim3(nblk(ntiles, kB)), dim3(kB), 0, st, (const int64_t*)d_ts, ntiles, nnz,
-                         flags);
+      // heads counted per scan block, their block offsets scanned, then the
+      // segments written at their positions (no per-entry flag array)
+      const int64_t nb = (nnz + kScanTile - 1) / kScanTile;
+      int64_t* bs = tmp.get<int64_t>(nb + 1);
+      hipLaunchKernelGGL(k_seghead_count, dim3((unsigned)nb), dim3(kScanBlock), 0, st, b_row, nnz,
+                         (const int64_t*)d_ts, ntiles, bs);
       HIPX(hipGetLastError());
-      nseg = excl_scan<int32_t, int32_t>(flags, nnz, pos, tmp, st);
+      hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, st, bs, nb, bs + nb);
+      HIPX(hipGetLastError());
+      HIPX(hipMemcpyAsync(&nseg, bs + nb, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      HIPX(hipStreamSynchronize(st));
       seg_start = tmp.get<int32_t>(nseg);
       seg_row = tmp.get<int32_t>(nseg);
       seg_tile = tmp.get<int32_t>(nseg);
       seg_len = tmp.get<int32_t>(nseg);
-      hipLaunchKernelGGL(k_seg_emit, dim3(nblk(nnz, kB)), dim3(kB), 0, st, flags, pos, b_icol, b_row, rowmap, nnz,
-                         tmap, seg_start, seg_row, seg_tile);
+      hipLaunchKernelGGL(k_seghead_emit, dim3((unsigned)nb), dim3(kScanBlock), 0, st, b_row, b_icol, rowmap, nnz,
+                         (const int64_t*)d_ts, ntiles, tmap, (const int64_t*)bs, seg_start, seg_row, seg_tile);
       HIPX(hipGetLastError());
       hipLaunchKernelGGL(k_seg_len, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_start, nseg, nnz, seg_len);
       HIPX(hipGetLastError());
-      tmp.release(flags);
-      tmp.release(pos);
+      tmp.release(bs);
     }
     clk.mark("a5 segment emission");
     if (h->n_panels > 0) {
