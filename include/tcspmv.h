@@ -115,7 +115,7 @@ typedef struct {
   int32_t panels;             /* row panels (MI355X reading of Section 3.2's row partition, applied
                                  to the workgroups of one GPU): 0 (default) = none; P > 0 = P
                                  panels; -1 = automatic: min(compute units, ceil(n_rows / 2048))
-                                 panels of up to 9/8 of an even share of rows (rounded up to 64)
+                                 panels of up to 17/16 of an even share of rows (rounded up to 64)
                                  unless panel_rows is given, and, unless tile_bounds is given, a
                                  head tile of the columns that fit in the LDS left behind y (a
                                  multiple of 1024, staged in LDS), then tiles of tile_width

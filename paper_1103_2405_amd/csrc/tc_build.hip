@@ -1294,14 +1294,16 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     if (h->n_panels < 0) {
       // automatic: one 16-wavefront workgroup per compute unit (fewer for
       // matrices of under 2048 rows per compute unit), each panel sized for
-      // an eighth more rows than an even share; the LDS left behind y holds
-      // the head tile (a multiple of 1024 columns, at least 1024).  More
-      // panels than compute units only when the rows do not fit.
+      // a sixteenth more rows than an even share (room for the weights to
+      // move the bounds; more slack shrinks the head tile, less unbalances
+      // the panels); the LDS left behind y holds the head tile (a multiple
+      // of 1024 columns, at least 1024).  More panels than compute units
+      // only when the rows do not fit.
       int64_t P = std::max<int64_t>(1, std::min<int64_t>(h->n_cu, (A->n_rows + 2047) / 2048));
-      int64_t R = ((9 * ((A->n_rows + P - 1) / P) + 7) / 8 + 63) / 64 * 64;
+      int64_t R = ((17 * ((A->n_rows + P - 1) / P) + 15) / 16 + 63) / 64 * 64;
       if (R > wg_floats - 1024) {
         R = (wg_floats - 1024) / 64 * 64;
-        P = (9 * A->n_rows / 8 + R - 1) / R;
+        P = (17 * A->n_rows / 16 + R - 1) / R;
       }
       h->n_panels = (int32_t)std::max<int64_t>(1, P);
       if (h->panel_rows == 0) h->panel_rows = (int32_t)std::max<int64_t>(64, R);

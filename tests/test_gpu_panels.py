@@ -156,7 +156,7 @@ def test_panel_automatic_format_and_pagerank(scale):
     say(inf)
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     P = min(n_cu, -(-csr[0] // 2048))
-    R = ((9 * (-(-csr[0] // P)) + 7) // 8 + 63) // 64 * 64
+    R = ((17 * (-(-csr[0] // P)) + 15) // 16 + 63) // 64 * 64
     # P panels are asked for; the row cap can leave rows for further panels
     assert inf["n_panels"] >= P and inf["panel_rows"] == max(64, R) and inf["panel_waves"] == 16
     assert inf["split_len"] == 1024 and set(gm.export_format(metadata_only=True)["tile_wl"]) == {512}
