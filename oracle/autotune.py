@@ -49,6 +49,13 @@ def ceil_to(v: int, s: int) -> int:
     return -(-v // s) * s
 
 
+def rm_pad(w: int, S: int) -> int:
+    """Padded row length of a row-major workload (Solution 3: rows padded to a
+    multiple of the warp size).  With S = 64 rows of at most 32 entries pad to
+    32, the paper's own warp size."""
+    return S // 2 if S >= 64 and 2 * w <= S else ceil_to(w, S)
+
+
 def partition_rows(lengths: Sequence[int], wl: int, S: int, split_len: int) -> List[Tuple]:
     """Greedy packing of a tile's rows (sorted by decreasing length) into
     workloads (Solution 3, Algorithm 3 lines 7-16).
@@ -71,7 +78,7 @@ def partition_rows(lengths: Sequence[int], wl: int, S: int, split_len: int) -> L
             continue
         h = min(max(1, wl // w), R - i)
         if w >= h:
-            out.append((RM, w, ceil_to(w, S), h, i, h, -1, 0))
+            out.append((RM, w, rm_pad(w, S), h, i, h, -1, 0))
             i += h
         else:
             hp = ceil_to(h, S)

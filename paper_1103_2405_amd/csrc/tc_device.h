@@ -79,11 +79,17 @@ __device__ inline double dpp_f64(double v) {
   return __hiloint2double(h2, l2);
 }
 
-// Sum over each DPP row of 16 lanes; the total lands in the row's lane 15.
-__device__ inline double row16_sum(double v) {
+// Sum over each 8-lane half of a DPP row; the totals land in lanes 7 and 15
+// of the row (the first three steps of the row's running sum).
+__device__ inline double row8_sum(double v) {
   v += dpp_f64<0x111>(v);  // row_shr:1
   v += dpp_f64<0x112>(v);  // row_shr:2
   v += dpp_f64<0x114>(v);  // row_shr:4
+  return v;
+}
+// Sum over each DPP row of 16 lanes; the total lands in the row's lane 15.
+__device__ inline double row16_sum(double v) {
+  v = row8_sum(v);
   v += dpp_f64<0x118>(v);  // row_shr:8
   return v;
 }
@@ -109,8 +115,10 @@ __device__ inline double dot4(v4i i, v4f v, const G& xg) {
   return fma((double)v.w, (double)x3, s);
 }
 
-// Row-major rectangle with 64-element-aligned rows (S a multiple of 64):
-// every lane reads 4 consecutive entries (16 bytes) per 256-entry chunk.
+// Row-major rectangle with 64-element-aligned rows (S a multiple of 64), or
+// rows padded to 32: every lane reads 4 consecutive entries (16 bytes) per
+// 256-entry chunk.
+//   w_pad = 32:  a chunk holds 8 rows, 8 lanes each -> sums per half DPP row
 //   w_pad = 64:  a chunk holds 4 rows, 16 lanes each -> sums per DPP row
 //   w_pad = 128: a chunk holds 2 rows, 32 lanes each
 //   otherwise:   one row at a time, chunks of 256 (last one masked)
@@ -122,7 +130,7 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
                                bool chunk, int32_t sl) {
   const int64_t off = d.data_off;
   const int32_t wp = d.w_pad, nr = d.n_rows;
-  if (wp == 64 || wp == 128) {
+  if (wp == 32 || wp == 64 || wp == 128) {
     const int lpr = wp >> 2;             // lanes per row
     const int rpc = kWave / lpr;         // rows per chunk
     const int my = lane / lpr;           // my row inside the chunk
@@ -146,7 +154,10 @@ __device__ inline void rm_wide(const Wl& d, int lane, const int32_t* __restrict_
       }
       if (oka) sa = dot4(ia, va, x);
       if (okb) sb = dot4(ib, vb, x);
-      if (wp == 64) {
+      if (wp == 32) {
+        sa = row8_sum(sa);
+        sb = row8_sum(sb);
+      } else if (wp == 64) {
         sa = row16_sum(sa);
         sb = row16_sum(sb);
       } else {
@@ -359,7 +370,7 @@ __device__ __attribute__((always_inline)) inline void run_workload(const Wl& d, 
       cm_rows<2, 4, S>(d, lane, idx, val, rowid, x, y, sl);
     else
       cm_rows<1, 8, S>(d, lane, idx, val, rowid, x, y, sl);
-  } else if (layout != kCM && aligned && (d.w_pad & 63) == 0) {
+  } else if (layout != kCM && aligned && ((d.w_pad & 63) == 0 || (d.w_pad == 32 && layout == kRM))) {
     rm_wide<S>(d, lane, idx, val, rowid, x, y, partial, layout == kChunk, sl);
   } else {
     generic_wl<S>(d, lane, layout, idx, val, rowid, x, y, partial, sl);

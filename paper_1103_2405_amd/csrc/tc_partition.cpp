@@ -12,6 +12,9 @@
 //    that Algorithm 2's lower bound cannot exceed its upper bound by much);
 //  - h = max(1, floor(WL / w)); a column-major workload pads h to a multiple
 //    of S and then takes that many real rows when they remain;
+//  - a row-major workload pads its rows to a multiple of S, except that with
+//    S = 64 rows of at most 32 entries are padded to 32 (the paper pads to its
+//    warp of 32 threads; a wavefront instruction then covers two such rows);
 //  - the table is a grid over powers of two of the padded (w, h); a shape is
 //    looked up at the nearest power of two of each side in log scale, ties
 //    rounding up, clamped to the grid;
@@ -33,6 +36,11 @@ namespace {
 thread_local std::string g_err;
 
 int64_t ceil_to(int64_t v, int64_t s) { return (v + s - 1) / s * s; }
+
+// Padded length of a row-major workload's rows: a multiple of S, or half of
+// S = 64 for rows of at most 32 entries (the paper's warp of 32; two such rows
+// fill one 64-wide wavefront instruction).
+int64_t rm_pad(int64_t w, int64_t S) { return S >= 64 && 2 * w <= S ? S / 2 : ceil_to(w, S); }
 
 int nearest_log2(int64_t v) {
   if (v < 1) v = 1;
@@ -79,7 +87,7 @@ void walk(const std::vector<LenRun>& runs, int64_t wl, const PartitionParams& p,
     if (R - i <= hmax) {  // last workload of the tile
       const int64_t h = R - i;
       if (w >= h)
-        f(Batch{kRM, w, ceil_to(w, S), h, h, 1, i, h, -1, 0});
+        f(Batch{kRM, w, rm_pad(w, S), h, h, 1, i, h, -1, 0});
       else
         f(Batch{kCM, w, w, ceil_to(h, S), h, 1, i, h, -1, 0});
       i = R;
@@ -89,7 +97,7 @@ void walk(const std::vector<LenRun>& runs, int64_t wl, const PartitionParams& p,
       const int64_t step = hmax;
       // workloads whose first row is in this run and that are not the tile's last
       const int64_t q = std::min((run_end - i + step - 1) / step, (R - i - hmax + step - 1) / step);
-      f(Batch{kRM, w, ceil_to(w, S), hmax, hmax, q, i, step, -1, 0});
+      f(Batch{kRM, w, rm_pad(w, S), hmax, hmax, q, i, step, -1, 0});
       i += q * step;
     } else {
       const int64_t hp = ceil_to(hmax, S);

@@ -37,12 +37,16 @@ def test_partition_split_rows():
 
 
 def test_model_constant_table_is_padded_area():
-    # 640 rows of length 3, S = 64: WL 3..9 gives 64-wide row-major rows
-    # (64 * 640 padded area), WL >= 12 gives column-major blocks of 64 rows
-    # with no padding (3 * 640).
+    # 640 rows of length 3, S = 64: WL 3..9 gives row-major rows padded to
+    # 32 (rows of at most half a wavefront: 32 * 640 padded area); S = 128
+    # pads them to 128; WL >= 12 gives column-major blocks of 64 rows with no
+    # padding (3 * 640).
     L = [3] * 640
     t = const_table(100)
-    assert model_time(L, 3, t, "dense", 10 ** 6, 64, 0) == 64 * 640 / 100
+    assert model_time(L, 3, t, "dense", 10 ** 6, 64, 0) == 32 * 640 / 100
+    assert model_time(L, 3, t, "dense", 10 ** 6, 128, 0) == 64 * 640 / 100
+    # rows of 33 entries are longer than half a wavefront: padded to 64
+    assert model_time([33] * 64, 33, t, "dense", 10 ** 6, 64, 0) == 64 * 64 / 100
     assert model_time(L, 12, t, "dense", 10 ** 6, 64, 0) == 3 * 640 / 100
     # Algorithm 2 picks the first size without padding (ties keep the smaller)
     assert choose_wl(L, 1920, t, "dense", 100, 64, 0) == 12

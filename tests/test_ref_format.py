@@ -91,7 +91,9 @@ def check_invariants(csr, fmt):
     for j in range(len(fmt["wl_tile"])):
         lay, wp, hp = fmt["wl_layout"][j], fmt["wl_w_pad"][j], fmt["wl_h_pad"][j]
         if lay == RM:
-            assert wp % S == 0 and wp >= fmt["wl_w"][j]
+            # a multiple of S, or S / 2 for rows of at most half of S = 64
+            half = S >= 64 and wp == S // 2 and fmt["wl_w"][j] <= S // 2
+            assert (wp % S == 0 or half) and wp >= fmt["wl_w"][j]
         else:
             assert hp % S == 0 and fmt["wl_w"][j] < hp
         if j + 1 < len(fmt["wl_tile"]):
