@@ -66,7 +66,10 @@ typedef struct {
 /* Build options (tc_build_opts_default fills the defaults). */
 typedef struct {
   int32_t tile_width;         /* W, columns per dense tile (Solution 1); 0 = 2^23 (32 MB of x,
-                                 measured best on MI355X for power-law graphs up to 2^23 nodes) */
+                                 measured best on MI355X for power-law graphs up to 2^23 nodes)
+                                 without row panels, and with automatic panels the largest power
+                                 of two of columns whose x fills at most half of one XCD's L2
+                                 (2^19 with MI355X's 4 MB) */
   int32_t n_tiles;            /* -1: Algorithm 1 decides; >= 0: that many dense tiles (clipped) */
   int32_t wl_policy;          /* 0: Algorithm 2 per tile; 1: wl_per_tile; 2: wl_all for every tile */
   int32_t wl_all;             /* workload size for wl_policy 2 */
@@ -119,7 +122,7 @@ typedef struct {
                                  unless panel_rows is given, and, unless tile_bounds is given, a
                                  head tile of the columns that fit in the LDS left behind y (a
                                  multiple of 1024, staged in LDS), then tiles of tile_width
-                                 (default 2^19) columns by Algorithm 1's rule, then the sparse
+                                 (default: half an XCD's L2 of x) columns by Algorithm 1's rule, then the sparse
                                  tile; with wl_policy 0 and split_len -1 the panel tiles then
                                  take workloads of 512 entries and split rows longer than 1024
                                  (measured best here for a build and 100 products: Algorithm

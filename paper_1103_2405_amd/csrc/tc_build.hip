@@ -17,6 +17,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <functional>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -1216,22 +1217,55 @@ struct Staged {
   T& operator[](int64_t i) { return p[i]; }
 };
 
-// compute units and LDS of the current device
-void device_limits(tc_handle* h) {
-  int dev = 0, cus = 0;
-  HIPX(hipGetDevice(&dev));
+// what a build needs to know of a device
+struct DeviceLimits {
+  int32_t n_cu = 0;
+  int64_t lds_cu_bytes = 0, lds_floats = 0, l2_bytes = 0;
+};
+
+// compute units, LDS and L2 of device dev, queried once per process (some
+// attributes take milliseconds to read, and every build needs them)
+DeviceLimits query_limits(int dev) {
+  DeviceLimits L;
+  int cus = 0;
   HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  h->n_cu = cus > 0 ? cus : 256;
+  L.n_cu = cus > 0 ? cus : 256;
   // LDS a workgroup may use (the opt-in limit) and LDS per compute unit
-  int blk = 0, optin = 0, per_cu = 0;
+  int blk = 0, optin = 0, per_cu = 0, l2 = 0;
   if (hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) blk = 65536;
   if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
   if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
     per_cu = 0;
+  if (hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, dev) != hipSuccess) l2 = 0;
   (void)hipGetLastError();
   const int64_t wg = std::max(blk, optin);
-  h->lds_cu_bytes = per_cu > 0 ? per_cu : wg;
-  h->lds_floats = std::min<int64_t>(std::min<int64_t>(wg, h->lds_cu_bytes) / 4, kLdsMaxFloats);
+  L.lds_cu_bytes = per_cu > 0 ? per_cu : wg;
+  L.lds_floats = std::min<int64_t>(std::min<int64_t>(wg, L.lds_cu_bytes) / 4, kLdsMaxFloats);
+  L.l2_bytes = l2 > 0 ? l2 : ((int64_t)4 << 20);
+  return L;
+}
+
+// compute units, LDS and L2 of the current device
+void device_limits(tc_handle* h) {
+  static std::mutex mu;
+  static std::map<int, DeviceLimits> known;
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  DeviceLimits L;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = known.find(dev);
+    if (it != known.end()) L = it->second;
+  }
+  if (L.n_cu == 0) {
+    L = query_limits(dev);
+    std::lock_guard<std::mutex> g(mu);
+    known[dev] = L;
+  }
+  h->n_cu = L.n_cu;
+  h->lds_cu_bytes = L.lds_cu_bytes;
+  h->lds_floats = L.lds_floats;
+  h->l2_bytes = L.l2_bytes;
 }
 
 // Row panels (MI355X reading of the row partition of Section 3.2, with the
@@ -1286,6 +1320,17 @@ std::vector<int64_t> make_panels(int32_t* seg_tile, const int32_t* seg_row, cons
 void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h) {
   PhaseClock clk(st);
   device_limits(h);
+  if (h->W == 0) {
+    // automatic panels: column tiles whose x segment fills at most half of
+    // one XCD's L2 (the rest holds the matrix streams passing through), a
+    // power of two of at least 2^16 columns.  All workgroups sweep the
+    // column tiles in the same order, so the current tile's x is what every
+    // L2 holds (Section 3.1, Solution 1, with the L2 in place of the texture
+    // cache).
+    int64_t w = (int64_t)1 << 16;
+    while (w * 2 * (int64_t)sizeof(float) * 2 <= h->l2_bytes && w < ((int64_t)1 << 30)) w *= 2;
+    h->W = (int32_t)w;
+  }
   int64_t panel_head = 0;  // automatic panels: width of the LDS-staged head tile
   if (h->n_panels != 0) {
     const int64_t wg_floats = h->lds_floats;
@@ -2071,7 +2116,8 @@ extern "C" tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, 
   h->n_rows = A->n_rows;
   h->n_cols = A->n_cols;
   h->nnz = A->nnz;
-  h->W = o->tile_width > 0 ? o->tile_width : (o->panels < 0 ? (1 << 19) : (1 << 23));
+  // with automatic panels an unset width comes from the L2 in build()
+  h->W = o->tile_width > 0 ? o->tile_width : (o->panels < 0 ? 0 : (1 << 23));
   h->S = o->wave > 0 ? o->wave : 64;
   h->split_len = o->split_len < 0 ? -1 : o->split_len;
   // automatic row panels with automatic sizes: workloads of kPanelWl entries

@@ -184,6 +184,7 @@ struct tc_handle {
   int32_t lds_tiles = 1;            // LDS staging of narrow tiles: 0 never, 1 automatic, 2 whenever it fits
   int64_t lds_floats = 0;           // floats of x one workgroup can stage (device limit)
   int64_t lds_cu_bytes = 0;         // LDS bytes per compute unit
+  int64_t l2_bytes = 0;             // L2 bytes of one XCD (the L2 a workgroup's gathers see)
   int32_t* d_half = nullptr;        // HITS: 0/1 half of each internal index (lazily built)
   // row panels: tile g = panel g / n_col_tiles, column tile g % n_col_tiles
   int32_t n_panels = 0, n_col_tiles = 0, panel_rows = 0, panel_waves = 0;

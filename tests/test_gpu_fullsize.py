@@ -109,8 +109,13 @@ def cl23_panels(cl23):
 
 def test_full_size_panels_spmv_all_rows_and_tile_order(cl23, cl23_panels):
     inf = cl23_panels.info()
-    say("panels", inf["n_panels"], "column tiles", inf["n_col_tiles"], "rows", inf["panel_rows"])
+    say("panels", inf["n_panels"], "column tiles", inf["n_col_tiles"], "rows", inf["panel_rows"],
+        "tile width", inf["tile_width"])
     assert inf["n_panels"] > 1 and inf["n_col_tiles"] > 1
+    # column tiles chosen from the device: a power of two of columns whose x
+    # fills at most half an XCD's L2 (MI355X: 4 MB, so 2^19)
+    W = inf["tile_width"]
+    assert W >= 1 << 16 and W & (W - 1) == 0 and 8 * W <= 64 << 20
     n = cl23[0]
     x = gg.uniform_f32(n, 101)
     assert_spmv_all_rows(cl23_panels, cl23, x)
