@@ -251,7 +251,8 @@ def diff_rwr(K: int = 30, every: int = 6, reps: int = 3):
 def rmat20_drivers(tol: float = 1e-6):
     """R-MAT scale 20 (1,048,576 nodes, edge factor 16): one SpMV and PageRank,
     HITS and one-query RWR run to an L1 change of tol (checked every 5
-    iterations), each on its own tiled build."""
+    iterations), each on its own tiled build; SpMV and PageRank also with
+    automatic row panels."""
     import torch
     import graphgen as gg
     from paper_1103_2405_amd import DeviceCsr, TiledMatrix
@@ -277,6 +278,15 @@ def rmat20_drivers(tol: float = 1e-6):
     (p, it, res), ms = timed(lambda: tm.pagerank(0.85, tol, 1000, 5))
     out["pagerank"] = {"iters": it, "resid": res, "ms": round(ms, 2)}
     tm.close()
+    # the same with automatic row panels (the benchmark's format)
+    tp = TiledMatrix(A, panels=-1)
+    _, ms = timed(lambda: [tp.spmv_internal(x, y) for _ in range(20)])
+    inf = tp.info()
+    out["spmv_panels"] = {"us": round(ms * 1e3 / 20, 1), "gbps": round(nbytes / (ms / 20 * 1e6), 1),
+                          "n_panels": inf["n_panels"], "n_col_tiles": inf["n_col_tiles"]}
+    (p, it, res), ms = timed(lambda: tp.pagerank(0.85, tol, 1000, 5))
+    out["pagerank_panels"] = {"iters": it, "resid": res, "ms": round(ms, 2)}
+    tp.close()
     H = TiledMatrix(DeviceCsr(gg.hits_matrix(g)))
     (a, h, it, res), ms = timed(lambda: H.hits(tol, 1000, 5))
     out["hits"] = {"nnz": int(H.nnz), "iters": it, "resid": res, "ms": round(ms, 2)}
