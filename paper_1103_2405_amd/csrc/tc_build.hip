@@ -1780,7 +1780,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   clk.mark("a6 runs");
   if (o->wl_policy == 1 && o->n_wl_per_tile < ntiles)
     throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
-  std::vector<std::vector<HostWl>> twls(ntiles);
+  std::vector<int64_t> tcount(ntiles, 0);  // workloads of each tile
   std::vector<double> tmodel(ntiles, 0.0);
   std::vector<int> tbad(ntiles, 0);
   // per tile: padded elements and stored row ids of its workloads
@@ -1804,32 +1804,41 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       return;
     }
     h->tile_wl[t] = WLt;
-    if (!runs.empty()) tmodel[t] = model_time(runs, WLt, table, sparse_t, pt);
-    partition_tile(runs, WLt, t, trow[t], pt, &twls[t]);
-    int64_t a = 0, r = 0;
-    for (const HostWl& w : twls[t]) {
-      const int64_t area = (int64_t)w.w_pad * w.h_pad;
-      a += area + ((h->camping_pad && area % 512 == 0) ? 64 : 0);
-      r += w.h_pad;
-    }
-    tdoff[t + 1] = a;
-    troff[t + 1] = r;
+    // the model's walk counts the workloads, so each tile's list is written
+    // straight into its place below
+    int64_t cnt = 0;
+    if (!runs.empty()) tmodel[t] = model_time(runs, WLt, table, sparse_t, pt, &cnt);
+    tcount[t] = cnt;
   };
   parallel_for(ntiles, 64, tile_job);
   clk.mark("a6 tile partitions");
-  // workload, element and row-id offsets of every tile, then the tiles'
-  // workloads copied into place in parallel
+  // workload offsets of every tile, then each tile's workloads written in
+  // place in parallel with their padded elements and stored row ids
   for (int t = 0; t < ntiles; ++t) {
     if (tbad[t]) throw Fail{TC_EINVAL, "workload size must be >= 1"};
     h->model_us += tmodel[t];
-    h->tile_wl_begin[t + 1] = h->tile_wl_begin[t] + (int64_t)twls[t].size();
-    tdoff[t + 1] += tdoff[t];
-    troff[t + 1] += troff[t];
+    h->tile_wl_begin[t + 1] = h->tile_wl_begin[t] + tcount[t];
   }
   wls.reset(h->tile_wl_begin[ntiles]);
   parallel_for(ntiles, 64, [&](int64_t t) {
-    std::copy(twls[t].begin(), twls[t].end(), wls.data() + h->tile_wl_begin[t]);
+    if (tcount[t] == 0) return;
+    PartitionParams pt = pp;
+    pt.split_len = (int32_t)h->tile_split[t];
+    HostWl* out = wls.data() + h->tile_wl_begin[t];
+    partition_tile(truns[t], h->tile_wl[t], (int32_t)t, trow[t], pt, out);
+    int64_t a = 0, r = 0;
+    for (int64_t q = 0; q < tcount[t]; ++q) {
+      const int64_t area = (int64_t)out[q].w_pad * out[q].h_pad;
+      a += area + ((h->camping_pad && area % 512 == 0) ? 64 : 0);
+      r += out[q].h_pad;
+    }
+    tdoff[t + 1] = a;
+    troff[t + 1] = r;
   });
+  for (int t = 0; t < ntiles; ++t) {
+    tdoff[t + 1] += tdoff[t];
+    troff[t + 1] += troff[t];
+  }
   clk.mark("a6 sizes and partition");
   h->d_tile_wl_begin = hold<int64_t>(h, ntiles + 1);
   HIPX(hipMemcpyAsync(h->d_tile_wl_begin, h->tile_wl_begin.data(), sizeof(int64_t) * (ntiles + 1),
@@ -1889,9 +1898,21 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipMemcpyAsync(chunk_first.data(), d_f, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
   }
-  std::vector<size_t> ord(chunk_wl.size());
+  // chunks in increasing row, (tile, chunk) order kept within a row: a stable
+  // LSD counting sort over 11-bit digits of the row (rows are int32 >= 0)
+  std::vector<size_t> ord(chunk_wl.size()), ord2(chunk_wl.size());
   std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return chunk_row[a] < chunk_row[b]; });
+  {
+    const int rbits = bits_for((uint64_t)std::max<int64_t>(n_rows - 1, 0));
+    std::vector<size_t> cnt(2049);
+    for (int sh = 0; sh < rbits; sh += 11) {
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (size_t q : ord) ++cnt[(((uint32_t)chunk_row[q] >> sh) & 2047u) + 1];
+      for (size_t b = 1; b < cnt.size(); ++b) cnt[b] += cnt[b - 1];
+      for (size_t q : ord) ord2[cnt[((uint32_t)chunk_row[q] >> sh) & 2047u]++] = q;
+      ord.swap(ord2);
+    }
+  }
   std::vector<int32_t> slot_of(chunk_wl.size());
   std::vector<SplitRow> srows;
   for (size_t q = 0; q < ord.size(); ++q) {

@@ -78,16 +78,18 @@ struct PartitionParams {
 // Algorithm 2 / Algorithm 3 (performance model) for one tile.
 int64_t choose_wl(const std::vector<LenRun>& runs, int64_t tile_nnz, const PerfTable& table,
                   bool sparse_tile, const PartitionParams& p);
+// n_wl (optional): the number of workloads of the partition
 double model_time(const std::vector<LenRun>& runs, int64_t wl, const PerfTable& table,
-                  bool sparse_tile, const PartitionParams& p);
+                  bool sparse_tile, const PartitionParams& p, int64_t* n_wl = nullptr);
 // Split length of one tile: split_len >= 0 is used as given (0 = never
 // split); -1 picks the tile's per-wavefront share of entries, rounded up to a
 // multiple of S and kept within [S, 8192].
 int64_t tile_split_len(int32_t split_len, int64_t tile_nnz, int64_t max_act_warp, int32_t S);
-// Greedy packing of a tile into workloads (Solution 3); appends to `out`.
+// Greedy packing of a tile into workloads (Solution 3), written to out[0, n)
+// where n is the workload count model_time reports for the same arguments.
 // row_base is the index of the tile's first row in the global sorted-row list.
 void partition_tile(const std::vector<LenRun>& runs, int64_t wl, int32_t tile, int64_t row_base,
-                    const PartitionParams& p, std::vector<HostWl>* out);
+                    const PartitionParams& p, HostWl* out);
 
 // thread-local error message
 void set_error(const std::string& msg);

@@ -191,7 +191,7 @@ bool load_perf_table(const char* path, PerfTable* t, std::string* err) {
 }
 
 double model_time(const std::vector<LenRun>& runs, int64_t wl, const PerfTable& table, bool sparse_tile,
-                  const PartitionParams& p) {
+                  const PartitionParams& p, int64_t* n_wl) {
   std::vector<double> P, Size;
   std::vector<int64_t> Cnt;
   int64_t j = 0;  // workload index
@@ -217,6 +217,7 @@ double model_time(const std::vector<LenRun>& runs, int64_t wl, const PerfTable& 
       left -= c;
     }
   });
+  if (n_wl) *n_wl = j;
   double total = 0.0;
   for (size_t i = 0; i < P.size(); ++i) {
     const double mean = P[i] / (double)Cnt[i];
@@ -249,22 +250,22 @@ int64_t choose_wl(const std::vector<LenRun>& runs, int64_t tile_nnz, const PerfT
 }
 
 void partition_tile(const std::vector<LenRun>& runs, int64_t wl, int32_t tile, int64_t row_base,
-                    const PartitionParams& p, std::vector<HostWl>* out) {
+                    const PartitionParams& p, HostWl* out) {
   walk(runs, wl, p, [&](const Batch& b) {
+    HostWl h;
+    h.tile = tile;
+    h.layout = b.layout == kCM ? kCM : kRM;
+    h.w = (int32_t)b.w;
+    h.w_pad = (int32_t)b.w_pad;
+    h.h_pad = (int32_t)b.h_pad;
+    h.n_rows = (int32_t)b.n_rows;
+    h.chunk = b.layout == kChunk ? b.chunk : -1;
+    h.n_chunks = b.layout == kChunk ? b.n_chunks : 0;
+    h.data_off = 0;
+    h.rowid_off = 0;
     for (int64_t q = 0; q < b.count; ++q) {
-      HostWl h;
-      h.tile = tile;
-      h.layout = b.layout == kCM ? kCM : kRM;
-      h.w = (int32_t)b.w;
-      h.w_pad = (int32_t)b.w_pad;
-      h.h_pad = (int32_t)b.h_pad;
       h.row_begin = (int32_t)(row_base + b.row_begin + q * b.step);
-      h.n_rows = (int32_t)b.n_rows;
-      h.chunk = b.layout == kChunk ? b.chunk : -1;
-      h.n_chunks = b.layout == kChunk ? b.n_chunks : 0;
-      h.data_off = 0;
-      h.rowid_off = 0;
-      out->push_back(h);
+      *out++ = h;
     }
   });
 }
