@@ -548,6 +548,13 @@ __global__ void k_run_emit(const int32_t* __restrict__ flags, const int32_t* __r
   }
 }
 
+// (length, rows) of every run: a run ends where the next begins, or at nseg
+__global__ void k_run_pairs(const int64_t* __restrict__ run_pos, const int32_t* __restrict__ run_len, int64_t nruns,
+                            int64_t nseg, LenRun* __restrict__ runs) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nruns) runs[r] = LenRun{run_len[r], (r + 1 < nruns ? run_pos[r + 1] : nseg) - run_pos[r]};
+}
+
 // rows of the split rows' chunks (sorted-row positions at) and each row's first tile
 __global__ void k_chunk_rows(const int32_t* __restrict__ rows_sorted, const int32_t* __restrict__ first,
                              const int32_t* __restrict__ at, int64_t nc, int32_t* __restrict__ row,
@@ -837,9 +844,7 @@ struct TileOp {
 
 // ------------------------------------------------------------ host helpers
 template <typename In, typename Out>
-int64_t excl_scan(const In* in, int64_t n, Out* out, Tmp& tmp, hipStream_t st) {
-  const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
-  int64_t* bs = tmp.get<int64_t>(nb + 1);
+void excl_scan_async(const In* in, int64_t n, Out* out, int64_t* bs, int64_t nb, hipStream_t st) {
   if (n > 0) {
     hipLaunchKernelGGL((k_scan_reduce<In>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, bs);
     HIPX(hipGetLastError());
@@ -852,6 +857,14 @@ int64_t excl_scan(const In* in, int64_t n, Out* out, Tmp& tmp, hipStream_t st) {
     hipLaunchKernelGGL((k_scan_down<In, Out>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, bs, out);
     HIPX(hipGetLastError());
   }
+}
+
+// exclusive scan; returns the total (which waits for the stream)
+template <typename In, typename Out>
+int64_t excl_scan(const In* in, int64_t n, Out* out, Tmp& tmp, hipStream_t st) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+  int64_t* bs = tmp.get<int64_t>(nb + 1);
+  excl_scan_async(in, n, out, bs, nb, st);
   int64_t total = 0;
   HIPX(hipMemcpyAsync(&total, bs + nb, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIPX(hipStreamSynchronize(st));
@@ -859,25 +872,39 @@ int64_t excl_scan(const In* in, int64_t n, Out* out, Tmp& tmp, hipStream_t st) {
   return total;
 }
 
+// One stable counting-sort pass over `nbits` bits of the key (stream
+// ordered, no host wait).  The scatter stages each chunk in LDS, so the
+// chunk is sized to keep one block's staging within 80 KB (two blocks per
+// compute unit).
+constexpr size_t kCsStageBytes = (size_t)80 << 10;
 template <class Op>
 void cs_pass(const Op& op, int64_t n, int nbits, Tmp& tmp, hipStream_t st) {
   if (n <= 0) return;
-  const int nbuckets = 1 << nbits;
-  const int64_t chunk = 4096;
+  using Item = typename Op::Item;
+  const int nbuckets = std::max(kWave, 1 << nbits);  // the staged scatter takes multiples of 64
+  int64_t chunk = 4096;
+  while (chunk > 256 && (size_t)kCsWaves * ((size_t)chunk * sizeof(Item) + 16 * (size_t)nbuckets) > kCsStageBytes)
+    chunk /= 2;
   const int64_t nchunks = (n + chunk - 1) / chunk;
   const unsigned grid = (unsigned)((nchunks + kCsWaves - 1) / kCsWaves);
-  int32_t* hist = tmp.get<int32_t>((int64_t)nbuckets * nchunks);
-  int64_t* offs = tmp.get<int64_t>((int64_t)nbuckets * nchunks);
+  const int64_t nh = (int64_t)nbuckets * nchunks;
+  int32_t* hist = tmp.get<int32_t>(nh);
+  int64_t* offs = tmp.get<int64_t>(nh);
+  const int64_t nsb = std::max<int64_t>(1, (nh + kScanTile - 1) / kScanTile);
+  int64_t* bs = tmp.get<int64_t>(nsb + 1);
   hipLaunchKernelGGL((k_cs_hist<Op>), dim3(grid), dim3(kCsBlock), kCsWaves * nbuckets * sizeof(int32_t), st, op, n,
                      nbuckets, chunk, nchunks, hist);
   HIPX(hipGetLastError());
-  excl_scan<int32_t, int64_t>(hist, (int64_t)nbuckets * nchunks, offs, tmp, st);
-  hipLaunchKernelGGL((k_cs_scatter<Op>), dim3(grid), dim3(kCsBlock), kCsWaves * nbuckets * sizeof(int64_t), st, op,
-                     n, nbuckets, nbits, chunk, nchunks, (const int64_t*)offs);
+  excl_scan_async<int32_t, int64_t>(hist, nh, offs, bs, nsb, st);
+  const size_t stage = (size_t)kCsWaves * ((size_t)chunk * sizeof(Item) + 16 * (size_t)nbuckets);
+  HIPX(hipFuncSetAttribute((const void*)k_cs_scatter_staged<Op>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)stage));
+  hipLaunchKernelGGL((k_cs_scatter_staged<Op>), dim3(grid), dim3(kCsBlock), stage, st, op, n, nbuckets, nbits, chunk,
+                     nchunks, (const int64_t*)offs, (const int32_t*)hist);
   HIPX(hipGetLastError());
-  HIPX(hipStreamSynchronize(st));
   tmp.release(hist);
   tmp.release(offs);
+  tmp.release(bs);
 }
 
 int32_t dev_max(const int32_t* a, int64_t n, Tmp& tmp, hipStream_t st) {
@@ -1608,8 +1635,10 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   int64_t nseg = 0;
   int32_t *rows_sorted = nullptr, *rows_len = nullptr, *srt_start = nullptr;
   std::vector<int64_t> trow(ntiles + 1, 0);
-  std::unique_ptr<Staged<int64_t>> run_pos;  // start and length of every (tile, length) run
-  std::unique_ptr<Staged<int32_t>> run_len;
+  // (length, rows) of every (tile, length) run, tile-major, and each tile's
+  // first run (runs never span tiles: the tile is in the key's top bits)
+  std::unique_ptr<Staged<LenRun>> run_list;
+  std::vector<int64_t> tile_run;
   int64_t nruns = 0;
   if (nnz > 0) {
     int32_t *seg_start, *seg_row, *seg_tile, *seg_len;
@@ -1732,10 +1761,18 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     int32_t* d_rl = tmp.get<int32_t>(nruns);
     hipLaunchKernelGGL(k_run_emit, dim3(nblk(nseg, kB)), dim3(kB), 0, st, rflags, rpos, rows_len, nseg, d_rp, d_rl);
     HIPX(hipGetLastError());
-    run_pos.reset(new Staged<int64_t>(nruns, st));
-    run_len.reset(new Staged<int32_t>(nruns, st));
-    HIPX(hipMemcpyAsync(run_pos->p, d_rp, sizeof(int64_t) * nruns, hipMemcpyDeviceToHost, st));
-    HIPX(hipMemcpyAsync(run_len->p, d_rl, sizeof(int32_t) * nruns, hipMemcpyDeviceToHost, st));
+    LenRun* d_runs = tmp.get<LenRun>(nruns);
+    hipLaunchKernelGGL(k_run_pairs, dim3(nblk(nruns, kB)), dim3(kB), 0, st, (const int64_t*)d_rp,
+                       (const int32_t*)d_rl, nruns, nseg, d_runs);
+    HIPX(hipGetLastError());
+    int64_t* d_trun = tmp.get<int64_t>(ntiles + 1);
+    hipLaunchKernelGGL(k_lower_bound_pre, dim3(nblk(ntiles + 1, kB)), dim3(kB), 0, st, (const int64_t*)d_rp, nruns,
+                       (const int64_t*)d_off, (int)(ntiles + 1), d_trun);
+    HIPX(hipGetLastError());
+    run_list.reset(new Staged<LenRun>(nruns, st));
+    tile_run.assign(ntiles + 1, 0);
+    HIPX(hipMemcpyAsync(run_list->p, d_runs, sizeof(LenRun) * nruns, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(tile_run.data(), d_trun, sizeof(int64_t) * (ntiles + 1), hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
   }
   if (nnz == 0 && h->n_panels > 0) {
@@ -1766,17 +1803,10 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   // tiles are independent, so with many tiles (row panels) they are spread
   // over host threads, each writing its own tiles' workload lists.
   // (every run lies in one tile: the tile is in the key's top bits)
-  std::vector<std::vector<LenRun>> truns(ntiles);
-  if (nruns > 0) {
-    const int64_t* rp = run_pos->p;
-    const int32_t* rl = run_len->p;
-    parallel_for(ntiles, 64, [&](int64_t t) {
-      for (int64_t ri = std::lower_bound(rp, rp + nruns, trow[t]) - rp; ri < nruns && rp[ri] < trow[t + 1]; ++ri) {
-        const int64_t end = ri + 1 < nruns ? std::min(rp[ri + 1], trow[t + 1]) : trow[t + 1];
-        truns[t].push_back(LenRun{rl[ri], end - rp[ri]});
-      }
-    });
-  }
+  std::vector<RunSpan> truns(ntiles);
+  if (nruns > 0)
+    for (int t = 0; t < ntiles; ++t)
+      truns[t] = RunSpan{run_list->p + tile_run[t], (size_t)(tile_run[t + 1] - tile_run[t])};
   clk.mark("a6 runs");
   if (o->wl_policy == 1 && o->n_wl_per_tile < ntiles)
     throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
@@ -1786,7 +1816,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   // per tile: padded elements and stored row ids of its workloads
   std::vector<int64_t> tdoff(ntiles + 1, 0), troff(ntiles + 1, 0);
   auto tile_job = [&](int64_t t) {
-    const std::vector<LenRun>& runs = truns[t];
+    const RunSpan& runs = truns[t];
     PartitionParams pt = pp;
     pt.split_len = (int32_t)h->tile_split[t];
     const bool sparse_t = (h->n_panels > 0 ? t % h->n_col_tiles : t) >= T;

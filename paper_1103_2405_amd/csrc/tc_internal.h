@@ -67,6 +67,16 @@ struct LenRun {
   int64_t len;
   int64_t count;
 };
+// One tile's runs, a view into the build's run list.
+struct RunSpan {
+  const LenRun* p = nullptr;
+  size_t n = 0;
+  const LenRun* begin() const { return p; }
+  const LenRun* end() const { return p + n; }
+  size_t size() const { return n; }
+  bool empty() const { return n == 0; }
+  const LenRun& operator[](size_t i) const { return p[i]; }
+};
 
 struct PartitionParams {
   int32_t S;
@@ -76,10 +86,10 @@ struct PartitionParams {
 };
 
 // Algorithm 2 / Algorithm 3 (performance model) for one tile.
-int64_t choose_wl(const std::vector<LenRun>& runs, int64_t tile_nnz, const PerfTable& table,
+int64_t choose_wl(const RunSpan& runs, int64_t tile_nnz, const PerfTable& table,
                   bool sparse_tile, const PartitionParams& p);
 // n_wl (optional): the number of workloads of the partition
-double model_time(const std::vector<LenRun>& runs, int64_t wl, const PerfTable& table,
+double model_time(const RunSpan& runs, int64_t wl, const PerfTable& table,
                   bool sparse_tile, const PartitionParams& p, int64_t* n_wl = nullptr);
 // Split length of one tile: split_len >= 0 is used as given (0 = never
 // split); -1 picks the tile's per-wavefront share of entries, rounded up to a
@@ -88,7 +98,7 @@ int64_t tile_split_len(int32_t split_len, int64_t tile_nnz, int64_t max_act_warp
 // Greedy packing of a tile into workloads (Solution 3), written to out[0, n)
 // where n is the workload count model_time reports for the same arguments.
 // row_base is the index of the tile's first row in the global sorted-row list.
-void partition_tile(const std::vector<LenRun>& runs, int64_t wl, int32_t tile, int64_t row_base,
+void partition_tile(const RunSpan& runs, int64_t wl, int32_t tile, int64_t row_base,
                     const PartitionParams& p, HostWl* out);
 
 // thread-local error message

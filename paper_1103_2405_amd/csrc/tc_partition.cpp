@@ -64,7 +64,7 @@ struct Batch {
 // Walk the greedy partition in emission order, calling f(batch) for every
 // batch of identical workloads.
 template <class F>
-void walk(const std::vector<LenRun>& runs, int64_t wl, const PartitionParams& p, F&& f) {
+void walk(const RunSpan& runs, int64_t wl, const PartitionParams& p, F&& f) {
   int64_t R = 0;
   for (const auto& r : runs) R += r.count;
   const int64_t S = p.S;
@@ -190,7 +190,7 @@ bool load_perf_table(const char* path, PerfTable* t, std::string* err) {
   return true;
 }
 
-double model_time(const std::vector<LenRun>& runs, int64_t wl, const PerfTable& table, bool sparse_tile,
+double model_time(const RunSpan& runs, int64_t wl, const PerfTable& table, bool sparse_tile,
                   const PartitionParams& p, int64_t* n_wl) {
   std::vector<double> P, Size;
   std::vector<int64_t> Cnt;
@@ -226,7 +226,7 @@ double model_time(const std::vector<LenRun>& runs, int64_t wl, const PerfTable& 
   return total;
 }
 
-int64_t choose_wl(const std::vector<LenRun>& runs, int64_t tile_nnz, const PerfTable& table, bool sparse_tile,
+int64_t choose_wl(const RunSpan& runs, int64_t tile_nnz, const PerfTable& table, bool sparse_tile,
                   const PartitionParams& p) {
   int64_t low = -1;
   for (const auto& r : runs)
@@ -249,7 +249,7 @@ int64_t choose_wl(const std::vector<LenRun>& runs, int64_t tile_nnz, const PerfT
   return best;
 }
 
-void partition_tile(const std::vector<LenRun>& runs, int64_t wl, int32_t tile, int64_t row_base,
+void partition_tile(const RunSpan& runs, int64_t wl, int32_t tile, int64_t row_base,
                     const PartitionParams& p, HostWl* out) {
   walk(runs, wl, p, [&](const Batch& b) {
     HostWl h;

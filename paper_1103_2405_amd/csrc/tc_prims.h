@@ -107,9 +107,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_down(const In* __restrict__
 // Stable counting-sort pass.  The input is cut into chunks of `chunk` items,
 // one wavefront per chunk.  Pass 1 counts each chunk's buckets; an exclusive
 // scan over the bucket-major count matrix gives every (bucket, chunk) its
-// first output slot; pass 2 walks each chunk in order, 64 items at a time, and
-// ranks equal buckets inside the step by lane order (ballots over the bucket's
-// bits), so equal keys keep their input order.
+// first output slot; pass 2 places the items (k_cs_scatter_staged).
 //
 // Op provides:  struct Item;                                   (one element)
 //               __device__ Item load(int64_t k) const;
@@ -131,71 +129,40 @@ __global__ void __launch_bounds__(kCsBlock) k_cs_hist(Op op, int64_t n, int32_t 
   for (int i = lane; i < nbuckets; i += kWave) cnt[i] = 0;
   __syncthreads();
   if (c < nchunks) {
-    const int64_t end = min(n, (c + 1) * chunk);
-    int64_t k = c * chunk + lane;
-    for (; k + 3 * kWave < end; k += 4 * kWave) {  // four loads in flight
-      const uint32_t b0 = op.bucket_of(op.load(k)), b1 = op.bucket_of(op.load(k + kWave)),
-                     b2 = op.bucket_of(op.load(k + 2 * kWave)), b3 = op.bucket_of(op.load(k + 3 * kWave));
-      atomicAdd(&cnt[b0], 1);
-      atomicAdd(&cnt[b1], 1);
-      atomicAdd(&cnt[b2], 1);
-      atomicAdd(&cnt[b3], 1);
+    const int64_t first = c * chunk, end = min(n, (c + 1) * chunk);
+    // four items per lane in flight, the next four loaded before these are
+    // counted (lanes past the end reload the first item and count nothing)
+    uint32_t nb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = first + u * kWave + lane;
+      nb[u] = op.bucket_of(op.load(k < end ? k : first));
     }
-    for (; k < end; k += kWave) atomicAdd(&cnt[op.bucket_of(op.load(k))], 1);
+    for (int64_t base0 = first; base0 < end; base0 += 4 * kWave) {
+      uint32_t b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        b[u] = nb[u];
+        const int64_t k = base0 + (4 + u) * kWave + lane;
+        nb[u] = op.bucket_of(op.load(k < end ? k : first));
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (base0 + u * kWave + lane < end) atomicAdd(&cnt[b[u]], 1);
+    }
   }
   __syncthreads();
   if (c < nchunks)
     for (int i = lane; i < nbuckets; i += kWave) hist[(int64_t)i * nchunks + c] = cnt[i];
 }
 
-template <class Op>
-__global__ void __launch_bounds__(kCsBlock) k_cs_scatter(Op op, int64_t n, int32_t nbuckets, int32_t nbits,
-                                                         int64_t chunk, int64_t nchunks,
-                                                         const int64_t* __restrict__ offs) {
-  extern __shared__ int64_t cs_run[];
-  const int lane = lane_id(), wv = threadIdx.x / kWave;
-  const int64_t c = (int64_t)blockIdx.x * kCsWaves + wv;
-  if (c >= nchunks) return;  // whole wavefront leaves; no block barrier below
-  int64_t* run = cs_run + wv * nbuckets;
-  for (int i = lane; i < nbuckets; i += kWave) run[i] = offs[(int64_t)i * nchunks + c];
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  const int64_t first = c * chunk, end = min(n, (c + 1) * chunk);
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t base0 = first; base0 < end; base0 += 4 * kWave) {
-    typename Op::Item it[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {  // four loads in flight, then the steps in order
-      const int64_t k = base0 + u * kWave + lane;
-      it[u] = op.load(k < end ? k : first);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t k = base0 + u * kWave + lane;
-      const bool valid = k < end;
-      const uint32_t b = op.bucket_of(it[u]);
-      uint64_t peers = __ballot(valid);
-      for (int bit = 0; bit < nbits; ++bit) {
-        const bool set = (b >> bit) & 1u;
-        const uint64_t bal = __ballot(set);
-        peers &= set ? bal : ~bal;
-      }
-      const int64_t pos = valid ? run[b] + (int64_t)__popcll(peers & lt) : 0;
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (valid) op.store(pos, it[u]);
-      if (valid && (peers >> lane) == 1ull) run[b] += (int64_t)__popcll(peers);
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    }
-  }
-}
-
-// The same pass with each chunk staged in LDS: the items are first placed in
-// chunk-local bucket order, then every bucket's run of the chunk goes out with
-// consecutive lanes, so the stores are coalesced instead of touching a line
-// per lane.  Positions (and so the result) are those of k_cs_scatter.  hist
-// holds the (bucket, chunk) counts; nbuckets must be a multiple of 64.
+// Pass 2: each wavefront walks its chunk in order, 64 items at a time, and
+// ranks equal buckets inside the step by lane order (ballots over the
+// bucket's bits), so equal keys keep their input order.  The items are placed
+// in chunk-local bucket order in LDS; then every bucket's run of the chunk
+// goes out with consecutive lanes, so the stores are coalesced and no global
+// store sits between the loads of the walk.  hist holds the (bucket, chunk)
+// counts; nbuckets must be a multiple of 64.
 // Dynamic LDS per block: kCsWaves * (chunk * sizeof(Item) + 16 * nbuckets).
 template <class Op>
 __global__ void __launch_bounds__(kCsBlock) k_cs_scatter_staged(Op op, int64_t n, int32_t nbuckets, int32_t nbits,
@@ -233,12 +200,19 @@ __global__ void __launch_bounds__(kCsBlock) k_cs_scatter_staged(Op op, int64_t n
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const int64_t first = c * chunk, end = min(n, (c + 1) * chunk);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  Item nx[4];  // the next group's items, loaded while this group is placed
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t k = first + u * kWave + lane;
+    nx[u] = op.load(k < end ? k : first);
+  }
   for (int64_t base0 = first; base0 < end; base0 += 4 * kWave) {
     Item it[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t k = base0 + u * kWave + lane;
-      it[u] = op.load(k < end ? k : first);
+      it[u] = nx[u];
+      const int64_t k = base0 + (4 + u) * kWave + lane;
+      nx[u] = op.load(k < end ? k : first);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
