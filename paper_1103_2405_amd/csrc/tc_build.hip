@@ -365,6 +365,35 @@ __global__ void k_icol(const int32_t* __restrict__ col, const int32_t* __restric
   if (k < nnz) icol[k] = cpos[col[k]];
 }
 
+// Entries in internal-row order: output position p lies in internal row
+// irow[p] (expanded from iptr, the scan of the internal rows' lengths); it
+// takes the entry of the same rank in the row's CSR range.  The row keeps
+// its entries in CSR order.  Written: the internal column, the value and
+// the caller's row id.
+__global__ void k_irow_len(const int64_t* __restrict__ rp, const int32_t* __restrict__ rowinv, int64_t n_rows,
+                           int32_t* __restrict__ ilen) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_rows) {
+    const int32_t o = rowinv[r];
+    ilen[r] = (int32_t)(rp[o + 1] - rp[o]);
+  }
+}
+
+__global__ void k_perm_entries(const int32_t* __restrict__ irow, const int64_t* __restrict__ iptr,
+                               const int32_t* __restrict__ rowinv, const int64_t* __restrict__ rp,
+                               const int32_t* __restrict__ col, const int32_t* __restrict__ cpos,
+                               const float* __restrict__ val, int64_t nnz, int32_t* __restrict__ icol,
+                               float* __restrict__ pval, int32_t* __restrict__ prow) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t r = irow[p];
+  const int32_t o = rowinv[r];
+  const int64_t e = rp[o] + (p - iptr[r]);
+  icol[p] = cpos[col[e]];
+  pval[p] = val[e];
+  prow[p] = o;
+}
+
 // Tile of an internal column: fixed-width tiles (icol / W, the columns past
 // the T dense tiles forming tile T) or explicit tile starts (tiles 1..ns).
 struct TileMap {
@@ -1574,26 +1603,61 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     HIPX(hipGetLastError());
     vsrc = (const float*)iota;
   }
+  // With relabelled rows and several tiles (not TILE-COO, whose arrays keep
+  // CSR order within a tile), the entries enter the tile passes in internal-
+  // row order, so each tile's segments come out in increasing internal row
+  // and the segment sort in a5 needs no passes over the row bits.
+  const bool perm_rows = !one_tile && h->relabel && h->kernel != 1;
+  const bool rows_in_order = one_tile || perm_rows || !h->relabel;
   if (nnz > 0) {
     int32_t* icol = tmp.get<int32_t>(nnz);
-    hipLaunchKernelGGL(k_icol, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, cpos, nnz, icol);
-    HIPX(hipGetLastError());
+    int32_t* row_of = nullptr;
+    float* pval = nullptr;
+    if (perm_rows) {
+      int32_t* ilen = tmp.get<int32_t>(n_rows);
+      int64_t* iptr = tmp.get<int64_t>(n_rows + 1);
+      hipLaunchKernelGGL(k_irow_len, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, (const int32_t*)rowinv,
+                         n_rows, ilen);
+      HIPX(hipGetLastError());
+      const int64_t nsb = std::max<int64_t>(1, (n_rows + kScanTile - 1) / kScanTile);
+      int64_t* bs = tmp.get<int64_t>(nsb + 1);
+      excl_scan_async<int32_t, int64_t>(ilen, n_rows, iptr, bs, nsb, st);
+      HIPX(hipMemcpyAsync(iptr + n_rows, bs + nsb, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+      int32_t* irow = tmp.get<int32_t>(nnz);
+      hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, (const int64_t*)iptr, n_rows, irow);
+      HIPX(hipGetLastError());
+      row_of = tmp.get<int32_t>(nnz);
+      pval = tmp.get<float>(nnz);
+      hipLaunchKernelGGL(k_perm_entries, dim3(nblk(nnz, kB)), dim3(kB), 0, st, (const int32_t*)irow,
+                         (const int64_t*)iptr, (const int32_t*)rowinv, A->row_ptr, A->col_idx, cpos, vsrc, nnz, icol,
+                         pval, row_of);
+      HIPX(hipGetLastError());
+      tmp.release(irow);
+      tmp.release(iptr);
+      tmp.release(ilen);
+      tmp.release(bs);
+    } else {
+      hipLaunchKernelGGL(k_icol, dim3(nblk(nnz, kB)), dim3(kB), 0, st, A->col_idx, cpos, nnz, icol);
+      HIPX(hipGetLastError());
+    }
     const int tb = bits_for((uint64_t)(ntiles > 1 ? ntiles - 1 : 0));
     if (one_tile) {
       b_icol = icol;
       b_val = vsrc;
     } else {
-      int32_t* row_of = tmp.get<int32_t>(nnz);
-      hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, row_of);
-      HIPX(hipGetLastError());
+      if (!row_of) {
+        row_of = tmp.get<int32_t>(nnz);
+        hipLaunchKernelGGL(k_expand_rows, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, n_rows, row_of);
+        HIPX(hipGetLastError());
+      }
       // LSD passes over 8-bit digits of the tile id; buffers alternate between
       // two sets (the caller's values are only read)
       int32_t* bi[2] = {tmp.get<int32_t>(nnz), icol};
       int32_t* br[2] = {tmp.get<int32_t>(nnz), row_of};
-      float* bv[2] = {tmp.get<float>(nnz), nullptr};
+      float* bv[2] = {tmp.get<float>(nnz), pval};
       const int32_t* ci = icol;
       const int32_t* cr = row_of;
-      const float* cv = vsrc;
+      const float* cv = pval ? pval : vsrc;
       int p = 0;
       for (int sh = 0; sh < tb; sh += 8, ++p) {
         const int s = p & 1;
@@ -1722,9 +1786,10 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     hipLaunchKernelGGL(k_seg_keys, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, seg_start, nseg,
                        maxlen, lb, rb, k0, v0);
     HIPX(hipGetLastError());
-    // one tile: the segments already come in increasing row (the key's low
-    // rb bits), so the stable passes over the length bits finish the order
-    for (int sh = one_tile ? rb : 0; sh < lb + rb + tb; sh += 8) {
+    // segments already in increasing internal row within each tile (the
+    // key's low rb bits): the stable passes over the length and tile bits
+    // finish the order
+    for (int sh = rows_in_order ? rb : 0; sh < lb + rb + tb; sh += 8) {
       cs_pass(RadixU64Op{k0, v0, k1, v1, sh}, nseg, 8, tmp, st);
       std::swap(k0, k1);
       std::swap(v0, v1);
