@@ -369,29 +369,29 @@ __global__ void k_icol(const int32_t* __restrict__ col, const int32_t* __restric
 // irow[p] (expanded from iptr, the scan of the internal rows' lengths); it
 // takes the entry of the same rank in the row's CSR range.  The row keeps
 // its entries in CSR order.  Written: the internal column, the value and
-// the caller's row id.
+// the internal row.
 __global__ void k_irow_len(const int64_t* __restrict__ rp, const int32_t* __restrict__ rowinv, int64_t n_rows,
-                           int32_t* __restrict__ ilen) {
+                           int32_t* __restrict__ ilen, int64_t* __restrict__ istart) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n_rows) {
     const int32_t o = rowinv[r];
-    ilen[r] = (int32_t)(rp[o + 1] - rp[o]);
+    const int64_t a = rp[o];
+    ilen[r] = (int32_t)(rp[o + 1] - a);
+    istart[r] = a;
   }
 }
 
 __global__ void k_perm_entries(const int32_t* __restrict__ irow, const int64_t* __restrict__ iptr,
-                               const int32_t* __restrict__ rowinv, const int64_t* __restrict__ rp,
-                               const int32_t* __restrict__ col, const int32_t* __restrict__ cpos,
-                               const float* __restrict__ val, int64_t nnz, int32_t* __restrict__ icol,
-                               float* __restrict__ pval, int32_t* __restrict__ prow) {
+                               const int64_t* __restrict__ istart, const int32_t* __restrict__ col,
+                               const int32_t* __restrict__ cpos, const float* __restrict__ val, int64_t nnz,
+                               int32_t* __restrict__ icol, float* __restrict__ pval, int32_t* __restrict__ prow) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nnz) return;
   const int32_t r = irow[p];
-  const int32_t o = rowinv[r];
-  const int64_t e = rp[o] + (p - iptr[r]);
+  const int64_t e = istart[r] + (p - iptr[r]);
   icol[p] = cpos[col[e]];
   pval[p] = val[e];
-  prow[p] = o;
+  prow[p] = r;
 }
 
 // Tile of an internal column: fixed-width tiles (icol / W, the columns past
@@ -442,8 +442,7 @@ __device__ inline uint32_t seg_head_bits(const int32_t* __restrict__ b_row, int6
                                          const int64_t* __restrict__ tstart, int32_t ntiles, int64_t base,
                                          int32_t* rows) {
   int32_t prev = base > 0 && base <= nnz ? b_row[base - 1] : -1;
-#pragma unroll
-  for (int i = 0; i < kScanPer; ++i) rows[i] = b_row[min(base + i, nnz - 1)];
+  load_run(b_row, base, nnz, *reinterpret_cast<int32_t(*)[kScanPer]>(rows));
   int32_t lo = 0, hi = ntiles;  // first tile starting at or after base
   while (lo < hi) {
     const int32_t mid = (lo + hi) >> 1;
@@ -474,7 +473,8 @@ __global__ void __launch_bounds__(kScanBlock) k_seghead_count(const int32_t* __r
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// every head's segment at its position: start entry, internal row, tile
+// every head's segment at its position: start entry, internal row (b_row
+// holds the caller's rows when rowmap is given, else internal rows), tile
 __global__ void __launch_bounds__(kScanBlock) k_seghead_emit(const int32_t* __restrict__ b_row,
                                                              const int32_t* __restrict__ b_icol,
                                                              const int32_t* __restrict__ rowmap, int64_t nnz,
@@ -484,8 +484,9 @@ __global__ void __launch_bounds__(kScanBlock) k_seghead_emit(const int32_t* __re
                                                              int32_t* __restrict__ seg_row,
                                                              int32_t* __restrict__ seg_tile) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-  int32_t rows[kScanPer];
+  int32_t rows[kScanPer], cols[kScanPer];
   const uint32_t m = seg_head_bits(b_row, nnz, tstart, ntiles, base, rows);
+  load_run(b_icol, base, nnz, cols);  // read whole, not under the per-head branch
   int64_t tot;
   int64_t off = block_excl_scan<int64_t>((int64_t)__popc(m), &tot) + block_off[blockIdx.x];
 #pragma unroll
@@ -493,8 +494,8 @@ __global__ void __launch_bounds__(kScanBlock) k_seghead_emit(const int32_t* __re
     if (!((m >> i) & 1u)) continue;
     const int64_t k = base + i;
     seg_start[off] = (int32_t)k;
-    seg_row[off] = rowmap[rows[i]];
-    seg_tile[off] = tm(b_icol[k]);
+    seg_row[off] = rowmap ? rowmap[rows[i]] : rows[i];
+    seg_tile[off] = tm(cols[i]);
     ++off;
   }
 }
@@ -631,18 +632,33 @@ __global__ void k_lower_bound_pre(const int64_t* __restrict__ pre, int64_t n, co
   out[p] = lo;
 }
 
-// tile of a segment with row panels: panel of its row * column tiles + column tile
-__global__ void k_seg_panel(int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_row, int64_t nseg,
-                            const int32_t* __restrict__ pb, int32_t np, int32_t nct) {
+
+// Row panels: the segment's tile becomes panel * nct + column tile (the
+// panel bounds pb staged in LDS when lds_pb), then the row's first-touch
+// tile and touched flag as in k_first_touch (split lengths per column tile).
+__global__ void k_seg_panel_touch(int32_t* __restrict__ seg_tile, const int32_t* __restrict__ seg_row,
+                                  const int32_t* __restrict__ seg_len, int64_t nseg, const int32_t* __restrict__ pb,
+                                  int32_t np, int32_t nct, int lds_pb, const int64_t* __restrict__ split_col,
+                                  int32_t* __restrict__ first, int32_t* __restrict__ touched) {
+  extern __shared__ int32_t spb[];
+  if (lds_pb) {
+    for (int i = threadIdx.x; i <= np; i += blockDim.x) spb[i] = pb[i];
+    __syncthreads();
+  }
+  const int32_t* b = lds_pb ? spb : pb;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nseg) return;
-  const int32_t r = seg_row[s];
+  const int32_t r = seg_row[s], ct = seg_tile[s];
   int32_t lo = 0, hi = np - 1;  // last panel with pb[p] <= r
   while (lo < hi) {
     const int32_t mid = (lo + hi + 1) >> 1;
-    if (pb[mid] <= r) lo = mid; else hi = mid - 1;
+    if (b[mid] <= r) lo = mid; else hi = mid - 1;
   }
-  seg_tile[s] = lo * nct + seg_tile[s];
+  const int32_t t = lo * nct + ct;
+  seg_tile[s] = t;
+  touched[r] = 1;
+  const int64_t sp = split_col[ct];
+  if (!(sp > 0 && (int64_t)seg_len[s] > sp)) atomicMin(&first[r], t);
 }
 
 __global__ void k_tile_entries(const int64_t* __restrict__ pre, const int64_t* __restrict__ off, int32_t ntiles,
@@ -1329,11 +1345,11 @@ void device_limits(tc_handle* h) {
 // segments: each row's weight is its entries in segments that are not split
 // into chunks; panel p ends at the first row where the running weight reaches
 // ceil((p + 1) total / P), holding at least one and at most `rows` rows, and
-// rows left after P panels go into further panels of `rows`.  Segment tiles
-// become panel * n_col_tiles + column tile.  Returns the panel bounds.
-std::vector<int64_t> make_panels(int32_t* seg_tile, const int32_t* seg_row, const int32_t* seg_len, int64_t nseg,
-                                 int64_t n_rows, const int64_t* d_split_col, int32_t P, int64_t rows, int32_t nct,
-                                 Tmp& tmp, hipStream_t st) {
+// rows left after P panels go into further panels of `rows`.  Returns the
+// panel bounds, and in *d_pb_out a device copy (int32).
+std::vector<int64_t> make_panels(const int32_t* seg_tile, const int32_t* seg_row, const int32_t* seg_len,
+                                 int64_t nseg, int64_t n_rows, const int64_t* d_split_col, int32_t P, int64_t rows,
+                                 int32_t nct, Tmp& tmp, hipStream_t st, int32_t** d_pb_out) {
   std::vector<int64_t> pb{0};
   if (n_rows == 0) return pb;
   int32_t* w = tmp.get<int32_t>(n_rows);
@@ -1364,12 +1380,8 @@ std::vector<int64_t> make_panels(int32_t* seg_tile, const int32_t* seg_row, cons
   std::vector<int32_t> pb32(pb.begin(), pb.end());
   int32_t* d_pb = tmp.get<int32_t>(np + 1);
   HIPX(hipMemcpyAsync(d_pb, pb32.data(), sizeof(int32_t) * (np + 1), hipMemcpyHostToDevice, st));
-  if (nseg > 0) {
-    hipLaunchKernelGGL(k_seg_panel, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_row, nseg,
-                       (const int32_t*)d_pb, np, nct);
-    HIPX(hipGetLastError());
-  }
-  HIPX(hipStreamSynchronize(st));
+  HIPX(hipStreamSynchronize(st));  // pb32 goes out of scope
+  *d_pb_out = d_pb;
   return pb;
 }
 
@@ -1616,8 +1628,9 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     if (perm_rows) {
       int32_t* ilen = tmp.get<int32_t>(n_rows);
       int64_t* iptr = tmp.get<int64_t>(n_rows + 1);
+      int64_t* istart = tmp.get<int64_t>(n_rows);
       hipLaunchKernelGGL(k_irow_len, dim3(nblk(n_rows, kB)), dim3(kB), 0, st, A->row_ptr, (const int32_t*)rowinv,
-                         n_rows, ilen);
+                         n_rows, ilen, istart);
       HIPX(hipGetLastError());
       const int64_t nsb = std::max<int64_t>(1, (n_rows + kScanTile - 1) / kScanTile);
       int64_t* bs = tmp.get<int64_t>(nsb + 1);
@@ -1629,9 +1642,10 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       row_of = tmp.get<int32_t>(nnz);
       pval = tmp.get<float>(nnz);
       hipLaunchKernelGGL(k_perm_entries, dim3(nblk(nnz, kB)), dim3(kB), 0, st, (const int32_t*)irow,
-                         (const int64_t*)iptr, (const int32_t*)rowinv, A->row_ptr, A->col_idx, cpos, vsrc, nnz, icol,
-                         pval, row_of);
+                         (const int64_t*)iptr, (const int64_t*)istart, A->col_idx, cpos, vsrc, nnz, icol, pval,
+                         row_of);
       HIPX(hipGetLastError());
+      tmp.release(istart);
       tmp.release(irow);
       tmp.release(iptr);
       tmp.release(ilen);
@@ -1738,7 +1752,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       seg_row = tmp.get<int32_t>(nseg);
       seg_tile = tmp.get<int32_t>(nseg);
       seg_len = tmp.get<int32_t>(nseg);
-      hipLaunchKernelGGL(k_seghead_emit, dim3((unsigned)nb), dim3(kScanBlock), 0, st, b_row, b_icol, rowmap, nnz,
+      hipLaunchKernelGGL(k_seghead_emit, dim3((unsigned)nb), dim3(kScanBlock), 0, st, b_row, b_icol,
+                         perm_rows ? (const int32_t*)nullptr : (const int32_t*)rowmap, nnz,
                          (const int64_t*)d_ts, ntiles, tmap, (const int64_t*)bs, seg_start, seg_row, seg_tile);
       HIPX(hipGetLastError());
       hipLaunchKernelGGL(k_seg_len, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_start, nseg, nnz, seg_len);
@@ -1749,9 +1764,17 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     if (h->n_panels > 0) {
       // row panels: every (panel, column tile) pair becomes a tile, panel-major
       const int32_t nct = ntiles;
+      int32_t* d_pb = nullptr;
       h->panel_begin = make_panels(seg_tile, seg_row, seg_len, nseg, n_rows, d_split_t, h->n_panels,
-                                   h->panel_rows, nct, tmp, st);
+                                   h->panel_rows, nct, tmp, st, &d_pb);
       h->n_panels = (int32_t)h->panel_begin.size() - 1;
+      // segment tiles become (panel, column tile) tiles; first touches with them
+      const int lds_pb = h->n_panels + 1 <= 8192 ? 1 : 0;
+      hipLaunchKernelGGL(k_seg_panel_touch, dim3(nblk(nseg, kB)), dim3(kB),
+                         lds_pb ? sizeof(int32_t) * (size_t)(h->n_panels + 1) : 0, st, seg_tile, seg_row, seg_len,
+                         nseg, (const int32_t*)d_pb, h->n_panels, nct, lds_pb, (const int64_t*)d_split_t, first,
+                         touched);
+      HIPX(hipGetLastError());
       h->n_col_tiles = nct;
       ntiles = h->n_panels * nct;
       h->n_tiles = ntiles;
@@ -1771,9 +1794,11 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       trow.assign(ntiles + 1, 0);
     }
     clk.mark("a5 segments formed");
-    hipLaunchKernelGGL(k_first_touch, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg,
-                       (const int64_t*)d_split_t, first, touched);
-    HIPX(hipGetLastError());
+    if (h->n_panels == 0) {
+      hipLaunchKernelGGL(k_first_touch, dim3(nblk(nseg, kB)), dim3(kB), 0, st, seg_tile, seg_len, seg_row, nseg,
+                         (const int64_t*)d_split_t, first, touched);
+      HIPX(hipGetLastError());
+    }
     const int32_t maxlen = dev_max(seg_len, nseg, tmp, st);
     const int lb = bits_for((uint64_t)maxlen);
     const int rb = bits_for((uint64_t)(n_rows > 1 ? n_rows - 1 : 0));

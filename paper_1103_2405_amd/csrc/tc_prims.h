@@ -15,6 +15,46 @@ constexpr int64_t kScanTile = (int64_t)kScanBlock * kScanPer;
 
 __device__ inline int lane_id() { return (int)__lane_id(); }
 
+// v[i] = a[min(base + i, n - 1)] for the kScanPer items of one thread of the
+// scan layout (n >= 1).  A run that lies inside [0, n) at a 16-byte aligned
+// address is read with 16-byte loads: four lanes' runs then share each
+// cache line request instead of sixteen.
+template <typename T>
+__device__ inline void load_run(const T* __restrict__ a, int64_t base, int64_t n, T (&v)[kScanPer]) {
+  const T* p = a + min(base, n - 1);
+  if ((sizeof(T) == 4 || sizeof(T) == 8) && base + kScanPer <= n && ((uintptr_t)p & 15) == 0) {
+    constexpr int per = 16 / (int)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < kScanPer / per; ++q) {
+      const int4 w = reinterpret_cast<const int4*>(p)[q];
+      __builtin_memcpy(&v[q * per], &w, 16);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) v[i] = a[min(base + i, n - 1)];
+  }
+}
+
+// a[base + i] = v[i] for base + i < n, with 16-byte stores for a whole
+// aligned run
+template <typename T>
+__device__ inline void store_run(T* __restrict__ a, int64_t base, int64_t n, const T (&v)[kScanPer]) {
+  T* p = a + base;
+  if ((sizeof(T) == 4 || sizeof(T) == 8) && base + kScanPer <= n && ((uintptr_t)p & 15) == 0) {
+    constexpr int per = 16 / (int)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < kScanPer / per; ++q) {
+      int4 w;
+      __builtin_memcpy(&w, &v[q * per], 16);
+      reinterpret_cast<int4*>(p)[q] = w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i)
+      if (base + i < n) p[i] = v[i];
+  }
+}
+
 // Inclusive scan across the 64 lanes of a wavefront.
 template <typename T>
 __device__ inline T wave_incl_scan(T v) {
@@ -51,12 +91,11 @@ template <typename In>
 __global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const In* __restrict__ in, int64_t n,
                                                             int64_t* __restrict__ block_sums) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  In v[kScanPer];
+  load_run(in, base, n, v);  // past n: in[n - 1], not added
   int64_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanPer; ++i) {  // all loads issued together (past n: in[n - 1], not added)
-    const In t = in[min(base + i, n - 1)];
-    s += base + i < n ? (int64_t)t : 0;
-  }
+  for (int i = 0; i < kScanPer; ++i) s += base + i < n ? (int64_t)v[i] : 0;
   int64_t tot;
   block_excl_scan<int64_t>(s, &tot);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
@@ -87,20 +126,22 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_down(const In* __restrict__
                                                           Out* __restrict__ out) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
   In v[kScanPer];
+  load_run(in, base, n, v);
   int64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    const In t = in[min(base + i, n - 1)];
-    v[i] = base + i < n ? t : (In)0;
+    if (base + i >= n) v[i] = (In)0;
     s += (int64_t)v[i];
   }
   int64_t tot;
   int64_t off = block_excl_scan<int64_t>(s, &tot) + bs[blockIdx.x];
+  Out o[kScanPer];
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    if (base + i < n) out[base + i] = (Out)off;
+    o[i] = (Out)off;
     off += (int64_t)v[i];
   }
+  store_run(out, base, n, o);
 }
 
 // ---------------------------------------------------------------------------
