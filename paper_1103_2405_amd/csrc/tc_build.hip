@@ -381,17 +381,53 @@ __global__ void k_irow_len(const int64_t* __restrict__ rp, const int32_t* __rest
   }
 }
 
-__global__ void k_perm_entries(const int32_t* __restrict__ irow, const int64_t* __restrict__ iptr,
-                               const int64_t* __restrict__ istart, const int32_t* __restrict__ col,
-                               const int32_t* __restrict__ cpos, const float* __restrict__ val, int64_t nnz,
-                               int32_t* __restrict__ icol, float* __restrict__ pval, int32_t* __restrict__ prow) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nnz) return;
-  const int32_t r = irow[p];
-  const int64_t e = istart[r] + (p - iptr[r]);
-  icol[p] = cpos[col[e]];
-  pval[p] = val[e];
-  prow[p] = r;
+// One block per `chunk` positions (kPermPer per thread, all loads of a step
+// issued together).  With hist, the block also counts its chunk's tiles
+// (bucket (tile >> 0) & 255 of TileMap tm, nbuckets buckets) into
+// hist[bucket * nchunks + chunk]: the first tile pass's histogram.
+constexpr int kPermPer = 4;
+template <class TM>
+__global__ void __launch_bounds__(kB) k_perm_entries(const int32_t* __restrict__ irow, const int64_t* __restrict__ iptr,
+                                                     const int64_t* __restrict__ istart,
+                                                     const int32_t* __restrict__ col, const int32_t* __restrict__ cpos,
+                                                     const float* __restrict__ val, int64_t nnz,
+                                                     int32_t* __restrict__ icol, float* __restrict__ pval,
+                                                     int32_t* __restrict__ prow, TM tm, int32_t nbuckets,
+                                                     int64_t nchunks, int32_t* __restrict__ hist) {
+  extern __shared__ int32_t pcnt[];
+  if (hist) {
+    for (int i = threadIdx.x; i < nbuckets; i += kB) pcnt[i] = 0;
+    __syncthreads();
+  }
+  const int64_t p0 = (int64_t)blockIdx.x * (kB * kPermPer) + threadIdx.x;
+  int32_t r[kPermPer], c[kPermPer];
+  int64_t e[kPermPer];
+  float v[kPermPer];
+#pragma unroll
+  for (int u = 0; u < kPermPer; ++u) r[u] = irow[min(p0 + u * kB, nnz - 1)];
+#pragma unroll
+  for (int u = 0; u < kPermPer; ++u) e[u] = istart[r[u]] + (min(p0 + u * kB, nnz - 1) - iptr[r[u]]);
+#pragma unroll
+  for (int u = 0; u < kPermPer; ++u) {
+    c[u] = col[e[u]];
+    v[u] = val[e[u]];
+  }
+#pragma unroll
+  for (int u = 0; u < kPermPer; ++u) c[u] = cpos[c[u]];
+#pragma unroll
+  for (int u = 0; u < kPermPer; ++u) {
+    const int64_t p = p0 + u * kB;
+    if (p < nnz) {
+      icol[p] = c[u];
+      pval[p] = v[u];
+      prow[p] = r[u];
+      if (hist) atomicAdd(&pcnt[(uint32_t)tm(c[u]) & 255u], 1);
+    }
+  }
+  if (hist) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbuckets; i += kB) hist[(int64_t)i * nchunks + blockIdx.x] = pcnt[i];
+  }
 }
 
 // Tile of an internal column: fixed-width tiles (icol / W, the columns past
@@ -683,15 +719,18 @@ __global__ void k_compact_idx(const int32_t* __restrict__ flags, const int32_t* 
   if (i < n && flags[i]) out[pos[i]] = (int32_t)i;
 }
 
-struct PackWl {
-  int64_t data_off, rowid_off;
-  int32_t w_pad, h_pad, n_rows, layout;
-  int32_t row_begin, chunk_off, chunk_len, tile_first, extra, tile;
+// what the pack needs of a workload beyond its device descriptor
+struct PackX {
+  int32_t row_begin;  // first sorted row (a chunk: its row)
+  int32_t chunk_off;  // a chunk: its first entry within the row, else -1
+  int32_t chunk_len;  // a chunk: its real entries
+  int32_t tile;
 };
 
 // a7: one wavefront per workload writes its rectangle, its pads and row ids.
 constexpr int kPackSlices = 4;
-__global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int64_t n_wl,
+__global__ void __launch_bounds__(kB) k_pack(const Wl* __restrict__ dwl, const PackX* __restrict__ pxs,
+                                             int64_t n_wl, const int32_t* __restrict__ tile_first, int camping,
                                              const int32_t* __restrict__ srt_start,
                                              const int32_t* __restrict__ rows_len,
                                              const int32_t* __restrict__ rows_sorted,
@@ -708,12 +747,28 @@ __global__ void __launch_bounds__(kB) k_pack(const PackWl* __restrict__ wls, int
   if (w >= n_wl * kPackSlices) return;
   const int64_t j = w / kPackSlices;
   const int sl = (int)(w % kPackSlices);
-  const PackWl d = wls[j];
+  const Wl wd = dwl[j];
+  const PackX x = pxs[j];
+  struct {
+    int64_t data_off, rowid_off;
+    int32_t w_pad, h_pad, n_rows, layout, row_begin, tile, tile_first, extra;
+  } d;
+  d.data_off = wd.data_off;
+  d.rowid_off = wd.rowid_off;
+  d.w_pad = wd.w_pad;
+  d.h_pad = wd.h_pad;
+  d.n_rows = wd.n_rows;
+  d.layout = wd.info & 3;
+  d.row_begin = x.row_begin;
+  d.tile = x.tile;
+  d.tile_first = tile_first[x.tile];
+  const int64_t area = (int64_t)wd.w_pad * wd.h_pad;
+  d.extra = (camping && area % 512 == 0) ? 64 : 0;  // the camping pad after the rectangle
   const int64_t off = d.data_off;
-  if (d.chunk_off >= 0) {
+  if (x.chunk_off >= 0) {
     const int32_t s = d.row_begin;
-    const int64_t st = (int64_t)srt_start[s] + d.chunk_off;
-    const int64_t L = d.chunk_len;
+    const int64_t st = (int64_t)srt_start[s] + x.chunk_off;
+    const int64_t L = x.chunk_len;
     const int64_t step = (int64_t)kWave * kPackSlices;
     for (int64_t c0 = lane + (int64_t)sl * kWave; c0 < d.w_pad; c0 += 4 * step) {
       int32_t ti[4];
@@ -922,24 +977,42 @@ int64_t excl_scan(const In* in, int64_t n, Out* out, Tmp& tmp, hipStream_t st) {
 // chunk is sized to keep one block's staging within 80 KB (two blocks per
 // compute unit).
 constexpr size_t kCsStageBytes = (size_t)80 << 10;
+struct CsPlan {
+  int nbuckets;
+  int64_t chunk, nchunks;
+};
+template <class Item>
+CsPlan cs_plan(int64_t n, int nbits) {
+  CsPlan c;
+  c.nbuckets = std::max(kWave, 1 << nbits);  // the staged scatter takes multiples of 64
+  c.chunk = 4096;
+  while (c.chunk > 256 &&
+         (size_t)kCsWaves * ((size_t)c.chunk * sizeof(Item) + 16 * (size_t)c.nbuckets) > kCsStageBytes)
+    c.chunk /= 2;
+  c.nchunks = (n + c.chunk - 1) / c.chunk;
+  return c;
+}
+
+// pre_hist: the pass's (bucket, chunk) counts, already made by the caller
+// with the chunking of cs_plan (owned by the caller)
 template <class Op>
-void cs_pass(const Op& op, int64_t n, int nbits, Tmp& tmp, hipStream_t st) {
+void cs_pass(const Op& op, int64_t n, int nbits, Tmp& tmp, hipStream_t st, int32_t* pre_hist = nullptr) {
   if (n <= 0) return;
   using Item = typename Op::Item;
-  const int nbuckets = std::max(kWave, 1 << nbits);  // the staged scatter takes multiples of 64
-  int64_t chunk = 4096;
-  while (chunk > 256 && (size_t)kCsWaves * ((size_t)chunk * sizeof(Item) + 16 * (size_t)nbuckets) > kCsStageBytes)
-    chunk /= 2;
-  const int64_t nchunks = (n + chunk - 1) / chunk;
+  const CsPlan pl = cs_plan<Item>(n, nbits);
+  const int nbuckets = pl.nbuckets;
+  const int64_t chunk = pl.chunk, nchunks = pl.nchunks;
   const unsigned grid = (unsigned)((nchunks + kCsWaves - 1) / kCsWaves);
   const int64_t nh = (int64_t)nbuckets * nchunks;
-  int32_t* hist = tmp.get<int32_t>(nh);
+  int32_t* hist = pre_hist ? pre_hist : tmp.get<int32_t>(nh);
   int64_t* offs = tmp.get<int64_t>(nh);
   const int64_t nsb = std::max<int64_t>(1, (nh + kScanTile - 1) / kScanTile);
   int64_t* bs = tmp.get<int64_t>(nsb + 1);
-  hipLaunchKernelGGL((k_cs_hist<Op>), dim3(grid), dim3(kCsBlock), kCsWaves * nbuckets * sizeof(int32_t), st, op, n,
-                     nbuckets, chunk, nchunks, hist);
-  HIPX(hipGetLastError());
+  if (!pre_hist) {
+    hipLaunchKernelGGL((k_cs_hist<Op>), dim3(grid), dim3(kCsBlock), kCsWaves * nbuckets * sizeof(int32_t), st, op,
+                       n, nbuckets, chunk, nchunks, hist);
+    HIPX(hipGetLastError());
+  }
   excl_scan_async<int32_t, int64_t>(hist, nh, offs, bs, nsb, st);
   const size_t stage = (size_t)kCsWaves * ((size_t)chunk * sizeof(Item) + 16 * (size_t)nbuckets);
   HIPX(hipFuncSetAttribute((const void*)k_cs_scatter_staged<Op>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -947,7 +1020,7 @@ void cs_pass(const Op& op, int64_t n, int nbits, Tmp& tmp, hipStream_t st) {
   hipLaunchKernelGGL((k_cs_scatter_staged<Op>), dim3(grid), dim3(kCsBlock), stage, st, op, n, nbuckets, nbits, chunk,
                      nchunks, (const int64_t*)offs, (const int32_t*)hist);
   HIPX(hipGetLastError());
-  tmp.release(hist);
+  if (!pre_hist) tmp.release(hist);
   tmp.release(offs);
   tmp.release(bs);
 }
@@ -1173,25 +1246,15 @@ struct PhaseClock {
 // within [0, n_slots), and its rows within its tile's sorted rows.  The
 // offsets come from a running sum, so a violation is a bug in the partition;
 // it is reported instead of handing a kernel an address outside a buffer.
-void check_descriptors(const Wl* dwl, const HostArray<HostWl>& wls,
-                       const std::vector<int64_t>& tile_row_off, int64_t n_slots, int64_t nnz_pad, int64_t n_rowid) {
-  const int64_t ntiles = (int64_t)tile_row_off.size() - 1;
-  for (size_t j = 0; j < wls.size(); ++j) {
-    const Wl& d = dwl[j];
-    const HostWl& w = wls[j];
-    const int layout = d.info & 3;
-    bool ok = d.w_pad >= 0 && d.h_pad >= 1 && d.n_rows >= 1 && d.n_rows <= d.h_pad && d.data_off >= 0 &&
-              d.rowid_off >= 0 && d.data_off + (int64_t)d.w_pad * d.h_pad <= nnz_pad &&
-              d.rowid_off + d.h_pad <= n_rowid && layout <= kChunk && w.tile >= 0 && w.tile < ntiles;
-    if (ok && layout == kChunk) ok = d.n_rows == 1 && d.h_pad == 1 && (d.info >> 2) < n_slots;
-    if (ok) {
-      const int64_t rb = tile_row_off[w.tile], re = tile_row_off[w.tile + 1];
-      ok = (int64_t)w.row_begin >= rb && (int64_t)w.row_begin + (layout == kChunk ? 1 : w.n_rows) <= re;
-    }
-    if (!ok)
-      throw Fail{TC_EINVAL, "internal error: workload " + std::to_string(j) + " (tile " + std::to_string(w.tile) +
-                                ") addresses outside the packed arrays"};
-  }
+inline bool descriptor_ok(const Wl& d, const HostWl& w, int64_t tile, int64_t row_lo, int64_t row_hi,
+                          int64_t n_slots, int64_t nnz_pad, int64_t n_rowid) {
+  const int layout = d.info & 3;
+  bool ok = d.w_pad >= 0 && d.h_pad >= 1 && d.n_rows >= 1 && d.n_rows <= d.h_pad && d.data_off >= 0 &&
+            d.rowid_off >= 0 && d.data_off + (int64_t)d.w_pad * d.h_pad <= nnz_pad &&
+            d.rowid_off + d.h_pad <= n_rowid && layout <= kChunk && w.tile == tile;
+  if (ok && layout == kChunk) ok = d.n_rows == 1 && d.h_pad == 1 && (d.info >> 2) < n_slots;
+  if (ok) ok = (int64_t)w.row_begin >= row_lo && (int64_t)w.row_begin + (layout == kChunk ? 1 : w.n_rows) <= row_hi;
+  return ok;
 }
 
 // Workload size of the automatic row panels (see tc_build_tiled).
@@ -1229,8 +1292,12 @@ class HostPool {
   }
 
  private:
+  // TC_HOST_THREADS=n in the environment: n threads in all (the caller's
+  // included; 1 runs every loop on the calling thread); default up to 16
   HostPool() {
-    const int k = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency())) - 1;
+    int n = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+    if (const char* e = std::getenv("TC_HOST_THREADS")) n = std::max(1, std::min(256, std::atoi(e)));
+    const int k = n - 1;
     for (int i = 0; i < k; ++i) th_.emplace_back([this] { loop(); });
   }
   void work() {
@@ -1625,6 +1692,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     int32_t* icol = tmp.get<int32_t>(nnz);
     int32_t* row_of = nullptr;
     float* pval = nullptr;
+    int32_t* hist0 = nullptr;  // histogram of the first tile pass, when made by the permutation
     if (perm_rows) {
       int32_t* ilen = tmp.get<int32_t>(n_rows);
       int64_t* iptr = tmp.get<int64_t>(n_rows + 1);
@@ -1641,9 +1709,17 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       HIPX(hipGetLastError());
       row_of = tmp.get<int32_t>(nnz);
       pval = tmp.get<float>(nnz);
-      hipLaunchKernelGGL(k_perm_entries, dim3(nblk(nnz, kB)), dim3(kB), 0, st, (const int32_t*)irow,
+      // the first tile pass's histogram comes with the permutation when its
+      // chunks are the permutation's blocks
+      const int tb0 = std::min(8, bits_for((uint64_t)(ntiles - 1)));
+      const CsPlan pl = cs_plan<TileItem>(nnz, tb0);
+      const int64_t pchunk = (int64_t)kB * kPermPer;
+      const int64_t pblocks = (nnz + pchunk - 1) / pchunk;
+      if (pl.chunk == pchunk) hist0 = tmp.get<int32_t>((int64_t)pl.nbuckets * pl.nchunks);
+      hipLaunchKernelGGL((k_perm_entries<TileMap>), dim3((unsigned)pblocks), dim3(kB),
+                         hist0 ? sizeof(int32_t) * (size_t)pl.nbuckets : 0, st, (const int32_t*)irow,
                          (const int64_t*)iptr, (const int64_t*)istart, A->col_idx, cpos, vsrc, nnz, icol, pval,
-                         row_of);
+                         row_of, tmap, pl.nbuckets, pl.nchunks, hist0);
       HIPX(hipGetLastError());
       tmp.release(istart);
       tmp.release(irow);
@@ -1677,7 +1753,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
         const int s = p & 1;
         if (!bv[s]) bv[s] = tmp.get<float>(nnz);
         const int nb = std::min(8, tb - sh);
-        cs_pass(TileOp{ci, cv, cr, bi[s], bv[s], br[s], tmap, sh}, nnz, nb, tmp, st);
+        cs_pass(TileOp{ci, cv, cr, bi[s], bv[s], br[s], tmap, sh}, nnz, nb, tmp, st, sh == 0 ? hist0 : nullptr);
         ci = bi[s];
         cr = br[s];
         cv = bv[s];
@@ -1901,6 +1977,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   if (o->wl_policy == 1 && o->n_wl_per_tile < ntiles)
     throw Fail{TC_EINVAL, "wl_per_tile has fewer entries than tiles built"};
   std::vector<int64_t> tcount(ntiles, 0);  // workloads of each tile
+  std::vector<int64_t> tchunk(ntiles, 0);  // of them, the leading chunk workloads (split rows come first)
+  std::vector<int> tstray(ntiles, 0);
   std::vector<double> tmodel(ntiles, 0.0);
   std::vector<int> tbad(ntiles, 0);
   // per tile: padded elements and stored row ids of its workloads
@@ -1946,15 +2024,20 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     pt.split_len = (int32_t)h->tile_split[t];
     HostWl* out = wls.data() + h->tile_wl_begin[t];
     partition_tile(truns[t], h->tile_wl[t], (int32_t)t, trow[t], pt, out);
-    int64_t a = 0, r = 0;
+    int64_t a = 0, r = 0, c = 0;
+    while (c < tcount[t] && out[c].chunk >= 0) ++c;
+    tchunk[t] = c;
     for (int64_t q = 0; q < tcount[t]; ++q) {
       const int64_t area = (int64_t)out[q].w_pad * out[q].h_pad;
       a += area + ((h->camping_pad && area % 512 == 0) ? 64 : 0);
       r += out[q].h_pad;
+      if (q >= c && out[q].chunk >= 0) tstray[t] = 1;
     }
     tdoff[t + 1] = a;
     troff[t + 1] = r;
   });
+  for (int t = 0; t < ntiles; ++t)
+    if (tstray[t]) throw Fail{TC_EINVAL, "internal error: a chunk workload after a tile's first rows"};
   for (int t = 0; t < ntiles; ++t) {
     tdoff[t + 1] += tdoff[t];
     troff[t + 1] += troff[t];
@@ -1970,11 +2053,7 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
     // workgroup (their sums go to partial slots), listed per column tile
     const int32_t nct = h->n_col_tiles;
     std::vector<int64_t> ncb(ntiles), cbv(nct + 1, 0), chunks;
-    for (int g = 0; g < ntiles; ++g) {
-      int64_t j = h->tile_wl_begin[g];
-      while (j < h->tile_wl_begin[g + 1] && wls[j].chunk >= 0) ++j;
-      ncb[g] = j;
-    }
+    for (int g = 0; g < ntiles; ++g) ncb[g] = h->tile_wl_begin[g] + tchunk[g];
     for (int t = 0; t < nct; ++t) {
       cbv[t] = (int64_t)chunks.size();
       for (int p = 0; p < h->n_panels; ++p)
@@ -1998,8 +2077,8 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   clk.mark("a6 panel lists");
   // split rows: slots grouped by row, in (tile, chunk) order
   std::vector<int64_t> chunk_wl;
-  for (int64_t j = 0; j < nwl; ++j)
-    if (wls[j].chunk >= 0) chunk_wl.push_back(j);
+  for (int t = 0; t < ntiles; ++t)
+    for (int64_t j = h->tile_wl_begin[t]; j < h->tile_wl_begin[t] + tchunk[t]; ++j) chunk_wl.push_back(j);
   std::vector<int32_t> chunk_row(chunk_wl.size()), chunk_first(chunk_wl.size());
   if (!chunk_wl.empty()) {
     // row ids of split rows (they sit at the start of their tile's sorted
@@ -2045,32 +2124,45 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->n_split_rows = (int64_t)srows.size();
 
   clk.mark("a6 split rows");
-  // offsets (per tile in parallel from the tile prefix sums); chunk slots after
+  // descriptors, per tile in parallel from the tile prefix sums, each
+  // checked as it is made (a tile's leading chunk workloads take the partial
+  // slots slot_of[cbase[t] ...])
   const int64_t doff = tdoff[ntiles], roff = troff[ntiles];
+  if (doff >= ((int64_t)1 << 40)) throw Fail{TC_EUNSUPPORTED, "padded format too large"};
+  h->nnz_pad = doff;
+  h->n_rowid = roff;
+  std::vector<int64_t> cbase(ntiles + 1, 0);
+  for (int t = 0; t < ntiles; ++t) cbase[t + 1] = cbase[t] + tchunk[t];
   Staged<Wl> dwl(nwl, st);
-  Staged<PackWl> pwl(nwl, st);
+  Staged<PackX> pxs(nwl, st);
+  std::atomic<int64_t> bad{INT64_MAX};
   parallel_for(ntiles, 64, [&](int64_t t) {
     int64_t d = tdoff[t], r = troff[t];
-    for (int64_t j = h->tile_wl_begin[t]; j < h->tile_wl_begin[t + 1]; ++j) {
+    const int64_t jb = h->tile_wl_begin[t];
+    const int64_t rb = h->tile_row_off[t], re = h->tile_row_off[t + 1];
+    for (int64_t j = jb; j < h->tile_wl_begin[t + 1]; ++j) {
       HostWl& w = wls[j];
       const int64_t area = (int64_t)w.w_pad * w.h_pad;
       const int32_t extra = (h->camping_pad && area % 512 == 0) ? 64 : 0;
       w.data_off = d;
       w.rowid_off = r;
-      dwl[j] = Wl{d, r, w.w_pad, w.h_pad, w.n_rows, w.layout};
-      const int32_t coff = w.chunk >= 0 ? (int32_t)(w.chunk * h->tile_split[w.tile]) : -1;
-      pwl[j] = PackWl{d, r, w.w_pad, w.h_pad, w.n_rows, w.layout, w.row_begin, coff, w.w,
-                      (int32_t)h->tile_col_begin[w.tile], extra, w.tile};
+      const bool chunk = j - jb < tchunk[t];
+      const Wl dd{d, r, w.w_pad, w.h_pad, w.n_rows, chunk ? (int32_t)(kChunk | (slot_of[cbase[t] + (j - jb)] << 2)) : w.layout};
+      dwl[j] = dd;
+      pxs[j] = PackX{w.row_begin, chunk ? (int32_t)(w.chunk * h->tile_split[w.tile]) : -1, w.w, w.tile};
+      if (!descriptor_ok(dd, w, t, rb, re, h->n_slots, doff, roff)) {
+        int64_t cur = bad.load();
+        while (j < cur && !bad.compare_exchange_weak(cur, j)) {
+        }
+      }
       d += area + extra;
       r += w.h_pad;
     }
   });
-  for (size_t q = 0; q < chunk_wl.size(); ++q) dwl[chunk_wl[q]].info = kChunk | (slot_of[q] << 2);
-  h->nnz_pad = doff;
-  h->n_rowid = roff;
-  if (doff >= ((int64_t)1 << 40)) throw Fail{TC_EUNSUPPORTED, "padded format too large"};
+  if (bad.load() != INT64_MAX)
+    throw Fail{TC_EINVAL, "internal error: workload " + std::to_string(bad.load()) + " (tile " +
+                              std::to_string(wls[(size_t)bad.load()].tile) + ") addresses outside the packed arrays"};
   clk.mark("a6 descriptors");
-  check_descriptors(dwl.p, wls, h->tile_row_off, h->n_slots, doff, roff);
 
   clk.mark("a6 partition");
   // ---- a7: pack
@@ -2079,10 +2171,15 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   h->d_rowid = hold<int32_t>(h, roff);
   h->d_wl = hold<Wl>(h, nwl);
   if (nwl > 0) {
-    PackWl* d_pwl = tmp.get<PackWl>(nwl);
-    HIPX(hipMemcpyAsync(d_pwl, pwl.p, sizeof(PackWl) * nwl, hipMemcpyHostToDevice, st));
+    PackX* d_px = tmp.get<PackX>(nwl);
+    Staged<int32_t> tfirst(ntiles, st);
+    for (int t = 0; t < ntiles; ++t) tfirst[t] = (int32_t)h->tile_col_begin[t];
+    int32_t* d_tfirst = tmp.get<int32_t>(ntiles);
     HIPX(hipMemcpyAsync(h->d_wl, dwl.p, sizeof(Wl) * nwl, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_pack, dim3(nblk(nwl * kPackSlices, kB / kWave)), dim3(kB), 0, st, d_pwl, nwl, srt_start, rows_len,
+    HIPX(hipMemcpyAsync(d_px, pxs.p, sizeof(PackX) * nwl, hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(d_tfirst, tfirst.p, sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_pack, dim3(nblk(nwl * kPackSlices, kB / kWave)), dim3(kB), 0, st, (const Wl*)h->d_wl,
+                       (const PackX*)d_px, nwl, (const int32_t*)d_tfirst, h->camping_pad ? 1 : 0, srt_start, rows_len,
                        rows_sorted, b_icol, b_val, (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid,
                        o->value_map ? pad_minus_one() : 0.0f);
     HIPX(hipGetLastError());
