@@ -224,7 +224,10 @@ void tc_build_opts_default(tc_build_opts* opts);
  * Synchronises `stream`.  Errors: TC_EINVAL for a NULL argument, negative
  * sizes, a non-monotone row_ptr, row_ptr[n_rows] != nnz, a column id out of
  * range or an unusable option; TC_EUNSUPPORTED for nnz >= 2^31, n_rows >= 2^30 or
- * n_cols >= 2^31 - 1; TC_ENOMEM; TC_EHIP. */
+ * n_cols >= 2^31 - 1; TC_ENOMEM; TC_EHIP.  The per-tile host work runs on a
+ * pool of up to 16 threads kept for the life of the process; TC_HOST_THREADS=n
+ * in the environment (read when the pool starts) sets its size, 1 keeping all
+ * of it on the calling thread. */
 tc_status tc_build_tiled(const tc_csr* A, const tc_build_opts* opts, tc_stream_t stream,
                          tc_handle** out);
 
