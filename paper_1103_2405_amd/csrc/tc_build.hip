@@ -381,13 +381,13 @@ __global__ void k_irow_len(const int64_t* __restrict__ rp, const int32_t* __rest
   }
 }
 
-// One block per `chunk` positions (kPermPer per thread, all loads of a step
-// issued together).  With hist, the block also counts its chunk's tiles
-// (bucket (tile >> 0) & 255 of TileMap tm, nbuckets buckets) into
-// hist[bucket * nchunks + chunk]: the first tile pass's histogram.
-constexpr int kPermPer = 4;
+// One block of kPermBlock threads per kPermBlock positions.  With hist, the
+// block also counts its positions' tiles (bucket (tile >> 0) & 255 of TileMap
+// tm, nbuckets buckets) into hist[bucket * nchunks + block]: the first tile
+// pass's histogram when that pass's chunks are kPermBlock items.
+constexpr int kPermBlock = 1024;
 template <class TM>
-__global__ void __launch_bounds__(kB) k_perm_entries(const int32_t* __restrict__ irow, const int64_t* __restrict__ iptr,
+__global__ void __launch_bounds__(kPermBlock) k_perm_entries(const int32_t* __restrict__ irow, const int64_t* __restrict__ iptr,
                                                      const int64_t* __restrict__ istart,
                                                      const int32_t* __restrict__ col, const int32_t* __restrict__ cpos,
                                                      const float* __restrict__ val, int64_t nnz,
@@ -396,37 +396,22 @@ __global__ void __launch_bounds__(kB) k_perm_entries(const int32_t* __restrict__
                                                      int64_t nchunks, int32_t* __restrict__ hist) {
   extern __shared__ int32_t pcnt[];
   if (hist) {
-    for (int i = threadIdx.x; i < nbuckets; i += kB) pcnt[i] = 0;
+    for (int i = threadIdx.x; i < nbuckets; i += kPermBlock) pcnt[i] = 0;
     __syncthreads();
   }
-  const int64_t p0 = (int64_t)blockIdx.x * (kB * kPermPer) + threadIdx.x;
-  int32_t r[kPermPer], c[kPermPer];
-  int64_t e[kPermPer];
-  float v[kPermPer];
-#pragma unroll
-  for (int u = 0; u < kPermPer; ++u) r[u] = irow[min(p0 + u * kB, nnz - 1)];
-#pragma unroll
-  for (int u = 0; u < kPermPer; ++u) e[u] = istart[r[u]] + (min(p0 + u * kB, nnz - 1) - iptr[r[u]]);
-#pragma unroll
-  for (int u = 0; u < kPermPer; ++u) {
-    c[u] = col[e[u]];
-    v[u] = val[e[u]];
-  }
-#pragma unroll
-  for (int u = 0; u < kPermPer; ++u) c[u] = cpos[c[u]];
-#pragma unroll
-  for (int u = 0; u < kPermPer; ++u) {
-    const int64_t p = p0 + u * kB;
-    if (p < nnz) {
-      icol[p] = c[u];
-      pval[p] = v[u];
-      prow[p] = r[u];
-      if (hist) atomicAdd(&pcnt[(uint32_t)tm(c[u]) & 255u], 1);
-    }
+  const int64_t p = (int64_t)blockIdx.x * kPermBlock + threadIdx.x;
+  if (p < nnz) {
+    const int32_t r = irow[p];
+    const int64_t e = istart[r] + (p - iptr[r]);
+    const int32_t c = cpos[col[e]];
+    icol[p] = c;
+    pval[p] = val[e];
+    prow[p] = r;
+    if (hist) atomicAdd(&pcnt[(uint32_t)tm(c) & 255u], 1);
   }
   if (hist) {
     __syncthreads();
-    for (int i = threadIdx.x; i < nbuckets; i += kB) hist[(int64_t)i * nchunks + blockIdx.x] = pcnt[i];
+    for (int i = threadIdx.x; i < nbuckets; i += kPermBlock) hist[(int64_t)i * nchunks + blockIdx.x] = pcnt[i];
   }
 }
 
@@ -1713,10 +1698,9 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
       // chunks are the permutation's blocks
       const int tb0 = std::min(8, bits_for((uint64_t)(ntiles - 1)));
       const CsPlan pl = cs_plan<TileItem>(nnz, tb0);
-      const int64_t pchunk = (int64_t)kB * kPermPer;
-      const int64_t pblocks = (nnz + pchunk - 1) / pchunk;
-      if (pl.chunk == pchunk) hist0 = tmp.get<int32_t>((int64_t)pl.nbuckets * pl.nchunks);
-      hipLaunchKernelGGL((k_perm_entries<TileMap>), dim3((unsigned)pblocks), dim3(kB),
+      const int64_t pblocks = (nnz + kPermBlock - 1) / kPermBlock;
+      if (pl.chunk == kPermBlock) hist0 = tmp.get<int32_t>((int64_t)pl.nbuckets * pl.nchunks);
+      hipLaunchKernelGGL((k_perm_entries<TileMap>), dim3((unsigned)pblocks), dim3(kPermBlock),
                          hist0 ? sizeof(int32_t) * (size_t)pl.nbuckets : 0, st, (const int32_t*)irow,
                          (const int64_t*)iptr, (const int64_t*)istart, A->col_idx, cpos, vsrc, nnz, icol, pval,
                          row_of, tmap, pl.nbuckets, pl.nchunks, hist0);
