@@ -392,7 +392,8 @@ tc_status tc_stream_read(const float* d_buf, int64_t n, float* d_sink, tc_stream
  * coalesced; Section 3.1 on the cost of gathering x): for each of the n
  * entries, reads d_idx[e] and d_val[e] (int32 and float, device) in coalesced
  * groups of 64 as a column-major workload does, then gathers d_x[d_idx[e]]
- * (d_x: n_x floats, device); eight entries per lane in flight, 8192
+ * (d_x: n_x floats, device; by buffer loads with 32-bit offsets as the panel
+ * pass does, when n_x <= 2^29); eight entries per lane in flight, 8192
  * workgroups of 256 threads, each thread's sum written to d_sink (8192 * 256
  * floats, device).  An index outside [0, n_x) reads d_x[0].  n must be a
  * multiple of 512 and n_x at least 1 (TC_EINVAL otherwise).  Asynchronous on

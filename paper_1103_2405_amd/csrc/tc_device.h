@@ -69,6 +69,17 @@ __device__ inline float ld_nt(const float* p) { return __builtin_nontemporal_loa
 __device__ inline v4i ld_nt4(const int32_t* p) { return __builtin_nontemporal_load((const v4i*)p); }
 __device__ inline v4f ld_nt4(const float* p) { return __builtin_nontemporal_load((const v4f*)p); }
 
+// x[i] by a raw buffer load: a 32-bit byte offset from one scalar base, so a
+// gather needs no 64-bit address per lane (about 1% faster on the panel
+// pass).  Same value and cache policy as x[i]; x must hold at most
+// kBufMaxFloats floats.  Word 3 of the descriptor is the CDNA raw-dword
+// format.
+constexpr int64_t kBufMaxFloats = (int64_t)1 << 29;
+__device__ inline float ld_buf(const float* x, int32_t i) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, 0x7fffffff, 0x00020000);
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
+}
+
 // Cross-lane moves of a double through DPP (two 32-bit halves).  Lanes whose
 // source is outside the row read 0 (bound_ctrl), rows outside ROWMASK add 0.
 template <int CTRL, int ROWMASK = 0xf>

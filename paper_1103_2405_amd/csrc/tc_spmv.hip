@@ -74,11 +74,17 @@ __global__ void __launch_bounds__(kLdsB) k_tile_lds(const Wl* __restrict__ wl, i
 // is in at most one workload of a tile, and tiles are separated by barriers,
 // so each row's adds happen in tile order, as the first-touch product does
 // them (an add to the zeroed LDS row gives fl32(s), the first tile's store).
+template <bool Buf>
 struct PanelX {
   const float* __restrict__ x;
   float* ys;
   int32_t base;
-  __device__ float operator()(int32_t i) const { return x[i]; }
+  __device__ float operator()(int32_t i) const {
+    if constexpr (Buf)
+      return ld_buf(x, i);
+    else
+      return x[i];
+  }
   __device__ void addy(float*, int32_t rid, double s) const {
     float* q = ys + ((rid & ~kAddFlag) - base);
     *q = (float)((double)*q + s);
@@ -145,7 +151,8 @@ __device__ inline void panel_tile(const G& xg, int64_t g, int32_t t, int32_t p, 
 // w0 > 0 column tile 0 (internal columns [0, w0), the hottest) is first copied
 // into LDS behind y (rows_cap floats in).  At the end the panel's y is stored
 // once, coalesced (PR: as the PageRank update of it).
-template <int NW, bool PR = false>
+// BufX: x gathered by buffer loads (n_cols <= kBufMaxFloats).
+template <int NW, bool PR, bool BufX>
 __global__ void __launch_bounds__(NW * kWave) k_panel_spmv(const Wl* __restrict__ wl,
                                                            const int64_t* __restrict__ wl_begin,
                                                            const int64_t* __restrict__ ncb,
@@ -178,7 +185,7 @@ __global__ void __launch_bounds__(NW * kWave) k_panel_spmv(const Wl* __restrict_
     __syncthreads();
     t = 1;
   }
-  const PanelX xg{x, ys, r0};
+  const PanelX<BufX> xg{x, ys, r0};
   for (; t < nct; ++t) {
     panel_tile<NW>(xg, (int64_t)p * nct + t, t, p, np, wv, lane, wl, wl_begin, ncb, chunks, cb, idx, val, rowid, y,
                    partial);
@@ -276,6 +283,7 @@ constexpr int kStreamBlocks = 8192;
 // lane in flight; the same grid as k_stream_read, each thread's sum to sink.
 // An index outside [0, n_x) reads x[0].
 constexpr int kGatherPer = 8;
+template <bool Buf>
 __global__ void __launch_bounds__(kB) k_gather_read(const float* __restrict__ x, int64_t n_x,
                                                     const int32_t* __restrict__ idx, const float* __restrict__ val,
                                                     int64_t n_chunks, float* __restrict__ sink) {
@@ -293,7 +301,13 @@ __global__ void __launch_bounds__(kB) k_gather_read(const float* __restrict__ x,
       v[u] = __builtin_nontemporal_load(val + base + u * kWave);
     }
 #pragma unroll
-    for (int u = 0; u < kGatherPer; ++u) s += v[u] * x[(uint64_t)(uint32_t)id[u] < (uint64_t)n_x ? id[u] : 0];
+    for (int u = 0; u < kGatherPer; ++u) {
+      const int32_t i = (uint64_t)(uint32_t)id[u] < (uint64_t)n_x ? id[u] : 0;
+      if constexpr (Buf)
+        s += v[u] * ld_buf(x, i);
+      else
+        s += v[u] * x[i];
+    }
   }
   sink[t] = s;
 }
@@ -549,9 +563,19 @@ void panel_pass(tc_handle* h, const float* x, float* y, hipStream_t st, const Pa
   const int64_t rows_cap = (h->panel_rows + 3) & ~3;
   const int64_t w0 = panel_stage_width(h);
   const uint32_t lds = (uint32_t)(4 * (rows_cap + w0));
-  auto kern = pr ? (h->panel_waves == 4 ? k_panel_spmv<4, true>
-                    : h->panel_waves == 8 ? k_panel_spmv<8, true> : k_panel_spmv<16, true>)
-                 : (h->panel_waves == 4 ? k_panel_spmv<4> : h->panel_waves == 8 ? k_panel_spmv<8> : k_panel_spmv<16>);
+  const bool bx = h->n_cols <= kBufMaxFloats;
+  auto kern = pr ? (bx ? (h->panel_waves == 4   ? k_panel_spmv<4, true, true>
+                          : h->panel_waves == 8 ? k_panel_spmv<8, true, true>
+                                                : k_panel_spmv<16, true, true>)
+                       : (h->panel_waves == 4   ? k_panel_spmv<4, true, false>
+                          : h->panel_waves == 8 ? k_panel_spmv<8, true, false>
+                                                : k_panel_spmv<16, true, false>))
+                 : (bx ? (h->panel_waves == 4   ? k_panel_spmv<4, false, true>
+                          : h->panel_waves == 8 ? k_panel_spmv<8, false, true>
+                                                : k_panel_spmv<16, false, true>)
+                       : (h->panel_waves == 4   ? k_panel_spmv<4, false, false>
+                          : h->panel_waves == 8 ? k_panel_spmv<8, false, false>
+                                                : k_panel_spmv<16, false, false>));
   const PanelPr none{0.0, nullptr, 0, nullptr, nullptr, nullptr};
   if (lds > 65536) HIPC(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   launch_tile(h, kern, dim3((unsigned)h->n_panels), dim3((unsigned)(h->panel_waves * kWave)), lds, st,
@@ -726,7 +750,8 @@ extern "C" tc_status tc_gather_read(const float* d_x, int64_t n_x, const int32_t
     if (!d_sink || (n > 0 && (!d_x || !d_idx || !d_val))) throw Err{TC_EINVAL, "NULL argument"};
     if (n < 0 || n % (kGatherPer * kWave) || n_x < 1)
       throw Err{TC_EINVAL, "n must be a multiple of 512 and n_x positive"};
-    hipLaunchKernelGGL(k_gather_read, dim3(kStreamBlocks), dim3(kB), 0, (hipStream_t)stream, d_x, n_x, d_idx, d_val,
+    auto kern = n_x <= kBufMaxFloats ? k_gather_read<true> : k_gather_read<false>;
+    hipLaunchKernelGGL(kern, dim3(kStreamBlocks), dim3(kB), 0, (hipStream_t)stream, d_x, n_x, d_idx, d_val,
                        n / (kGatherPer * kWave), d_sink);
     HIPC(hipGetLastError());
     return TC_OK;
