@@ -2119,55 +2119,62 @@ void build(const tc_csr* A, const tc_build_opts* o, hipStream_t st, tc_handle* h
   for (int t = 0; t < ntiles; ++t) cbase[t + 1] = cbase[t] + tchunk[t];
   Staged<Wl> dwl(nwl, st);
   Staged<PackX> pxs(nwl, st);
-  std::atomic<int64_t> bad{INT64_MAX};
-  parallel_for(ntiles, 64, [&](int64_t t) {
-    int64_t d = tdoff[t], r = troff[t];
-    const int64_t jb = h->tile_wl_begin[t];
-    const int64_t rb = h->tile_row_off[t], re = h->tile_row_off[t + 1];
-    for (int64_t j = jb; j < h->tile_wl_begin[t + 1]; ++j) {
-      HostWl& w = wls[j];
-      const int64_t area = (int64_t)w.w_pad * w.h_pad;
-      const int32_t extra = (h->camping_pad && area % 512 == 0) ? 64 : 0;
-      w.data_off = d;
-      w.rowid_off = r;
-      const bool chunk = j - jb < tchunk[t];
-      const Wl dd{d, r, w.w_pad, w.h_pad, w.n_rows, chunk ? (int32_t)(kChunk | (slot_of[cbase[t] + (j - jb)] << 2)) : w.layout};
-      dwl[j] = dd;
-      pxs[j] = PackX{w.row_begin, chunk ? (int32_t)(w.chunk * h->tile_split[w.tile]) : -1, w.w, w.tile};
-      if (!descriptor_ok(dd, w, t, rb, re, h->n_slots, doff, roff)) {
-        int64_t cur = bad.load();
-        while (j < cur && !bad.compare_exchange_weak(cur, j)) {
-        }
-      }
-      d += area + extra;
-      r += w.h_pad;
-    }
-  });
-  if (bad.load() != INT64_MAX)
-    throw Fail{TC_EINVAL, "internal error: workload " + std::to_string(bad.load()) + " (tile " +
-                              std::to_string(wls[(size_t)bad.load()].tile) + ") addresses outside the packed arrays"};
-  clk.mark("a6 descriptors");
-
-  clk.mark("a6 partition");
-  // ---- a7: pack
+  // ---- a7: pack, pipelined with the descriptors: the tiles go in a few
+  // batches, and each batch's descriptors are copied and packed on the stream
+  // while the host makes the next batch's
   h->d_idx = hold<int32_t>(h, doff);
   h->d_val = hold<float>(h, doff);
   h->d_rowid = hold<int32_t>(h, roff);
   h->d_wl = hold<Wl>(h, nwl);
-  if (nwl > 0) {
-    PackX* d_px = tmp.get<PackX>(nwl);
-    Staged<int32_t> tfirst(ntiles, st);
-    for (int t = 0; t < ntiles; ++t) tfirst[t] = (int32_t)h->tile_col_begin[t];
-    int32_t* d_tfirst = tmp.get<int32_t>(ntiles);
-    HIPX(hipMemcpyAsync(h->d_wl, dwl.p, sizeof(Wl) * nwl, hipMemcpyHostToDevice, st));
-    HIPX(hipMemcpyAsync(d_px, pxs.p, sizeof(PackX) * nwl, hipMemcpyHostToDevice, st));
-    HIPX(hipMemcpyAsync(d_tfirst, tfirst.p, sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_pack, dim3(nblk(nwl * kPackSlices, kB / kWave)), dim3(kB), 0, st, (const Wl*)h->d_wl,
-                       (const PackX*)d_px, nwl, (const int32_t*)d_tfirst, h->camping_pad ? 1 : 0, srt_start, rows_len,
-                       rows_sorted, b_icol, b_val, (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid,
-                       o->value_map ? pad_minus_one() : 0.0f);
-    HIPX(hipGetLastError());
+  PackX* d_px = tmp.get<PackX>(nwl);
+  Staged<int32_t> tfirst(ntiles, st);
+  for (int t = 0; t < ntiles; ++t) tfirst[t] = (int32_t)h->tile_col_begin[t];
+  int32_t* d_tfirst = tmp.get<int32_t>(ntiles);
+  if (ntiles > 0) HIPX(hipMemcpyAsync(d_tfirst, tfirst.p, sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, st));
+  const int nbatch = ntiles >= 1024 ? 4 : 1;
+  for (int bi = 0; bi < nbatch; ++bi) {
+    const int64_t t0 = (int64_t)ntiles * bi / nbatch, t1 = (int64_t)ntiles * (bi + 1) / nbatch;
+    std::atomic<int64_t> bad{INT64_MAX};
+    parallel_for(t1 - t0, 16, [&](int64_t q) {
+      const int64_t t = t0 + q;
+      int64_t d = tdoff[t], r = troff[t];
+      const int64_t jb = h->tile_wl_begin[t];
+      const int64_t rb = h->tile_row_off[t], re = h->tile_row_off[t + 1];
+      for (int64_t j = jb; j < h->tile_wl_begin[t + 1]; ++j) {
+        HostWl& w = wls[j];
+        const int64_t area = (int64_t)w.w_pad * w.h_pad;
+        const int32_t extra = (h->camping_pad && area % 512 == 0) ? 64 : 0;
+        w.data_off = d;
+        w.rowid_off = r;
+        const bool chunk = j - jb < tchunk[t];
+        const Wl dd{d, r, w.w_pad, w.h_pad, w.n_rows,
+                    chunk ? (int32_t)(kChunk | (slot_of[cbase[t] + (j - jb)] << 2)) : w.layout};
+        dwl[j] = dd;
+        pxs[j] = PackX{w.row_begin, chunk ? (int32_t)(w.chunk * h->tile_split[w.tile]) : -1, w.w, w.tile};
+        if (!descriptor_ok(dd, w, t, rb, re, h->n_slots, doff, roff)) {
+          int64_t cur = bad.load();
+          while (j < cur && !bad.compare_exchange_weak(cur, j)) {
+          }
+        }
+        d += area + extra;
+        r += w.h_pad;
+      }
+    });
+    if (bad.load() != INT64_MAX)
+      throw Fail{TC_EINVAL, "internal error: workload " + std::to_string(bad.load()) + " (tile " +
+                                std::to_string(wls[(size_t)bad.load()].tile) + ") addresses outside the packed arrays"};
+    const int64_t j0 = h->tile_wl_begin[t0], nb = h->tile_wl_begin[t1] - j0;
+    if (nb > 0) {
+      HIPX(hipMemcpyAsync(h->d_wl + j0, dwl.p + j0, sizeof(Wl) * nb, hipMemcpyHostToDevice, st));
+      HIPX(hipMemcpyAsync(d_px + j0, pxs.p + j0, sizeof(PackX) * nb, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_pack, dim3(nblk(nb * kPackSlices, kB / kWave)), dim3(kB), 0, st,
+                         (const Wl*)(h->d_wl + j0), (const PackX*)(d_px + j0), nb, (const int32_t*)d_tfirst,
+                         h->camping_pad ? 1 : 0, srt_start, rows_len, rows_sorted, b_icol, b_val,
+                         (const int32_t*)first, h->d_idx, h->d_val, h->d_rowid, o->value_map ? pad_minus_one() : 0.0f);
+      HIPX(hipGetLastError());
+    }
   }
+  clk.mark("a6 descriptors + a7 pack");
   if (o->value_map) {
     h->d_vmap = hold<int32_t>(h, doff);
     if (doff > 0) {

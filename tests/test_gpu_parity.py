@@ -107,6 +107,19 @@ def test_format_rectangular_and_camping_pad():
     check_spmv(gm, csr, gg.uniform_f32(900, 1))
 
 
+def test_format_square_without_relabel_several_tiles():
+    # rows keep their ids: the entries stay in CSR order through the tile
+    # passes and the segment sort skips the row bits, as with relabelled rows
+    csr = gg.random_csr(1500, 1500, 0.01, 21, power=1.1)
+    ref = rf.build(csr, W=128, wl=[300] * 4096, S=64, split_len=64, relabel=False)
+    gm = TiledMatrix(csr, tile_width=128, wl=300, wave=64, split_len=64, relabel=0)
+    g = gm.export_format()
+    assert not g["relabel"] and ref["n_tiles_total"] > 1
+    assert_same_format(g, ref)
+    check_spmv(gm, csr, gg.uniform_f32(1500, 22))
+    gm.close()
+
+
 def test_format_rmat14_several_tiles():
     g = gg.rmat(14, 16, seed=14)
     csr = gg.pagerank_matrix(g)
@@ -483,16 +496,17 @@ def test_rwr_multi_with_a_graph_larger_than_lds():
         m.close()
 
 
-@pytest.mark.parametrize("W,split", [(0, -1), (0, 64), (1024, 64)])
-def test_refresh_values_equals_fresh_build(W, split):
+@pytest.mark.parametrize("W,split,panels", [(0, -1, 0), (0, 64, 0), (1024, 64, 0), (1024, 64, -1)])
+def test_refresh_values_equals_fresh_build(W, split, panels):
     # a handle built with the value map and then given new values holds
     # exactly what a build from the new values holds
     g = gg.rmat(12, 8, seed=31)
     n, _, rp, col, val = gg.pagerank_matrix(g)
     val2 = gg.uniform_f32(len(col), 32)
-    tm = TiledMatrix((n, n, rp, col, val), tile_width=W, split_len=split, value_map=True)
-    same = TiledMatrix((n, n, rp, col, val), tile_width=W, split_len=split)
-    fresh = TiledMatrix((n, n, rp, col, val2), tile_width=W, split_len=split)
+    kw = dict(tile_width=W, split_len=split, panels=panels)
+    tm = TiledMatrix((n, n, rp, col, val), value_map=True, **kw)
+    same = TiledMatrix((n, n, rp, col, val), **kw)
+    fresh = TiledMatrix((n, n, rp, col, val2), **kw)
     a0, s0 = tm.export_format(), same.export_format()
     for key in ("idx", "val", "rowid"):
         assert np.array_equal(a0[key].view(np.uint32), s0[key].view(np.uint32)), key
