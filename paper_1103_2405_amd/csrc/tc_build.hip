@@ -469,13 +469,15 @@ __device__ inline uint32_t seg_head_bits(const int32_t* __restrict__ b_row, int6
     const int32_t mid = (lo + hi) >> 1;
     if (tstart[mid] < base) lo = mid + 1; else hi = mid;
   }
+  // that tile's start, read again only when the run passes it
+  int64_t nxt = lo < ntiles ? tstart[lo] : INT64_MAX;
   uint32_t m = 0;
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
     const int64_t k = base + i;
     bool h = k == 0 || rows[i] != prev;
-    while (lo < ntiles && tstart[lo] < k) ++lo;
-    if (lo < ntiles && tstart[lo] == k) h = true;
+    while (nxt < k) nxt = ++lo < ntiles ? tstart[lo] : INT64_MAX;
+    if (nxt == k) h = true;
     if (k < nnz && h) m |= 1u << i;
     prev = rows[i];
   }
