@@ -365,11 +365,12 @@ __global__ void k_icol(const int32_t* __restrict__ col, const int32_t* __restric
   if (k < nnz) icol[k] = cpos[col[k]];
 }
 
-// Entries in internal-row order: output position p lies in internal row
-// irow[p] (expanded from iptr, the scan of the internal rows' lengths); it
-// takes the entry of the same rank in the row's CSR range.  The row keeps
-// its entries in CSR order.  Written: the internal column, the value and
-// the internal row.
+// Entries in internal-row order.  k_irow_len: each internal row's length and
+// the start of its CSR range; iptr is their scan.  k_perm_entries: output
+// position p lies in internal row irow[p] (expanded from iptr) and takes the
+// entry of the same rank in that row's CSR range, so a row keeps its entries
+// in CSR order.  Written: the internal column, the value and the internal
+// row.
 __global__ void k_irow_len(const int64_t* __restrict__ rp, const int32_t* __restrict__ rowinv, int64_t n_rows,
                            int32_t* __restrict__ ilen, int64_t* __restrict__ istart) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -387,13 +388,12 @@ __global__ void k_irow_len(const int64_t* __restrict__ rp, const int32_t* __rest
 // pass's histogram when that pass's chunks are kPermBlock items.
 constexpr int kPermBlock = 1024;
 template <class TM>
-__global__ void __launch_bounds__(kPermBlock) k_perm_entries(const int32_t* __restrict__ irow, const int64_t* __restrict__ iptr,
-                                                     const int64_t* __restrict__ istart,
-                                                     const int32_t* __restrict__ col, const int32_t* __restrict__ cpos,
-                                                     const float* __restrict__ val, int64_t nnz,
-                                                     int32_t* __restrict__ icol, float* __restrict__ pval,
-                                                     int32_t* __restrict__ prow, TM tm, int32_t nbuckets,
-                                                     int64_t nchunks, int32_t* __restrict__ hist) {
+__global__ void __launch_bounds__(kPermBlock)
+    k_perm_entries(const int32_t* __restrict__ irow, const int64_t* __restrict__ iptr,
+                   const int64_t* __restrict__ istart, const int32_t* __restrict__ col,
+                   const int32_t* __restrict__ cpos, const float* __restrict__ val, int64_t nnz,
+                   int32_t* __restrict__ icol, float* __restrict__ pval, int32_t* __restrict__ prow, TM tm,
+                   int32_t nbuckets, int64_t nchunks, int32_t* __restrict__ hist) {
   extern __shared__ int32_t pcnt[];
   if (hist) {
     for (int i = threadIdx.x; i < nbuckets; i += kPermBlock) pcnt[i] = 0;
@@ -654,7 +654,6 @@ __global__ void k_lower_bound_pre(const int64_t* __restrict__ pre, int64_t n, co
   }
   out[p] = lo;
 }
-
 
 // Row panels: the segment's tile becomes panel * nct + column tile (the
 // panel bounds pb staged in LDS when lds_pb), then the row's first-touch
