@@ -72,11 +72,12 @@ __device__ inline v4f ld_nt4(const float* p) { return __builtin_nontemporal_load
 // x[i] by a raw buffer load: a 32-bit byte offset from one scalar base, so a
 // gather needs no 64-bit address per lane (about 1% faster on the panel
 // pass).  Same value and cache policy as x[i]; x must hold at most
-// kBufMaxFloats floats.  Word 3 of the descriptor is the CDNA raw-dword
-// format.
+// kBufMaxFloats floats, so that 4 i fits the signed offset.  The descriptor
+// covers the whole 32-bit range (no record limit); its word 3 is the CDNA
+// raw-dword format.
 constexpr int64_t kBufMaxFloats = (int64_t)1 << 29;
 __device__ inline float ld_buf(const float* x, int32_t i) {
-  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, -1, 0x00020000);
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
 }
 
